@@ -1,0 +1,334 @@
+"""GCRO-DR along a sequence of systems, plain FP64 NumPy/SciPy (oracle, test infrastructure only).
+
+Follows Alg. 2 ("GCRO-DR", App. B.2) with the recycle-space adaptation of App. B.1, the
+Arnoldi relation Eq. 3 and the projected Arnoldi relation Eq. 6 (Sec. 4.2). GMRES(m) is this
+routine with k = 0 (Sec. 4.2: GMRES is the special case of GCRO-DR with k set to zero).
+
+Readings adopted where the paper is silent or loose (each is mirrored by the GPU library):
+* Real arithmetic: the conjugate transposes of the paper become transposes.
+* x0 = 0 for every system; the stopping test is relative, ||r|| <= rtol * ||b||.
+* Orthogonalisation: classical Gram-Schmidt with one full re-orthogonalisation (CGS2) against
+  [C_k, V_j]; B and H accumulate the coefficients of both passes.
+* Convergence is tested after every Arnoldi step on the least-squares residual of the
+  Hessenberg block (the rows belonging to C_k can always be satisfied exactly, so this is the
+  residual of the whole projected problem). ``full_cycles=True`` instead tests only between
+  cycles, as printed in Alg. 2.
+* The cycle that stops early still updates x, r and the recycle space (when it ran >= 1 step).
+* Happy breakdown: h_{j+1,j} <= 1e-14 * ||A v_j|| ends the cycle with an exact projected solve.
+* On exit the true residual b - A x is computed; if it is above the tolerance the solve goes on
+  from that residual.
+* ``maxit`` bounds the Arnoldi steps of one system.
+* Start-up QR of A*Y (App. B.1): R has a positive diagonal. A column j with
+  R_jj <= 1e-7 * ||(A Y)_j|| is treated as dependent and dropped (fewer recycled vectors).
+* Harmonic Ritz selection: the k eigenvalues of smallest modulus (ties by index, infinite
+  values never chosen). A complex pair is represented by the real and imaginary parts of one
+  eigenvector; when the k-th chosen value is one half of a conjugate pair, that half is dropped.
+* A first system (or any system without a recycle space) starts with a GMRES(m) cycle and takes
+  the k harmonic Ritz vectors of the standard form (Alg. 2, else branch) when that cycle ran more
+  than k steps; otherwise no recycle space is formed.
+* A system whose right-hand side is zero returns x = 0 and passes the incoming recycle space on.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+CONVERGED = 0
+MAXIT = 1
+BREAKDOWN = 2      # happy breakdown: converged through an exact projected solve
+NONFINITE = 3
+
+RANK_DROP_TOL = 1e-7
+BREAKDOWN_TOL = 1e-14
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    status: int
+    iters: int                 # Arnoldi steps
+    cycles: int
+    spmv: int                  # all products with A (Arnoldi, start-up A*Y, true residuals)
+    relres_true: float
+    relres_est: float
+    k_start: int = 0           # recycled vectors kept by the start-up QR
+    rank_dropped: int = 0      # recycled vectors dropped by the start-up QR
+    Y_next: np.ndarray | None = None
+    C_last: np.ndarray | None = None                   # C_k matching Y_next (A Y_next = C_last)
+    res_history: list = field(default_factory=list)   # ||r|| after the start and after each cycle
+
+
+def qr_pos(M: np.ndarray):
+    """Reduced QR with a non-negative diagonal of R (the unique factorisation when M has full rank)."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :], R * s[:, None]
+
+
+def ls_residual(Hbar: np.ndarray, beta: float) -> float:
+    """min_y ||beta e1 - Hbar y||: beta times the first entry of the unit vector orthogonal to range(Hbar)."""
+    Qf = np.linalg.qr(Hbar, mode="complete")[0]
+    return float(beta * abs(Qf[0, -1]))
+
+
+# ----------------------------------------------------------------------------------------------
+# Harmonic Ritz vectors
+# ----------------------------------------------------------------------------------------------
+def select_smallest(theta: np.ndarray, Z: np.ndarray, k: int):
+    """Real basis P of the eigenvectors of the k smallest-modulus eigenvalues (see module readings).
+
+    Eigenvalues are visited by increasing modulus (ties by index). A complex eigenvalue is taken
+    together with its conjugate partner (the remaining eigenvalue closest to its conjugate) as the
+    two columns Re z, Im z; when only one slot is left for a pair, the selection stops there.
+    """
+    theta = np.asarray(theta)
+    cand = [i for i in range(theta.size) if np.isfinite(theta[i])]
+    cand.sort(key=lambda i: (abs(theta[i]), i))
+    cols, vals, used = [], [], set()
+    for i in cand:
+        if len(cols) >= k:
+            break
+        if i in used:
+            continue
+        if np.imag(theta[i]) == 0.0:
+            cols.append(np.real(Z[:, i]))
+            vals.append(theta[i])
+            used.add(i)
+            continue
+        others = [p for p in cand if p not in used and p != i
+                  and np.sign(np.imag(theta[p])) == -np.sign(np.imag(theta[i]))]
+        if not others:
+            continue
+        p = min(others, key=lambda q: (abs(theta[q] - np.conj(theta[i])), q))
+        if len(cols) + 2 > k:
+            break
+        cols.append(np.real(Z[:, i]))
+        cols.append(np.imag(Z[:, i]))
+        vals.extend([theta[i], theta[p]])
+        used.update([i, p])
+    P = np.column_stack(cols) if cols else np.zeros((Z.shape[0], 0))
+    return P, np.asarray(vals)
+
+
+def harmonic_ritz_standard(Hbar: np.ndarray, k: int):
+    """k harmonic Ritz vectors of H_m + h_{m+1,m}^2 H_m^{-T} e_m e_m^T (Alg. 2, else branch)."""
+    j = Hbar.shape[1]
+    H = Hbar[:j, :]
+    h = Hbar[j, j - 1]
+    e = np.zeros(j)
+    e[-1] = 1.0
+    f = np.linalg.solve(H.T, e)
+    M = H.copy()
+    M[:, -1] += h * h * f
+    theta, Z = np.linalg.eig(M)
+    return select_smallest(theta, Z, k)
+
+
+def harmonic_ritz_generalized(G: np.ndarray, WtV: np.ndarray, k: int):
+    """k vectors of G^T G z = theta G^T (W^T V) z with smallest |theta| (Alg. 2, cycle body)."""
+    theta, Z = sla.eig(G.T @ G, G.T @ WtV)
+    return select_smallest(theta, Z, k)
+
+
+# ----------------------------------------------------------------------------------------------
+# Arnoldi with (I - C C^T) A and CGS2 (Eq. 3 when C is empty, Eq. 6 otherwise)
+# ----------------------------------------------------------------------------------------------
+def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool = False):
+    """Up to s Arnoldi steps from v1 = r/||r||.
+
+    Returns (V, Hbar, B, est, breakdown): V is n x (j+1), Hbar (j+1) x j, B kc x j for the j steps
+    taken, est the least-squares residual of Hbar against ||r|| e1.
+    """
+    n = r.size
+    kc = 0 if C is None else C.shape[1]
+    beta = float(np.linalg.norm(r))
+    basis = np.zeros((n, kc + s + 1), order="F")       # [C, v1, v2, ...]
+    if kc:
+        basis[:, :kc] = C
+    basis[:, kc] = r / beta
+    Hbar = np.zeros((s + 1, s))
+    B = np.zeros((kc, s))
+    est = beta
+    breakdown = False
+    j_done = 0
+    for j in range(s):
+        w = A @ basis[:, kc + j]
+        wn0 = float(np.linalg.norm(w))
+        Qb = basis[:, :kc + j + 1]
+        c1 = Qb.T @ w
+        w = w - Qb @ c1
+        c2 = Qb.T @ w
+        w = w - Qb @ c2
+        c = c1 + c2
+        B[:, j] = c[:kc]
+        Hbar[:j + 1, j] = c[kc:]
+        hn = float(np.linalg.norm(w))
+        j_done = j + 1
+        if hn <= BREAKDOWN_TOL * wn0:
+            breakdown = True
+            Hbar[j + 1, j] = 0.0
+        else:
+            Hbar[j + 1, j] = hn
+            basis[:, kc + j + 1] = w / hn
+        est = ls_residual(Hbar[:j + 2, :j + 1], beta)
+        if breakdown:
+            break
+        if not full_cycles and est <= tol_abs:
+            break
+    j = j_done
+    return basis[:, kc:kc + j + 1], Hbar[:j + 1, :j], B[:, :j], est, breakdown
+
+
+# ----------------------------------------------------------------------------------------------
+# Start-up with a recycled space (App. B.1; Alg. 2, if branch)
+# ----------------------------------------------------------------------------------------------
+def startup(A, Y: np.ndarray, r0: np.ndarray):
+    """[Q,R] = qr(A Y); C = Q; U = Y R^-1; x1 = U C^T r0; r1 = r0 - C C^T r0 (with column drops)."""
+    Z = A @ Y
+    keep = list(range(Y.shape[1]))
+    while keep:
+        Q, R = qr_pos(Z[:, keep])
+        bad = [t for t in range(len(keep))
+               if not R[t, t] > RANK_DROP_TOL * np.linalg.norm(Z[:, keep[t]])]
+        if not bad:
+            break
+        del keep[bad[0]]
+    dropped = Y.shape[1] - len(keep)
+    if not keep:
+        return np.zeros_like(r0), r0.copy(), None, None, dropped
+    C = Q
+    U = sla.solve_triangular(R, Y[:, keep].T, trans="T", lower=False).T    # Y R^{-1}
+    c = C.T @ r0
+    x1 = U @ c
+    r1 = r0 - C @ c
+    return x1, r1, C, U, dropped
+
+
+# ----------------------------------------------------------------------------------------------
+# One system
+# ----------------------------------------------------------------------------------------------
+def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 10,
+           rtol: float = 1e-8, maxit: int = 10000, full_cycles: bool = False) -> SolveResult:
+    """Solve A x = b from x0 = 0, recycling span(Y) (App. B.2, Alg. 2). Returns the next Y in Y_next."""
+    if k < 0 or m <= k or rtol <= 0:
+        raise ValueError("need 0 <= k < m and rtol > 0")
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    x = np.zeros(n)
+    if not (np.all(np.isfinite(b)) and np.all(np.isfinite(A.data))):
+        return SolveResult(x, NONFINITE, 0, 0, 0, np.nan, np.nan, Y_next=Y)
+    bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:
+        return SolveResult(x, CONVERGED, 0, 0, 0, 0.0, 0.0, Y_next=Y)
+    tol_abs = rtol * bnorm
+    r = b.copy()
+    C = U = None
+    spmv = iters = cycles = 0
+    k_start = dropped = 0
+    if k > 0 and Y is not None and Y.shape[1] > 0:
+        x, r, C, U, dropped = startup(A, Y, r)
+        spmv += Y.shape[1]
+        k_start = 0 if C is None else C.shape[1]
+    hist = [float(np.linalg.norm(r))]
+    est = hist[0]
+    status = None
+    breakdown = False
+    rt_norm = None
+    if hist[0] <= tol_abs:           # the projection onto C already solved the system
+        rt = b - A @ x
+        spmv += 1
+        rt_norm = float(np.linalg.norm(rt))
+        if rt_norm <= tol_abs:
+            status = CONVERGED
+        else:
+            r = rt
+    while status is None:
+        if iters >= maxit:
+            status = MAXIT
+            break
+        s = m if C is None else m - C.shape[1]
+        s = min(s, maxit - iters)
+        V, Hbar, B, est, breakdown = arnoldi_cycle(A, r, C, s, tol_abs, full_cycles)
+        j = Hbar.shape[1]
+        iters += j
+        spmv += j
+        cycles += 1
+        beta = float(np.linalg.norm(r))
+        if C is None:
+            # GMRES(m) cycle (Alg. 2, else branch): min ||c - Hbar y||, x += V_j y, r = V_{j+1}(c - Hbar y)
+            cvec = np.zeros(j + 1)
+            cvec[0] = beta
+            y = np.linalg.lstsq(Hbar, cvec, rcond=None)[0]
+            x = x + V[:, :j] @ y
+            r = V @ (cvec - Hbar @ y)
+            if k > 0 and j > k:
+                P, _ = harmonic_ritz_standard(Hbar, k)
+                if P.shape[1] > 0:
+                    Yt = V[:, :j] @ P
+                    Q, R = qr_pos(Hbar @ P)
+                    C = V @ Q
+                    U = sla.solve_triangular(R, Yt.T, trans="T", lower=False).T
+        else:
+            # GCRO-DR cycle (Alg. 2, while body)
+            kc = C.shape[1]
+            d = 1.0 / np.linalg.norm(U, axis=0)               # D_k: U D_k has unit columns
+            Ut = U * d[None, :]
+            Vhat = np.hstack([Ut, V[:, :j]])
+            What = np.hstack([C, V])
+            G = np.zeros((kc + j + 1, kc + j))
+            G[:kc, :kc] = np.diag(d)
+            G[:kc, kc:] = B
+            G[kc:, kc:] = Hbar
+            rhs = What.T @ r
+            y = np.linalg.lstsq(G, rhs, rcond=None)[0]
+            x = x + Vhat @ y
+            r = r - What @ (G @ y)
+            P, _ = harmonic_ritz_generalized(G, What.T @ Vhat, k)
+            if P.shape[1] > 0:
+                Yt = Vhat @ P
+                Q, R = qr_pos(G @ P)
+                C = What @ Q
+                U = sla.solve_triangular(R, Yt.T, trans="T", lower=False).T
+        hist.append(float(np.linalg.norm(r)))
+        if est <= tol_abs or breakdown:
+            rt = b - A @ x
+            spmv += 1
+            rt_norm = float(np.linalg.norm(rt))
+            if rt_norm <= tol_abs:
+                status = BREAKDOWN if breakdown else CONVERGED
+                break
+            r = rt
+    if status == MAXIT:
+        rt_norm = float(np.linalg.norm(b - A @ x))
+        spmv += 1
+    Y_next = U if (k > 0 and U is not None) else None
+    return SolveResult(x, status, iters, cycles, spmv, rt_norm / bnorm, float(est / bnorm),
+                       k_start, dropped, Y_next, C if Y_next is not None else None, hist)
+
+
+def gmres(A, b, m: int = 30, rtol: float = 1e-8, maxit: int = 10000) -> SolveResult:
+    """Restarted GMRES(m): GCRO-DR with k = 0 (Sec. 4.2)."""
+    return gcrodr(A, b, None, m, 0, rtol, maxit)
+
+
+def solve_sequence(As, bs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
+                   maxit: int = 10000, full_cycles: bool = False, limit: int | None = None):
+    """Solve the systems in ``order`` (identity when None), carrying Y = U_k from each to the next.
+
+    Returns a list of SolveResult indexed by original system index (None for systems not solved
+    when ``limit`` stops the sequence early).
+    """
+    N = len(As)
+    order = list(range(N)) if order is None else [int(i) for i in order]
+    if limit is not None:
+        order = order[:limit]
+    results = [None] * N
+    Y = None
+    for idx in order:
+        res = gcrodr(As[idx], bs[idx], Y, m, k, rtol, maxit, full_cycles)
+        results[idx] = res
+        Y = res.Y_next
+    return results

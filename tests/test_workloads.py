@@ -1,0 +1,62 @@
+"""Input generators: the FDM assembly pinned to the paper's worked example, and structural checks."""
+import os
+
+import numpy as np
+
+from workloads import darcy_from_nodes, darcy_sequence, grf_field, param_matrix
+
+
+def _load_golden(path):
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array(rows, dtype=np.float64)
+
+
+def test_fdm_matches_paper_2x2_example(golden_dir):
+    # a == 1, N_g = 2: -div(grad u) discretised; the paper prints Delta x^2 * (nabla^2 operator).
+    M_paper = _load_golden(os.path.join(golden_dir, "fdm_poisson_2x2.txt"))
+    sysm = darcy_from_nodes(np.ones((4, 4)))
+    h = 1.0 / 3.0
+    A = sysm.A.toarray()
+    np.testing.assert_allclose(A, -(1.0 / h ** 2) * M_paper, rtol=1e-14, atol=0)
+
+
+def test_structure_and_symmetry():
+    for N_g in (1, 2, 7, 32):
+        s = darcy_sequence(N_g, 1, first_seed=3)[0]
+        A = s.A
+        assert A.shape == (N_g * N_g, N_g * N_g)
+        assert A.nnz == 5 * N_g * N_g - 4 * N_g
+        assert A.indptr.dtype == np.int32 and A.indices.dtype == np.int32
+        assert abs(A - A.T).max() == 0.0
+        d = A.diagonal()
+        off = np.asarray(abs(A).sum(axis=1)).ravel() - d
+        assert np.all(d >= off * (1 - 1e-15))           # weak diagonal dominance
+        assert np.all(d > 0)
+
+
+def test_faces_reproduce_csr():
+    s = darcy_sequence(9, 1, first_seed=5)[0]
+    N_g = s.N_g
+    x = np.random.default_rng(0).standard_normal((N_g, N_g))
+    xp = np.zeros((N_g + 2, N_g + 2))
+    xp[1:-1, 1:-1] = x
+    ax, ay = s.ax, s.ay
+    y = (ax[:, :-1] * (x - xp[1:-1, :-2]) + ax[:, 1:] * (x - xp[1:-1, 2:])
+         + ay[:-1, :] * (x - xp[:-2, 1:-1]) + ay[1:, :] * (x - xp[2:, 1:-1])) * s.inv_h2
+    np.testing.assert_allclose(y.ravel(), s.A @ x.ravel(), rtol=1e-12, atol=1e-9 * s.inv_h2)
+
+
+def test_grf_is_seeded_and_unit_variance():
+    f1 = grf_field(66, 7)
+    f2 = grf_field(66, 7)
+    assert np.array_equal(f1, f2)
+    assert not np.array_equal(f1, grf_field(66, 8))
+    v = np.mean([grf_field(34, s).var() + grf_field(34, s).mean() ** 2 for s in range(200)])
+    assert 0.8 < v < 1.2
+
+
+def test_param_matrix_layout():
+    seq = darcy_sequence(4, 3)
+    P = param_matrix(seq)
+    assert P.shape == (3, 36) and P.flags.c_contiguous
+    assert np.array_equal(P[1], seq[1].a.ravel())
