@@ -1,0 +1,149 @@
+/*
+ * skr.h -- C ABI of the MI355X (gfx950) Sorting Krylov Recycling library (libskr.so).
+ *
+ * The library orders a batch of related sparse linear systems A_i x_i = b_i (Eq. 1) by the
+ * greedy nearest-neighbour sort of Alg. 1 (Sec. 4.1), and solves them in that order with
+ * GCRO-DR (Alg. 2, App. B.2), carrying the recycled subspace U_k from each system to the next
+ * (App. B.1). Plain restarted GMRES(m) is the same call with k = 0 (Sec. 4.2).
+ *
+ * Conventions for every entry point
+ *  - Pointers named *_dev are device pointers on the context's device; pointers named *_host are
+ *    host pointers. The caller owns all of them: the library never frees caller memory and reads
+ *    or writes it only during the call.
+ *  - All work is enqueued on the stream given to skr_ctx_create. Calls return after their
+ *    results are final (they synchronise that stream), so inputs may be reused at once.
+ *  - Floating point is IEEE FP64; indices are int32, orderings int64.
+ *  - Return value: 0 = success, < 0 = error (nothing further promised, skr_last_error() gives a
+ *    message), > 0 = completed with a warning.
+ *  - A context is not thread-safe: one host thread at a time per context.
+ */
+#ifndef SKR_H
+#define SKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SKR_OK                 0
+#define SKR_EINVAL            (-1)   /* bad sizes or options (e.g. k < 0, m <= k, rtol <= 0)   */
+#define SKR_ENOMEM            (-2)   /* device workspace could not be allocated                */
+#define SKR_EHIP              (-3)   /* HIP runtime failure                                    */
+#define SKR_ENONFINITE        (-4)   /* NaN or Inf in an input where none is allowed           */
+#define SKR_WARN_NOTCONVERGED   1    /* at least one system stopped at maxit                   */
+
+/* per-system status (skr_result.status) */
+#define SKR_CONVERGED   0   /* ||b - A x|| <= rtol ||b||                                        */
+#define SKR_MAXIT       1   /* stopped after maxit Arnoldi steps without meeting the tolerance  */
+#define SKR_BREAKDOWN   2   /* converged through a happy breakdown (invariant Krylov subspace)  */
+#define SKR_NONFINITE   3   /* b or A holds NaN/Inf; x is set to zero, nothing is recycled      */
+
+/* operator kinds (skr_op.kind) */
+#define SKR_OP_CSR      0   /* general sparse matrix, CSR                                        */
+#define SKR_OP_STENCIL5 1   /* matrix-free 2-D 5-point operator built from face coefficients   */
+
+typedef struct skr_ctx skr_ctx;
+
+/*
+ * One system matrix A (n x n). Device pointers, caller-owned.
+ *  CSR:      rowptr[n+1], colind[nnz] (0-based), values[nnz]; rows need not be sorted.
+ *  STENCIL5: unknowns on an nx-by-ny grid, unknown (i, j) (row i < ny, column j < nx) at index
+ *            i*nx + j (row-major as in the worked example of Sec. 3.1 / App. A);
+ *            ax[ny*(nx+1)]: ax[i*(nx+1) + j] is the coefficient on the face between columns
+ *            j-1 and j of row i (j = 0 and j = nx are the Dirichlet boundary faces);
+ *            ay[(ny+1)*nx]: ay[i*nx + j] is the face between rows i-1 and i of column j.
+ *            (A x)_ij = inv_h2 * ( sum of the 4 faces * x_ij - sum over interior neighbours of
+ *            face * x_neighbour ), i.e. -div(a grad u) with zero Dirichlet data.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t n;
+    int32_t nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double* values;
+    int32_t nx, ny;
+    double inv_h2;
+    const double* ax;
+    const double* ay;
+} skr_op;
+
+/* Solver options. m: maximum subspace size per cycle; k: recycled vectors (0 = GMRES(m));
+ * rtol: relative residual target; maxit: maximum Arnoldi steps per system; flags: reserved, 0. */
+typedef struct {
+    int32_t m;
+    int32_t k;
+    double rtol;
+    int64_t maxit;
+    uint32_t flags;
+} skr_opts;
+
+/* Per-system result, written at the system's original index. */
+typedef struct {
+    int32_t status;        /* SKR_CONVERGED, SKR_MAXIT, SKR_BREAKDOWN or SKR_NONFINITE            */
+    int32_t cycles;        /* Arnoldi cycles run                                                  */
+    int32_t k_start;       /* recycled vectors kept by the start-up QR of A*Y (0 without recycling)*/
+    int32_t rank_dropped;  /* recycled vectors dropped as numerically dependent at start-up       */
+    int64_t iters;         /* Arnoldi steps                                                       */
+    int64_t spmv;          /* products with A: Arnoldi, start-up A*Y columns, true residuals      */
+    double relres_true;    /* ||b - A x|| / ||b||, computed on the device at exit                 */
+    double relres_est;     /* least-squares residual estimate / ||b|| at exit                     */
+} skr_result;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t, NULL for
+ * the default stream). Device workspace is allocated by the library on first use and owned by the
+ * context. Returns SKR_EINVAL for a bad device, SKR_EHIP on runtime failure. */
+int skr_ctx_create(int device, void* hip_stream, skr_ctx** out);
+
+/* Free the context and its workspace (waits for its stream). NULL is accepted. */
+int skr_ctx_destroy(skr_ctx* ctx);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* skr_last_error(void);
+
+/* Library version string. */
+const char* skr_version(void);
+
+/*
+ * Greedy nearest-neighbour order of N systems (Alg. 1, Sec. 4.1).
+ *  params_dev: N x p row-major FP64 parameter matrices (row i = vec(P^(i))).
+ *  start: index of the first system (Alg. 1 starts at the first system: pass 0).
+ *  order_host: out, N int64, a permutation of 0..N-1 with order_host[0] = start.
+ *  step_d2_host: optional out (NULL to skip), N FP64, squared distance of each step (entry 0 = 0).
+ * Each step appends the unvisited system with the smallest squared Frobenius distance
+ * sum_p (P_cur[p] - P_j[p])^2 to the system appended last; the sum of the squares of the FP64
+ * differences is accumulated in double-double and rounded once, ties go to the lowest index,
+ * NaN/Inf distances are never preferred. Errors: SKR_EINVAL (N < 0, p < 1 with N > 0, start out
+ * of range), SKR_ENOMEM.
+ */
+int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64_t start,
+             int64_t* order_host, double* step_d2_host);
+
+/*
+ * Solve A_i x_i = b_i for i = order[0], order[1], ... (Eq. 1) with GCRO-DR(m, k) (Alg. 2),
+ * x0 = 0, carrying U_k from each solved system to the next (App. B.1).
+ *  ops:    host array of N operators (device data), indexed by original system index;
+ *          all must have the same n.
+ *  b_dev:  host array of N device pointers to right-hand sides (n FP64 each).
+ *  x_dev:  host array of N device pointers, out, solutions (n FP64 each).
+ *  order:  host array of N int64 (a permutation), or NULL for 0..N-1.
+ *  results_host: out, N entries at the original indices.
+ * Returns SKR_OK, SKR_WARN_NOTCONVERGED if some system hit maxit, or an error
+ * (SKR_EINVAL, SKR_ENOMEM, SKR_EHIP). A system with NaN/Inf in b or A gets status
+ * SKR_NONFINITE and x = 0; the sequence goes on.
+ */
+int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_dev,
+                       double* const* x_dev, int64_t N, const int64_t* order,
+                       const skr_opts* opts, skr_result* results_host);
+
+/* y_dev = A x_dev for one operator (the sparse product of the Arnoldi step; Eq. 3). */
+int skr_spmv(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKR_H */

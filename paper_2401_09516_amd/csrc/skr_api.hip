@@ -1,0 +1,425 @@
+// C ABI of libskr (include/skr.h): context, device workspace and the host-side control of the
+// sorted-sequence GCRO-DR solve. All arithmetic runs in the kernels of skr_solver.hip,
+// skr_dense.hip and skr_sort.hip; the host only sequences launches and reads a small control
+// block once per Arnoldi cycle.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "skr_internal.hpp"
+
+namespace skr {
+struct ColList;
+void launch_init(hipStream_t, const Work&, const double*, double*, double);
+void launch_clear_nonfinite(hipStream_t, const Work&);
+void launch_check_finite(hipStream_t, const Work&, const double*, long);
+void launch_zero(hipStream_t, double*, int);
+void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int);
+void launch_close_basis(hipStream_t, const Work&);
+void launch_cycle_gram(hipStream_t, const Work&, int, int);
+void launch_cycle_dense(hipStream_t, const Work&, int, int);
+void launch_cycle_update(hipStream_t, const Work&, double*);
+void launch_true_residual(hipStream_t, const Work&, const DevOp&, const double*, const double*);
+void launch_spmm(hipStream_t, const Work&, const DevOp&, int);
+void launch_startup_gram(hipStream_t, const Work&, int);
+void launch_chol(hipStream_t, const Work&, int, int);
+void launch_startup_apply(hipStream_t, const Work&, int, int);
+void launch_startup_project(hipStream_t, const Work&, double*);
+void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
+void launch_sort(hipStream_t, const double*, long, long, long, double*, long long*, double*);
+long sort_nmax();
+}  // namespace skr
+
+using namespace skr;
+
+struct skr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Work w;
+    CtrlHost* hctrl = nullptr;     // pinned
+    int* hkeff = nullptr;          // pinned
+    // sort scratch
+    double* sortD = nullptr;
+    size_t sortD_cap = 0;
+    long long* order_d = nullptr;
+    double* dist_d = nullptr;
+    size_t sortN_cap = 0;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(SKR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIPLAUNCHCHK()                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = hipGetLastError();                                                      \
+        if (e_ != hipSuccess) return fail(SKR_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+static void free_work(Work& w) {
+    double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part, w.part1, w.gpart, w.gram, w.red1, w.red2, w.H, w.Bm};
+    for (double* p : bufs)
+        if (p) (void)hipFree(p);
+    if (w.ctrl) (void)hipFree(w.ctrl);
+    if (w.coef) (void)hipFree(w.coef);
+    if (w.counters) (void)hipFree(w.counters);
+    w = Work();
+}
+
+template <class T>
+static hipError_t dalloc(T** p, size_t count) {
+    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
+    Work& w = ctx->w;
+    if (w.basis && w.n == n && w.m == m && w.k == k) return SKR_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    free_work(w);
+    w.n = n;
+    w.m = m;
+    w.k = k;
+    w.ld = (n + 63) / 64 * 64;
+    w.nblk = (n + ROWS - 1) / ROWS;
+    w.ngblk = std::min(256, std::max(1, (n + 255) / 256));
+    w.gram_max = (size_t)gram_cols_max(m, k);
+    const size_t ld = (size_t)w.ld;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(dalloc(&w.basis, (size_t)(k + m + 1) * ld));
+    chk(dalloc(&w.U, (size_t)std::max(k, 1) * ld));
+    chk(dalloc(&w.W[0], ld));
+    chk(dalloc(&w.W[1], ld));
+    chk(dalloc(&w.r, ld));
+    chk(dalloc(&w.part, (size_t)w.nblk * NC));
+    chk(dalloc(&w.part1, (size_t)w.nblk));
+    chk(dalloc(&w.gpart, (size_t)w.ngblk * w.gram_max));
+    chk(dalloc(&w.gram, w.gram_max));
+    chk(dalloc(&w.red1, NC));
+    chk(dalloc(&w.red2, NC));
+    chk(dalloc(&w.H, (size_t)LDH * MMAX));
+    chk(dalloc(&w.Bm, (size_t)KMAX * MMAX));
+    chk(dalloc(&w.ctrl, 1));
+    chk(dalloc(&w.coef, 1));
+    chk(dalloc(&w.counters, 8));
+    if (e != hipSuccess) {
+        free_work(w);
+        return fail(SKR_ENOMEM, "device workspace allocation failed: %s", hipGetErrorString(e));
+    }
+    // zero everything once so that unused basis columns never hold NaN bit patterns
+    chk(hipMemsetAsync(w.basis, 0, (size_t)(k + m + 1) * ld * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.U, 0, (size_t)std::max(k, 1) * ld * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.W[0], 0, ld * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.W[1], 0, ld * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.H, 0, (size_t)LDH * MMAX * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.Bm, 0, (size_t)KMAX * MMAX * sizeof(double), ctx->stream));
+    chk(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), ctx->stream));
+    chk(hipMemsetAsync(w.coef, 0, sizeof(Coef), ctx->stream));
+    chk(hipMemsetAsync(w.counters, 0, 8 * sizeof(unsigned), ctx->stream));
+    if (e != hipSuccess) return fail(SKR_EHIP, "workspace initialisation failed: %s", hipGetErrorString(e));
+    return SKR_OK;
+}
+
+static int read_ctrl(skr_ctx* ctx) {
+    HIPCHK(hipMemcpyAsync(ctx->hctrl, ctx->w.ctrl, sizeof(CtrlHost), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+
+static int to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
+    d = DevOp();
+    d.kind = o.kind;
+    d.n = o.n;
+    if (o.n <= 0) return fail(SKR_EINVAL, "operator n must be positive (got %d)", o.n);
+    if (o.kind == SKR_OP_CSR) {
+        if (!o.rowptr || !o.colind || !o.values || o.nnz < 0)
+            return fail(SKR_EINVAL, "CSR operator needs rowptr, colind, values and nnz >= 0");
+        d.rowptr = o.rowptr;
+        d.colind = o.colind;
+        d.val = o.values;
+        nvals = o.nnz;
+    } else if (o.kind == SKR_OP_STENCIL5) {
+        if (!o.ax || !o.ay || o.nx <= 0 || o.ny <= 0 || (int64_t)o.nx * o.ny != o.n)
+            return fail(SKR_EINVAL, "stencil operator needs ax, ay and nx * ny == n");
+        d.nx = o.nx;
+        d.ny = o.ny;
+        d.inv_h2 = o.inv_h2;
+        d.ax = o.ax;
+        d.ay = o.ay;
+        nvals = 0;
+    } else {
+        return fail(SKR_EINVAL, "unknown operator kind %d", o.kind);
+    }
+    return SKR_OK;
+}
+
+extern "C" {
+
+const char* skr_version(void) { return "skr-gfx950 0.1"; }
+
+const char* skr_last_error(void) { return g_err.c_str(); }
+
+int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
+    if (!out) return fail(SKR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SKR_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    skr_ctx* c = new skr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void**)&c->hctrl, sizeof(CtrlHost), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->hkeff, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(SKR_EHIP, "pinned host allocation failed");
+    }
+    *out = c;
+    g_err.clear();
+    return SKR_OK;
+}
+
+int skr_ctx_destroy(skr_ctx* ctx) {
+    if (!ctx) return SKR_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    free_work(ctx->w);
+    if (ctx->sortD) (void)hipFree(ctx->sortD);
+    if (ctx->order_d) (void)hipFree(ctx->order_d);
+    if (ctx->dist_d) (void)hipFree(ctx->dist_d);
+    if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
+    if (ctx->hkeff) (void)hipHostFree(ctx->hkeff);
+    delete ctx;
+    return SKR_OK;
+}
+
+int skr_spmv(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev) {
+    if (!ctx || !op || !x_dev || !y_dev) return fail(SKR_EINVAL, "NULL argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    DevOp d;
+    int64_t nv;
+    int rc = to_devop(*op, d, nv);
+    if (rc) return rc;
+    launch_spmv(ctx->stream, d, x_dev, y_dev);
+    HIPLAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+
+int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64_t start, int64_t* order_host,
+             double* step_d2_host) {
+    if (!ctx) return fail(SKR_EINVAL, "NULL context");
+    if (N < 0) return fail(SKR_EINVAL, "N must be >= 0");
+    if (N == 0) return SKR_OK;
+    if (!order_host) return fail(SKR_EINVAL, "order_host is NULL");
+    if (p < 1 || !params_dev) return fail(SKR_EINVAL, "need p >= 1 and params_dev");
+    if (start < 0 || start >= N) return fail(SKR_EINVAL, "start %lld out of range", (long long)start);
+    if (N > sort_nmax()) return fail(SKR_EINVAL, "N > %ld is not supported", sort_nmax());
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t need = (size_t)N * (size_t)N;
+    if (ctx->sortD_cap < need) {
+        if (ctx->sortD) (void)hipFree(ctx->sortD);
+        ctx->sortD = nullptr;
+        ctx->sortD_cap = 0;
+        if (hipMalloc((void**)&ctx->sortD, need * sizeof(double)) != hipSuccess)
+            return fail(SKR_ENOMEM, "sort distance matrix (%zu bytes)", need * sizeof(double));
+        ctx->sortD_cap = need;
+    }
+    if (ctx->sortN_cap < (size_t)N) {
+        if (ctx->order_d) (void)hipFree(ctx->order_d);
+        if (ctx->dist_d) (void)hipFree(ctx->dist_d);
+        ctx->order_d = nullptr;
+        ctx->dist_d = nullptr;
+        ctx->sortN_cap = 0;
+        if (hipMalloc((void**)&ctx->order_d, N * sizeof(long long)) != hipSuccess ||
+            hipMalloc((void**)&ctx->dist_d, N * sizeof(double)) != hipSuccess)
+            return fail(SKR_ENOMEM, "sort output buffers");
+        ctx->sortN_cap = (size_t)N;
+    }
+    launch_sort(ctx->stream, params_dev, (long)N, (long)p, (long)start, ctx->sortD, ctx->order_d, ctx->dist_d);
+    HIPLAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(order_host, ctx->order_d, N * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
+    if (step_d2_host)
+        HIPCHK(hipMemcpyAsync(step_d2_host, ctx->dist_d, N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+
+int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_dev, double* const* x_dev, int64_t N,
+                       const int64_t* order, const skr_opts* opts, skr_result* results_host) {
+    if (!ctx || !opts) return fail(SKR_EINVAL, "NULL context or options");
+    if (N < 0) return fail(SKR_EINVAL, "N must be >= 0");
+    if (N == 0) return SKR_OK;
+    if (!ops || !b_dev || !x_dev || !results_host) return fail(SKR_EINVAL, "NULL array argument");
+    const int m = opts->m, k = opts->k;
+    const double rtol = opts->rtol;
+    const int64_t maxit = opts->maxit;
+    if (m < 1 || m > MMAX) return fail(SKR_EINVAL, "m must be in [1, %d] (got %d)", MMAX, m);
+    if (k < 0 || k > KMAX || k >= m) return fail(SKR_EINVAL, "k must satisfy 0 <= k < m and k <= %d (got %d)", KMAX, k);
+    if (!(rtol > 0.0)) return fail(SKR_EINVAL, "rtol must be > 0");
+    if (maxit < 0) return fail(SKR_EINVAL, "maxit must be >= 0");
+    const int n = ops[0].n;
+    std::vector<char> seen((size_t)N, 0);
+    for (int64_t q = 0; q < N; ++q) {
+        const int64_t idx = order ? order[q] : q;
+        if (idx < 0 || idx >= N || seen[(size_t)idx]) return fail(SKR_EINVAL, "order is not a permutation of 0..N-1");
+        seen[(size_t)idx] = 1;
+        if (ops[idx].n != n) return fail(SKR_EINVAL, "all operators must have the same n");
+        if (!b_dev[idx] || !x_dev[idx]) return fail(SKR_EINVAL, "NULL b or x pointer for system %lld", (long long)idx);
+        DevOp d;
+        int64_t nv;
+        int rc = to_devop(ops[idx], d, nv);
+        if (rc) return rc;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_work(ctx, n, m, k);
+    if (rc) return rc;
+    Work& w = ctx->w;
+    hipStream_t s = ctx->stream;
+    CtrlHost& hc = *ctx->hctrl;
+    int kin = 0;   // recycled vectors carried from the previous system (held in w.U)
+    bool any_maxit = false;
+    for (int64_t q = 0; q < N; ++q) {
+        const int64_t idx = order ? order[q] : q;
+        DevOp op;
+        int64_t nvals;
+        to_devop(ops[idx], op, nvals);
+        const double* b = b_dev[idx];
+        double* x = x_dev[idx];
+        skr_result res;
+        std::memset(&res, 0, sizeof res);
+
+        launch_clear_nonfinite(s, w);
+        launch_init(s, w, b, x, rtol);
+        if (op.kind == SKR_OP_CSR) {
+            launch_check_finite(s, w, op.val, (long)nvals);
+        } else {
+            launch_check_finite(s, w, op.ax, (long)op.ny * (op.nx + 1));
+            launch_check_finite(s, w, op.ay, (long)(op.ny + 1) * op.nx);
+        }
+        HIPLAUNCHCHK();
+        if ((rc = read_ctrl(ctx))) return rc;
+        if (hc.nonfinite || !std::isfinite(hc.bnorm)) {
+            launch_zero(s, x, n);
+            res.status = SKR_NONFINITE;
+            res.relres_true = NAN;
+            res.relres_est = NAN;
+            results_host[idx] = res;
+            continue;   // the carried recycle space is passed on untouched
+        }
+        if (hc.bnorm == 0.0) {
+            res.status = SKR_CONVERGED;
+            results_host[idx] = res;
+            continue;
+        }
+        const double bnorm = hc.bnorm, tol_abs = hc.tol_abs;
+        int64_t iters = 0, spmv = 0;
+        int cycles = 0;
+        int kc = 0;
+        // ---- start-up with the carried recycle space (App. B.1)
+        if (k > 0 && kin > 0) {
+            launch_spmm(s, w, op, kin);
+            launch_startup_gram(s, w, kin);
+            launch_chol(s, w, kin, 1);
+            launch_startup_apply(s, w, 1, 0);
+            HIPLAUNCHCHK();
+            HIPCHK(hipMemcpyAsync(ctx->hkeff, &w.coef->k_eff, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const int ke = *ctx->hkeff;
+            spmv += kin;
+            res.rank_dropped = kin - ke;
+            if (ke > 0) {
+                launch_startup_gram(s, w, ke);
+                launch_chol(s, w, ke, 0);
+                launch_startup_apply(s, w, 0, 1);
+                launch_startup_project(s, w, x);
+                HIPLAUNCHCHK();
+            }
+            if ((rc = read_ctrl(ctx))) return rc;
+            kc = hc.kc;
+            res.k_start = kc;
+        }
+        int status = -1;
+        double est = hc.beta;
+        if (hc.beta <= tol_abs) {
+            launch_true_residual(s, w, op, b, x);
+            HIPLAUNCHCHK();
+            if ((rc = read_ctrl(ctx))) return rc;
+            spmv += 1;
+            if (std::sqrt(hc.res2) <= tol_abs) status = SKR_CONVERGED;
+        }
+        // ---- Arnoldi cycles (Alg. 2)
+        while (status < 0) {
+            if (iters >= maxit) { status = SKR_MAXIT; break; }
+            int scyc = (kc == 0) ? m : m - kc;
+            scyc = (int)std::min<int64_t>(scyc, maxit - iters);
+            for (int j = 0; j < scyc; ++j) launch_step(s, w, op, kc, j, scyc);
+            launch_close_basis(s, w);
+            if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
+            launch_cycle_dense(s, w, scyc, k);
+            launch_cycle_update(s, w, x);
+            HIPLAUNCHCHK();
+            if ((rc = read_ctrl(ctx))) return rc;
+            const int jd = hc.j_done;
+            if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
+            iters += jd;
+            spmv += jd;
+            cycles += 1;
+            est = hc.est;
+            kc = hc.kc;
+            if (!std::isfinite(est) || !std::isfinite(hc.beta)) {
+                launch_zero(s, x, n);
+                status = SKR_NONFINITE;
+                kc = 0;
+                break;
+            }
+            if (est <= tol_abs || hc.breakdown) {
+                const int brk = hc.breakdown;
+                launch_true_residual(s, w, op, b, x);
+                HIPLAUNCHCHK();
+                if ((rc = read_ctrl(ctx))) return rc;
+                spmv += 1;
+                if (std::sqrt(hc.res2) <= tol_abs) {
+                    status = brk ? SKR_BREAKDOWN : SKR_CONVERGED;
+                    break;
+                }
+            }
+        }
+        if (status == SKR_MAXIT) {
+            launch_true_residual(s, w, op, b, x);
+            HIPLAUNCHCHK();
+            if ((rc = read_ctrl(ctx))) return rc;
+            spmv += 1;
+            any_maxit = true;
+        }
+        res.status = status;
+        res.cycles = cycles;
+        res.iters = iters;
+        res.spmv = spmv;
+        res.relres_true = status == SKR_NONFINITE ? NAN : std::sqrt(hc.res2) / bnorm;
+        res.relres_est = est / bnorm;
+        results_host[idx] = res;
+        kin = (k > 0) ? kc : 0;
+    }
+    return any_maxit ? SKR_WARN_NOTCONVERGED : SKR_OK;
+}
+
+}  // extern "C"

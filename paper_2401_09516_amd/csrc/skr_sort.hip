@@ -1,0 +1,136 @@
+// Greedy nearest-neighbour sort of the systems (Alg. 1, Sec. 4.1) on gfx950.
+//
+// 1. Squared distance matrix d2(i, j) = sum_p (P_i[p] - P_j[p])^2 over N x p row-major parameter
+//    matrices. Each FP64 difference is rounded as usual, its square is split exactly into two
+//    doubles with an FMA, and the squares are accumulated in double-double (error-free sums), then
+//    rounded once. The pair is renormalised after every 128-element chunk, which bounds the
+//    accumulated error by about p * 128 * 2^-106 relative (~1e-25 at p = 66564), far below half
+//    an ulp of the result: the value equals the correctly rounded exact sum except when that sum
+//    lies within that distance of a rounding boundary, so the summation order does not matter.
+//    One workgroup computes a 16 x 16 tile of pairs, staging 128-element chunks of both row
+//    blocks in LDS; only tiles on or above the diagonal are launched and each value is written to
+//    both (i, j) and (j, i).
+// 2. One workgroup walks the greedy path: N - 1 steps, each an arg-min over one row of d2 of the
+//    unvisited systems, ties to the lowest index, NaN/Inf never preferred (a row with no finite
+//    candidate takes the lowest unvisited index).
+#include "skr_internal.hpp"
+
+namespace skr {
+
+constexpr int TS = 16;     // tile side (pairs)
+constexpr int PCH = 128;   // parameter chunk staged in LDS
+
+__global__ __launch_bounds__(TS * TS) void k_sq_dist(const double* __restrict__ P, long N, long p,
+                                                     double* __restrict__ D) {
+#pragma clang fp contract(off)
+    // tile index -> (bi, bj) with bi <= bj, row-major over the upper triangle
+    const long nt = (N + TS - 1) / TS;
+    long tid = blockIdx.x, bi = 0;
+    while (tid >= nt - bi) { tid -= nt - bi; ++bi; }
+    const long bj = bi + tid;
+    __shared__ double Ai[TS * (PCH + 1)];
+    __shared__ double Aj[TS * (PCH + 1)];
+    const int ti = threadIdx.x / TS, tj = threadIdx.x % TS;
+    const long i = bi * TS + ti, j = bj * TS + tj;
+    double s = 0.0, lo = 0.0;
+    for (long e0 = 0; e0 < p; e0 += PCH) {
+        const int len = (int)((p - e0) < PCH ? (p - e0) : PCH);
+        __syncthreads();
+        for (int e = threadIdx.x; e < TS * PCH; e += TS * TS) {
+            const int r = e / PCH, c = e % PCH;
+            const long ri = bi * TS + r, rj = bj * TS + r;
+            Ai[r * (PCH + 1) + c] = (ri < N && c < len) ? P[ri * p + e0 + c] : 0.0;
+            Aj[r * (PCH + 1) + c] = (rj < N && c < len) ? P[rj * p + e0 + c] : 0.0;
+        }
+        __syncthreads();
+        const double* a = Ai + ti * (PCH + 1);
+        const double* b = Aj + tj * (PCH + 1);
+        for (int c = 0; c < len; ++c) {
+            const double d = a[c] - b[c];
+            const double hi = d * d;
+            const double he = __builtin_fma(d, d, -hi);   // exact: d*d = hi + he
+            // error-free s + hi
+            const double t = s + hi;
+            const double bb = t - s;
+            const double err = (s - (t - bb)) + (hi - bb);
+            s = t;
+            lo = lo + (err + he);
+        }
+        // renormalise (s, lo) once per chunk so that |lo| stays below half an ulp of s
+        const double t2 = s + lo;
+        lo = lo - (t2 - s);
+        s = t2;
+    }
+    if (i < N && j < N) {
+        const double v = s + lo;
+        D[i * N + j] = v;
+        D[j * N + i] = v;
+    }
+}
+
+__device__ __forceinline__ bool key_less(double a, long ia, double b, long ib) {
+    return a < b || (a == b && ia < ib);
+}
+
+constexpr int GW = 256;
+constexpr long SORT_NMAX = 262144;   // visited bitmap kept in LDS (32 KB)
+
+__global__ __launch_bounds__(GW) void k_greedy(const double* __restrict__ D, long N, long start,
+                                               long long* __restrict__ order, double* __restrict__ dist) {
+    __shared__ unsigned visited[SORT_NMAX / 32];
+    __shared__ double sk[GW / 64];
+    __shared__ long si[GW / 64];
+    __shared__ long cur_s;
+    const int t = threadIdx.x;
+    for (long q = t; q < (N + 31) / 32; q += GW) visited[q] = 0u;
+    __syncthreads();
+    if (t == 0) {
+        visited[start >> 5] |= 1u << (start & 31);
+        order[0] = start;
+        dist[0] = 0.0;
+        cur_s = start;
+    }
+    __syncthreads();
+    for (long step = 1; step < N; ++step) {
+        const long cur = cur_s;
+        double bk = INFINITY;
+        long bi = N;
+        for (long jj = t; jj < N; jj += GW) {
+            if (visited[jj >> 5] & (1u << (jj & 31))) continue;
+            double v = D[cur * N + jj];
+            if (!(v < INFINITY)) v = INFINITY;    // NaN and +Inf are never preferred
+            if (key_less(v, jj, bk, bi)) { bk = v; bi = jj; }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ok = __shfl_xor(bk, off, 64);
+            const long oi = __shfl_xor(bi, off, 64);
+            if (key_less(ok, oi, bk, bi)) { bk = ok; bi = oi; }
+        }
+        if ((t & 63) == 0) { sk[t >> 6] = bk; si[t >> 6] = bi; }
+        __syncthreads();
+        if (t == 0) {
+            double k0 = sk[0];
+            long i0 = si[0];
+            for (int q = 1; q < GW / 64; ++q)
+                if (key_less(sk[q], si[q], k0, i0)) { k0 = sk[q]; i0 = si[q]; }
+            order[step] = i0;
+            dist[step] = D[cur * N + i0];
+            visited[i0 >> 5] |= 1u << (i0 & 31);
+            cur_s = i0;
+        }
+        __syncthreads();
+    }
+}
+
+long sort_nmax() { return SORT_NMAX; }
+
+void launch_sort(hipStream_t s, const double* P, long N, long p, long start, double* D, long long* order,
+                 double* dist) {
+    const long nt = (N + TS - 1) / TS;
+    const long tiles = nt * (nt + 1) / 2;
+    if (tiles > 0 && p > 0) hipLaunchKernelGGL(k_sq_dist, dim3((unsigned)tiles), dim3(TS * TS), 0, s, P, N, p, D);
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GW), 0, s, (const double*)D, N, start, order, dist);
+}
+
+}  // namespace skr

@@ -1,0 +1,184 @@
+"""ctypes binding of libskr (include/skr.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libskr.so``; this module converts Python objects
+into the C structures and pointers of the ABI. Device buffers are passed as objects with a
+``data_ptr()`` method (PyTorch tensors on a ROCm device) or as raw integer addresses. Loading
+fails loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libskr.so")
+
+SKR_OK = 0
+SKR_EINVAL = -1
+SKR_ENOMEM = -2
+SKR_EHIP = -3
+SKR_ENONFINITE = -4
+SKR_WARN_NOTCONVERGED = 1
+
+SKR_CONVERGED = 0
+SKR_MAXIT = 1
+SKR_BREAKDOWN = 2
+SKR_NONFINITE = 3
+
+SKR_OP_CSR = 0
+SKR_OP_STENCIL5 = 1
+
+EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
+            "skr_solve_sequence", "skr_spmv")
+
+
+class SkrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libskr error {code}: {msg}")
+        self.code = code
+
+
+class skr_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("inv_h2", ctypes.c_double),
+                ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p)]
+
+
+class skr_opts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("k", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+class skr_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("k_start", ctypes.c_int32),
+                ("rank_dropped", ctypes.c_int32), ("iters", ctypes.c_int64), ("spmv", ctypes.c_int64),
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load libskr.so and declare the prototypes of include/skr.h."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.skr_ctx_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+    lib.skr_ctx_create.restype = i32
+    lib.skr_ctx_destroy.argtypes = [vp]
+    lib.skr_ctx_destroy.restype = i32
+    lib.skr_last_error.argtypes = []
+    lib.skr_last_error.restype = ctypes.c_char_p
+    lib.skr_version.argtypes = []
+    lib.skr_version.restype = ctypes.c_char_p
+    lib.skr_sort.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
+    lib.skr_sort.restype = i32
+    lib.skr_solve_sequence.argtypes = [vp, ctypes.POINTER(skr_op), ctypes.POINTER(vp), ctypes.POINTER(vp), i64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(skr_opts),
+                                       ctypes.POINTER(skr_result)]
+    lib.skr_solve_sequence.restype = i32
+    lib.skr_spmv.argtypes = [vp, ctypes.POINTER(skr_op), vp, vp]
+    lib.skr_spmv.restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(buf) -> int:
+    if buf is None:
+        return 0
+    if isinstance(buf, int):
+        return buf
+    return int(buf.data_ptr())
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SkrError(rc, load_library().skr_last_error().decode())
+    return rc
+
+
+# ----------------------------------------------------------------------------------- operators
+@dataclass
+class Operator:
+    """An skr_op plus references that keep its device buffers alive."""
+    c: skr_op
+    keep: tuple
+
+
+def csr_op(rowptr, colind, values, n: int) -> Operator:
+    """CSR operator from device buffers (int32 rowptr[n+1], int32 colind[nnz], float64 values[nnz])."""
+    nnz = int(values.numel()) if hasattr(values, "numel") else 0
+    c = skr_op(kind=SKR_OP_CSR, n=n, nnz=nnz, rowptr=_ptr(rowptr), colind=_ptr(colind), values=_ptr(values))
+    return Operator(c, (rowptr, colind, values))
+
+
+def stencil_op(ax, ay, nx: int, ny: int, inv_h2: float) -> Operator:
+    """Matrix-free 5-point operator from face coefficients ax[ny*(nx+1)], ay[(ny+1)*nx] (float64)."""
+    c = skr_op(kind=SKR_OP_STENCIL5, n=nx * ny, nx=nx, ny=ny, inv_h2=inv_h2, ax=_ptr(ax), ay=_ptr(ay))
+    return Operator(c, (ax, ay))
+
+
+# ----------------------------------------------------------------------------------- entry points
+def skr_version() -> str:
+    return load_library().skr_version().decode()
+
+
+def skr_ctx_create(device: int = 0, stream=None) -> int:
+    """Create a context on ``device`` enqueuing on ``stream`` (a hipStream_t address, or None)."""
+    out = ctypes.c_void_p()
+    s = stream if isinstance(stream, int) or stream is None else int(stream)
+    _check(load_library().skr_ctx_create(device, s, ctypes.byref(out)))
+    return out.value
+
+
+def skr_ctx_destroy(ctx: int) -> None:
+    _check(load_library().skr_ctx_destroy(ctx))
+
+
+def skr_sort(ctx: int, params, N: int, p: int, start: int = 0, want_dist: bool = True):
+    """Alg. 1 on device parameters (N x p float64, row-major). Returns (order int64, step d2 or None)."""
+    order = np.zeros(max(N, 1), dtype=np.int64)
+    dist = np.zeros(max(N, 1), dtype=np.float64) if want_dist else None
+    dptr = dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_dist else None
+    _check(load_library().skr_sort(ctx, _ptr(params), N, p, start,
+                                   order.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dptr))
+    return order[:N], (dist[:N] if want_dist else None)
+
+
+def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
+                       maxit: int = 10000, flags: int = 0):
+    """Solve the systems in ``order`` with GCRO-DR(m, k) (k = 0: GMRES(m)).
+
+    ``ops``: list of Operator; ``bs``/``xs``: device buffers. Returns (return code, list of result dicts
+    at the original indices).
+    """
+    N = len(ops)
+    arr = (skr_op * max(N, 1))(*[o.c for o in ops])
+    bp = (ctypes.c_void_p * max(N, 1))(*[_ptr(b) for b in bs])
+    xp = (ctypes.c_void_p * max(N, 1))(*[_ptr(x) for x in xs])
+    if order is not None:
+        ordarr = np.ascontiguousarray(np.asarray(order, dtype=np.int64))
+        optr = ordarr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    else:
+        optr = None
+    opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
+    res = (skr_result * max(N, 1))()
+    rc = _check(load_library().skr_solve_sequence(ctx, arr, bp, xp, N, optr, ctypes.byref(opts), res))
+    out = [dict(status=r.status, cycles=r.cycles, k_start=r.k_start, rank_dropped=r.rank_dropped,
+                iters=r.iters, spmv=r.spmv, relres_true=r.relres_true, relres_est=r.relres_est)
+           for r in list(res)[:N]]
+    return rc, out
+
+
+def skr_spmv(ctx: int, op: Operator, x, y) -> None:
+    """y = A x on the device."""
+    _check(load_library().skr_spmv(ctx, ctypes.byref(op.c), _ptr(x), _ptr(y)))

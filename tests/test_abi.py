@@ -1,0 +1,67 @@
+"""The C ABI library loads and exports every function declared in include/*.h, and the ctypes
+structures of the binding match the C layouts (checked with a gcc-compiled probe). No GPU needed."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2401_09516_amd import skr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b(skr_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_declared_symbols():
+    if not os.path.exists(skr.LIB_PATH):
+        pytest.fail("libskr.so is not built (run __graft_entry__.build())")
+    lib = skr.load_library()
+    names = declared_functions()
+    assert set(skr.EXPORTED) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.skr_version().decode().startswith("skr-gfx950")
+    assert lib.skr_last_error() is not None
+
+
+def test_struct_layouts_match_header(tmp_path):
+    probe = tmp_path / "probe.c"
+    probe.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "skr.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("skr_op %zu\nskr_opts %zu\nskr_result %zu\n", sizeof(skr_op), sizeof(skr_opts), sizeof(skr_result));
+  F(skr_op, kind); F(skr_op, n); F(skr_op, nnz); F(skr_op, rowptr); F(skr_op, colind); F(skr_op, values);
+  F(skr_op, nx); F(skr_op, ny); F(skr_op, inv_h2); F(skr_op, ax); F(skr_op, ay);
+  F(skr_opts, m); F(skr_opts, k); F(skr_opts, rtol); F(skr_opts, maxit); F(skr_opts, flags);
+  F(skr_result, status); F(skr_result, cycles); F(skr_result, k_start); F(skr_result, rank_dropped);
+  F(skr_result, iters); F(skr_result, spmv); F(skr_result, relres_true); F(skr_result, relres_est);
+  return 0;
+}
+''')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe), "-o", str(exe)], check=True)
+    out = dict(ln.rsplit(" ", 1) for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    for cname, ct in (("skr_op", skr.skr_op), ("skr_opts", skr.skr_opts), ("skr_result", skr.skr_result)):
+        assert int(out[cname]) == ctypes.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
+
+
+def test_binding_rejects_missing_library(tmp_path):
+    with pytest.raises(ImportError):
+        skr.load_library(str(tmp_path / "nope.so"))

@@ -1,0 +1,232 @@
+"""GPU parity: libskr (HIP, gfx950) against the CPU oracle on the same seeded inputs.
+
+Bars (written in the tests): sort order and step distances bit-exact; SpMV per-row error within
+8 eps sum_j |a_ij x_j|; solutions within 1e-7 relative of the oracle's (or the residual bound
+mu (rr_gpu + rr_oracle) when that is larger), both at relative residual <= 1e-8; Arnoldi step
+counts equal to the oracle's up to one step.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from gpu_common import log, make_ctx, need_gpu, solution_bound
+from workloads import darcy_sequence, param_matrix
+from workloads.device import upload_systems
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = need_gpu()
+    from paper_2401_09516_amd import skr
+    ctx = make_ctx(torch)
+    yield torch, skr, ctx
+    skr.skr_ctx_destroy(ctx)
+
+
+# ------------------------------------------------------------------------------------------ SpMV
+@pytest.mark.parametrize("N_g", [1, 7, 32, 37, 256])
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_spmv(env, N_g, kind):
+    torch, skr, ctx = env
+    log(f"[spmv] kind={kind} N_g={N_g}")
+    s = darcy_sequence(N_g, 1, first_seed=9)[0]
+    x = np.random.default_rng(N_g).standard_normal(s.n)
+    ops, _, _ = upload_systems([s], "cuda:0", kind)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.full_like(xd, np.nan)
+    skr.skr_spmv(ctx, ops[0], xd, yd)
+    y = yd.cpu().numpy()
+    y_ref = s.A @ x
+    bound = 8 * EPS * (abs(s.A) @ np.abs(x))
+    assert np.all(np.abs(y - y_ref) <= bound)
+
+
+# ------------------------------------------------------------------------------------------ sort
+def _sort_gpu(torch, skr, ctx, P, start=0):
+    Pd = torch.from_numpy(np.ascontiguousarray(P)).cuda()
+    return skr.skr_sort(ctx, Pd, P.shape[0], P.shape[1], start)
+
+
+def test_sort_config1(env):
+    torch, skr, ctx = env
+    log("[sort] 32x32 Darcy, 16 systems")
+    P = param_matrix(darcy_sequence(32, 16))
+    order, d2 = _sort_gpu(torch, skr, ctx, P)
+    ref, ref_d2 = oracle.greedy_sort(P, return_dist=True)
+    assert np.array_equal(order, ref)
+    assert np.array_equal(d2, ref_d2)          # bitwise
+
+
+@pytest.mark.parametrize("N,p,start,dups", [(1, 5, 0, False), (2, 3, 1, False), (37, 300, 0, True),
+                                             (37, 300, 11, False), (50, 129, 3, True)])
+def test_sort_random_ragged(env, N, p, start, dups):
+    torch, skr, ctx = env
+    log(f"[sort] random N={N} p={p} start={start} dups={dups}")
+    rng = np.random.default_rng(N * 1000 + p)
+    P = rng.standard_normal((N, p)) * np.exp(rng.standard_normal((1, p)))
+    if dups:
+        P[N - 1] = P[2]
+        P[N - 2] = P[2]
+    order, d2 = _sort_gpu(torch, skr, ctx, P, start)
+    ref, ref_d2 = oracle.greedy_sort(P, start=start, return_dist=True)
+    assert np.array_equal(order, ref)
+    assert np.array_equal(d2, ref_d2)
+
+
+def test_sort_nonfinite_rows(env):
+    torch, skr, ctx = env
+    log("[sort] rows with NaN / Inf")
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal((9, 7))
+    P[4, 2] = np.nan
+    P[6, 0] = np.inf
+    order, _ = _sort_gpu(torch, skr, ctx, P)
+    ref = oracle.greedy_sort(P)
+    assert np.array_equal(order, ref)
+
+
+def test_sort_config2_sampled(env):
+    """256x256 Darcy parameter fields, 400 systems: permutation plus sampled steps re-derived
+    by the oracle (exact distance, arg-min over the remaining systems)."""
+    torch, skr, ctx = env
+    log("[sort] 256x256 Darcy, 400 systems (p = 66564)")
+    P = param_matrix(darcy_sequence(256, 400))
+    order, d2 = _sort_gpu(torch, skr, ctx, P)
+    assert order[0] == 0 and np.array_equal(np.sort(order), np.arange(400))
+    for t in (1, 2, 200, 399):
+        cur = order[t - 1]
+        left = np.setdiff1d(np.arange(400), order[:t])
+        dd = np.array([oracle.sq_distance(P[cur], P[j]) for j in left])
+        best = left[np.flatnonzero(dd == dd.min())[0]]
+        assert order[t] == best
+        assert d2[t] == dd.min()
+
+
+# ------------------------------------------------------------------------------------------ solves
+def _compare(systems, res_gpu, xs, res_ref, tag):
+    for i, s in enumerate(systems):
+        g, r = res_gpu[i], res_ref[i]
+        x = xs[i].cpu().numpy()
+        assert g["status"] == r.status, (tag, i, g, r.status)
+        if r.status != oracle.CONVERGED:
+            continue
+        assert g["relres_true"] <= 1e-8 * (1 + 1e-12), (tag, i, g)
+        bound, mu = solution_bound(s.A, s.b, r.x, g["relres_true"], r.relres_true)
+        rel = np.linalg.norm(x - r.x) / np.linalg.norm(r.x)
+        log(f"  {tag} sys {i}: iters gpu {g['iters']} oracle {r.iters}  cycles {g['cycles']}/{r.cycles}"
+            f"  rel {rel:.2e} (bound {bound:.1e}, mu {mu:.2f})")
+        assert rel <= bound, (tag, i, rel, bound)
+        assert abs(g["iters"] - r.iters) <= 1, (tag, i, g["iters"], r.iters)
+        assert g["k_start"] == r.k_start, (tag, i)
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_solve_config1(env, kind):
+    """32x32 Darcy, 16 systems sorted into one chain, GCRO-DR(30,10), rel-res 1e-8."""
+    torch, skr, ctx = env
+    log(f"[solve] config-1 chain kind={kind}")
+    systems = darcy_sequence(32, 16)
+    P = param_matrix(systems)
+    order = oracle.greedy_sort(P)
+    ops, bs, xs = upload_systems(systems, "cuda:0", kind)
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, 30, 10, 1e-8, 20000)
+    _compare(systems, res, xs, ref, f"cfg1-{kind}")
+
+
+def test_gmres_k0(env):
+    torch, skr, ctx = env
+    log("[solve] GMRES(30) = GCRO-DR with k = 0")
+    systems = darcy_sequence(32, 3, first_seed=40)
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=30, k=0, rtol=1e-8, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], None, 30, 0, 1e-8, 20000)
+    _compare(systems, res, xs, ref, "gmres")
+    for g, r in zip(res, ref):
+        assert g["spmv"] == r.spmv
+
+
+def test_ragged_sizes_and_small_m(env):
+    """n = 37^2 (ragged last workgroup), m = 12, k = 5, tighter tolerance."""
+    torch, skr, ctx = env
+    log("[solve] ragged n=1369, GCRO-DR(12,5), rtol 1e-10")
+    systems = darcy_sequence(37, 5, first_seed=70)
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=12, k=5, rtol=1e-10, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], None, 12, 5, 1e-10, 20000)
+    for i, s in enumerate(systems):
+        x = xs[i].cpu().numpy()
+        bound, _ = solution_bound(s.A, s.b, ref[i].x, res[i]["relres_true"], ref[i].relres_true)
+        assert res[i]["relres_true"] <= 1e-10 * (1 + 1e-9)
+        assert np.linalg.norm(x - ref[i].x) / np.linalg.norm(ref[i].x) <= bound
+        assert abs(res[i]["iters"] - ref[i].iters) <= 1
+
+
+def test_edge_cases(env):
+    torch, skr, ctx = env
+    log("[solve] edge cases: b = 0, NaN in b, maxit = 1, identity (happy breakdown), N = 0")
+    s = darcy_sequence(16, 1, first_seed=5)[0]
+    n = s.n
+    systems = [s, s, s, s]
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    bs[1].zero_()
+    bs[2][5] = float("nan")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=5000)
+    assert rc == skr.SKR_OK
+    assert res[0]["status"] == skr.SKR_CONVERGED
+    assert res[1]["status"] == skr.SKR_CONVERGED and res[1]["iters"] == 0 and not xs[1].any()
+    assert res[2]["status"] == skr.SKR_NONFINITE and not xs[2].any()
+    assert res[3]["status"] == skr.SKR_CONVERGED          # recycles the space of system 0
+    # maxit = 1
+    ops1, bs1, xs1 = upload_systems([s], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops1, bs1, xs1, None, m=20, k=6, rtol=1e-8, maxit=1)
+    assert rc == skr.SKR_WARN_NOTCONVERGED and res[0]["status"] == skr.SKR_MAXIT and res[0]["iters"] == 1
+    r1 = oracle.gcrodr(s.A, s.b, None, 20, 6, 1e-8, 1)
+    assert abs(res[0]["relres_true"] - r1.relres_true) <= 1e-12
+    # identity matrix: the first Arnoldi step breaks down and x = b exactly
+    I = sp.identity(n, format="csr")
+    import types
+    ident = types.SimpleNamespace(A=I, b=s.b, n=n, N_g=s.N_g)
+    ops2, bs2, xs2 = upload_systems([ident], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops2, bs2, xs2, None, m=20, k=6, rtol=1e-8, maxit=100)
+    assert res[0]["status"] == skr.SKR_BREAKDOWN and res[0]["iters"] == 1
+    np.testing.assert_allclose(xs2[0].cpu().numpy(), s.b, rtol=1e-14)
+    # empty sequence
+    rc, res = skr.skr_solve_sequence(ctx, [], [], [], None, m=20, k=6, rtol=1e-8, maxit=100)
+    assert rc == skr.SKR_OK and res == []
+
+
+def test_invalid_arguments(env):
+    torch, skr, ctx = env
+    log("[api] invalid arguments are rejected")
+    s = darcy_sequence(8, 1)[0]
+    ops, bs, xs = upload_systems([s], "cuda:0")
+    for m, k, rtol in ((5, 5, 1e-8), (70, 10, 1e-8), (10, -1, 1e-8), (10, 2, 0.0)):
+        with pytest.raises(skr.SkrError):
+            skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=m, k=k, rtol=rtol, maxit=10)
+    with pytest.raises(skr.SkrError):
+        skr.skr_solve_sequence(ctx, ops, bs, xs, [1], m=10, k=2, rtol=1e-8, maxit=10)
+
+
+def test_solve_config2_prefix(env):
+    """256x256 Darcy (n = 65536), the first 2 systems of the sorted 400-system chain,
+    GCRO-DR(60,20), rel-res 1e-8, GPU against the oracle."""
+    torch, skr, ctx = env
+    log("[solve] config-2 prefix: 256x256, 2 systems of the sorted chain, GCRO-DR(60,20)")
+    systems = darcy_sequence(256, 400)
+    P = param_matrix(systems)
+    order, _ = _sort_gpu(torch, skr, ctx, P)
+    del P
+    pre = [systems[i] for i in order[:2]]
+    ops, bs, xs = upload_systems(pre, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=60, k=20, rtol=1e-8, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in pre], [s.b for s in pre], None, 60, 20, 1e-8, 20000)
+    _compare(pre, res, xs, ref, "cfg2-prefix")
