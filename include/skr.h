@@ -71,8 +71,11 @@ typedef struct {
     const double* ay;
 } skr_op;
 
-/* Solver options. m: maximum subspace size per cycle; k: recycled vectors (0 = GMRES(m));
- * rtol: relative residual target; maxit: maximum Arnoldi steps per system; flags: reserved, 0. */
+/* Solver options. m: maximum subspace size per cycle (1..62); k: recycled vectors (0 = GMRES(m),
+ * k < m, k <= 32); rtol: relative residual target; maxit: maximum Arnoldi steps per system;
+ * flags: 0 or SKR_FLAG_PROFILE. */
+#define SKR_FLAG_PROFILE 1u   /* time every 16th Arnoldi step's kernels with hipEvents (see skr_profile_get) */
+
 typedef struct {
     int32_t m;
     int32_t k;
@@ -141,6 +144,35 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
 
 /* y_dev = A x_dev for one operator (the sparse product of the Arnoldi step; Eq. 3). */
 int skr_spmv(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev);
+
+/* Launch the SpMV kernel `repeats` times back to back between two hipEvents on the context's stream
+ * and return the mean duration of one launch in *ms_per_launch (host pointer). Errors: SKR_EINVAL. */
+int skr_spmv_repeat(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev, int32_t repeats,
+                    double* ms_per_launch);
+
+/* Kernel statistics gathered by solves run with SKR_FLAG_PROFILE. Each Arnoldi step is three
+ * kernels: A (v_j = w / h, w = A v_j, first projection Q^T w), B (w -= Q h1, second projection
+ * Q^T w) and C (w -= Q h2, ||w||, Givens update), with Q = [C_k, V_j] (Eq. 6, CGS2). Sampled launches
+ * are timed with hipEvents on the context's stream; bytes are the algorithmic HBM bytes of those
+ * launches (matrix and basis columns read once, vectors read/written once). */
+typedef struct {
+    int64_t launches;   /* timed launches                                   */
+    double ms;          /* summed duration of the timed launches           */
+    double bytes;       /* summed algorithmic bytes of the timed launches  */
+} skr_kernel_stat;
+
+typedef struct {
+    skr_kernel_stat step_a, step_b, step_c;
+    int64_t steps;        /* Arnoldi steps run by profiled solves                 */
+    int64_t cycles;       /* Arnoldi cycles run by profiled solves                */
+    double step_bytes;    /* algorithmic bytes of all those steps (A + B + C)     */
+} skr_profile;
+
+/* Copy the statistics accumulated since the last reset into *out (host pointer). */
+int skr_profile_get(skr_ctx* ctx, skr_profile* out);
+
+/* Clear the accumulated statistics. */
+int skr_profile_reset(skr_ctx* ctx);
 
 #ifdef __cplusplus
 }

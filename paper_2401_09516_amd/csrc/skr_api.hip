@@ -18,11 +18,11 @@ void launch_init(hipStream_t, const Work&, const double*, double*, double);
 void launch_clear_nonfinite(hipStream_t, const Work&);
 void launch_check_finite(hipStream_t, const Work&, const double*, long);
 void launch_zero(hipStream_t, double*, int);
-void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int);
-void launch_close_basis(hipStream_t, const Work&);
+void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int, hipEvent_t* ev);
+void launch_close_basis(hipStream_t, const Work&, int, int);
 void launch_cycle_gram(hipStream_t, const Work&, int, int);
-void launch_cycle_dense(hipStream_t, const Work&, int, int);
-void launch_cycle_update(hipStream_t, const Work&, double*);
+void launch_cycle_dense(hipStream_t, const Work&, int, int, int);
+void launch_cycle_update(hipStream_t, const Work&, double*, int, int);
 void launch_true_residual(hipStream_t, const Work&, const DevOp&, const double*, const double*);
 void launch_spmm(hipStream_t, const Work&, const DevOp&, int);
 void launch_startup_gram(hipStream_t, const Work&, int);
@@ -30,12 +30,30 @@ void launch_chol(hipStream_t, const Work&, int, int);
 void launch_startup_apply(hipStream_t, const Work&, int, int);
 void launch_startup_project(hipStream_t, const Work&, double*);
 void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
+void launch_spmv_repeat(hipStream_t, const DevOp&, const double*, double*, int);
 void launch_sort(hipStream_t, const double*, long, long, long, double*, long long*, double*);
 long sort_nmax();
 }  // namespace skr
 
 using namespace skr;
 
+constexpr int PROF_PERIOD = 16;   // one Arnoldi step in PROF_PERIOD is timed
+constexpr int PROF_MAXSAMP = (MMAX + PROF_PERIOD - 1) / PROF_PERIOD + 1;
+
+// Algorithmic bytes of the three step kernels at step j with ncol = kc + j + 1 basis columns.
+static double op_bytes(const DevOp& op, int64_t nvals) {
+    const double n = op.n;
+    if (op.kind == SKR_OP_CSR) return 12.0 * (double)nvals + 4.0 * (n + 1) + 8.0 * n;
+    return 8.0 * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 8.0 * n;
+}
+static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double& a, double& b, double& c) {
+    const double n = op.n;
+    a = op_bytes(op, nvals) + 8.0 * n /* w */ + 8.0 * n /* v_j */ + 8.0 * n * (ncol - 1);
+    b = 8.0 * n * ncol + 16.0 * n;
+    c = 8.0 * n * ncol + 16.0 * n;
+}
+
+struct skr_ctx;
 struct skr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -48,6 +66,11 @@ struct skr_ctx {
     long long* order_d = nullptr;
     double* dist_d = nullptr;
     size_t sortN_cap = 0;
+    // profiling
+    hipEvent_t ev[PROF_MAXSAMP * 4] = {};
+    bool ev_ok = false;
+    int64_t step_counter = 0;
+    skr_profile prof = {};
 };
 
 static thread_local std::string g_err;
@@ -75,11 +98,13 @@ static int fail(int code, const char* fmt, ...) {
     } while (0)
 
 static void free_work(Work& w) {
-    double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part, w.part1, w.gpart, w.gram, w.red1, w.red2, w.H, w.Bm};
+    double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
+                      w.red1, w.red2, w.H, w.Bm};
     for (double* p : bufs)
         if (p) (void)hipFree(p);
     if (w.ctrl) (void)hipFree(w.ctrl);
     if (w.coef) (void)hipFree(w.coef);
+    if (w.dense) (void)hipFree(w.dense);
     if (w.counters) (void)hipFree(w.counters);
     w = Work();
 }
@@ -109,8 +134,10 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     chk(dalloc(&w.W[0], ld));
     chk(dalloc(&w.W[1], ld));
     chk(dalloc(&w.r, ld));
+    chk(dalloc(&w.part_a, (size_t)w.nblk * NC));
+    chk(dalloc(&w.part_b, (size_t)w.nblk * NC));
+    chk(dalloc(&w.part_n, (size_t)w.nblk));
     chk(dalloc(&w.part, (size_t)w.nblk * NC));
-    chk(dalloc(&w.part1, (size_t)w.nblk));
     chk(dalloc(&w.gpart, (size_t)w.ngblk * w.gram_max));
     chk(dalloc(&w.gram, w.gram_max));
     chk(dalloc(&w.red1, NC));
@@ -119,6 +146,7 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     chk(dalloc(&w.Bm, (size_t)KMAX * MMAX));
     chk(dalloc(&w.ctrl, 1));
     chk(dalloc(&w.coef, 1));
+    chk(dalloc(&w.dense, 1));
     chk(dalloc(&w.counters, 8));
     if (e != hipSuccess) {
         free_work(w);
@@ -133,6 +161,7 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     chk(hipMemsetAsync(w.Bm, 0, (size_t)KMAX * MMAX * sizeof(double), ctx->stream));
     chk(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), ctx->stream));
     chk(hipMemsetAsync(w.coef, 0, sizeof(Coef), ctx->stream));
+    chk(hipMemsetAsync(w.dense, 0, sizeof(DenseWork), ctx->stream));
     chk(hipMemsetAsync(w.counters, 0, 8 * sizeof(unsigned), ctx->stream));
     if (e != hipSuccess) return fail(SKR_EHIP, "workspace initialisation failed: %s", hipGetErrorString(e));
     return SKR_OK;
@@ -192,6 +221,9 @@ int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
         delete c;
         return fail(SKR_EHIP, "pinned host allocation failed");
     }
+    c->ev_ok = true;
+    for (int q = 0; q < PROF_MAXSAMP * 4; ++q)
+        if (hipEventCreate(&c->ev[q]) != hipSuccess) c->ev_ok = false;
     *out = c;
     g_err.clear();
     return SKR_OK;
@@ -207,6 +239,8 @@ int skr_ctx_destroy(skr_ctx* ctx) {
     if (ctx->dist_d) (void)hipFree(ctx->dist_d);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
     if (ctx->hkeff) (void)hipHostFree(ctx->hkeff);
+    for (int q = 0; q < PROF_MAXSAMP * 4; ++q)
+        if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
     delete ctx;
     return SKR_OK;
 }
@@ -221,6 +255,38 @@ int skr_spmv(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev)
     launch_spmv(ctx->stream, d, x_dev, y_dev);
     HIPLAUNCHCHK();
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+
+int skr_spmv_repeat(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev, int32_t repeats,
+                    double* ms_per_launch) {
+    if (!ctx || !op || !x_dev || !y_dev || !ms_per_launch || repeats < 1) return fail(SKR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    DevOp d;
+    int64_t nv;
+    int rc = to_devop(*op, d, nv);
+    if (rc) return rc;
+    if (!ctx->ev_ok) return fail(SKR_EHIP, "events unavailable");
+    HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
+    launch_spmv_repeat(ctx->stream, d, x_dev, y_dev, repeats);
+    HIPLAUNCHCHK();
+    HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    *ms_per_launch = (double)ms / repeats;
+    return SKR_OK;
+}
+
+int skr_profile_get(skr_ctx* ctx, skr_profile* out) {
+    if (!ctx || !out) return fail(SKR_EINVAL, "NULL argument");
+    *out = ctx->prof;
+    return SKR_OK;
+}
+
+int skr_profile_reset(skr_ctx* ctx) {
+    if (!ctx) return fail(SKR_EINVAL, "NULL argument");
+    std::memset(&ctx->prof, 0, sizeof ctx->prof);
     return SKR_OK;
 }
 
@@ -297,6 +363,8 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
     CtrlHost& hc = *ctx->hctrl;
     int kin = 0;   // recycled vectors carried from the previous system (held in w.U)
     bool any_maxit = false;
+    const bool profile = (opts->flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
+    int samp_j[PROF_MAXSAMP];
     for (int64_t q = 0; q < N; ++q) {
         const int64_t idx = order ? order[q] : q;
         DevOp op;
@@ -371,21 +439,52 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
             if (iters >= maxit) { status = SKR_MAXIT; break; }
             int scyc = (kc == 0) ? m : m - kc;
             scyc = (int)std::min<int64_t>(scyc, maxit - iters);
-            for (int j = 0; j < scyc; ++j) launch_step(s, w, op, kc, j, scyc);
-            launch_close_basis(s, w);
+            int nsamp = 0;
+            for (int j = 0; j < scyc; ++j) {
+                hipEvent_t* ev = nullptr;
+                if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
+                    ev = ctx->ev + 4 * nsamp;
+                    samp_j[nsamp++] = j;
+                }
+                launch_step(s, w, op, kc, j, scyc, ev);
+            }
+            launch_close_basis(s, w, kc, scyc);
             if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
-            launch_cycle_dense(s, w, scyc, k);
-            launch_cycle_update(s, w, x);
+            launch_cycle_dense(s, w, kc, scyc, k);
+            // the new recycle size is at most k (0 when no recycle space is formed this cycle)
+            const bool forms = k > 0 && (kc > 0 || scyc > k);
+            launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : (k + 7) / 8 * 8) : 0);
             HIPLAUNCHCHK();
             if ((rc = read_ctrl(ctx))) return rc;
             const int jd = hc.j_done;
             if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
+            if (profile) {
+                skr_profile& pr = ctx->prof;
+                for (int q = 0; q < nsamp; ++q) {
+                    if (samp_j[q] >= jd) continue;   // steps after the stop are skipped launches
+                    float t[3];
+                    for (int e = 0; e < 3; ++e)
+                        HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[4 * q + e], ctx->ev[4 * q + e + 1]));
+                    double ba, bb, bc;
+                    step_bytes(op, nvals, kc + samp_j[q] + 1, ba, bb, bc);
+                    pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;
+                    pr.step_b.launches++; pr.step_b.ms += t[1]; pr.step_b.bytes += bb;
+                    pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc;
+                }
+                for (int j = 0; j < jd; ++j) {
+                    double ba, bb, bc;
+                    step_bytes(op, nvals, kc + j + 1, ba, bb, bc);
+                    pr.step_bytes += ba + bb + bc;
+                }
+                pr.steps += jd;
+                pr.cycles += 1;
+            }
             iters += jd;
             spmv += jd;
             cycles += 1;
             est = hc.est;
-            kc = hc.kc;
-            if (!std::isfinite(est) || !std::isfinite(hc.beta)) {
+            kc = hc.k_new;
+            if (!std::isfinite(est)) {
                 launch_zero(s, x, n);
                 status = SKR_NONFINITE;
                 kc = 0;

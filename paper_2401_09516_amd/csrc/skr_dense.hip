@@ -1,4 +1,4 @@
-// Small dense FP64 work of a GCRO-DR cycle end and of the start-up QR, one wavefront each.
+// Small dense FP64 work of a GCRO-DR cycle end and of the start-up QR.
 //
 // Cycle end (Alg. 2, cycle body): with kc recycled columns and jd Arnoldi steps, d = kc + jd,
 //   G = [[D_k, B], [0, Hbar]]             ((d+1) x d),   W-hat = [C, V_{jd+1}],  V-hat = [U D_k, V_jd]
@@ -30,6 +30,26 @@ __device__ __forceinline__ double wave_max64(double x) {
     return x;
 }
 
+// Copy a rows x cols column-major block from global (leading dimension lds) to LDS (leading
+// dimension ldd) with nthr threads, eight loads in flight per thread.
+__device__ __forceinline__ void stage_block(double* dst, int ldd, const double* src, int lds, int rows, int cols,
+                                            int t, int nthr) {
+    const int total = rows * cols;
+    for (int e0 = 0; e0 < total; e0 += 8 * nthr) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * nthr + t;
+            v[u] = (e < total) ? src[(e % rows) + (e / rows) * lds] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * nthr + t;
+            if (e < total) dst[(e % rows) + (e / rows) * ldd] = v[u];
+        }
+    }
+}
+
 // Householder reflector P = I - tau v v^T, v = (1, v1, v2), with P (x, y, z)^T = (alpha, 0, 0)^T.
 __device__ __forceinline__ void house3(double x, double y, double z, double& v1, double& v2, double& tau,
                                        double& alpha) {
@@ -59,41 +79,78 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
     }
 }
 
-__global__ __launch_bounds__(64) void k_cycle_dense(const double* __restrict__ H, const double* __restrict__ Bm,
-                                                    const double* __restrict__ gram, int jd_max, int k_target,
-                                                    Coef* coef, Ctrl* ctrl) {
+// Stage 1 of a cycle end (one wavefront): G, X = W-hat^T V-hat, Givens QR of G, least-squares
+// solution and the coefficients of the x and r updates. When a recycle space is to be formed, R_G,
+// the top d rows of Q_G^T X, the rotations and D_k are handed to the eigen stage through dw.
+__global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H, const double* __restrict__ Bm,
+                                                   const double* __restrict__ gram, int kc, int jd_max, int k_target,
+                                                   Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     __shared__ double G[LDG * DMAX];
     __shared__ double X[LDG * DMAX];
-    __shared__ double Z[DMAX * DMAX];
-    __shared__ double Wv[LDW * KMAX];
-    __shared__ double Uq[LDW * KMAX];
-    __shared__ double rhs[DMAX + 1], gcs[DMAX], gsn[DMAX], Dk[KMAX], wr[DMAX], wi[DMAX], hv[DMAX + 1];
-    __shared__ int taken[DMAX], sel_pos[KMAX], sel_cplx[KMAX], sel_col[KMAX];
+    __shared__ double rhs[DMAX + 1], gcs[DMAX], gsn[DMAX], Dk[KMAX], hv[DMAX + 1];
     const int t = threadIdx.x;
-    const int kc = ctrl->kc, jd = ctrl->j_done;
+    const int jd = ctrl->j_done;
     const double beta = ctrl->beta;
     const int d = kc + jd;
     const int nr = kc + 1;
-    const double eps = 2.220446049250313e-16;
 
-    // ---- D_k, G, X = W-hat^T V-hat (structured), right-hand side W-hat^T r
+    // ---- D_k, G, X = W-hat^T V-hat (structured), right-hand side W-hat^T r. Global inputs are
+    //      staged with eight loads in flight per lane.
     if (t < kc) Dk[t] = 1.0 / sqrt(gram[(kc + jd_max + 1 + t) * nr + t]);
-    __syncthreads();
-    for (int c = 0; c < d; ++c) {
+    for (int c = 0; c < d; ++c)
         if (t <= d) {
-            double gv = 0.0, xv = 0.0;
-            if (c < kc) {
-                gv = (t == c) ? Dk[c] : 0.0;
-                xv = gram[t * nr + c] * Dk[c];             // rows of C: C^T U D_k, rows of V: V^T U D_k
-            } else {
-                const int tt = c - kc;
-                if (t < kc) gv = Bm[t + tt * KMAX];
-                else if (t - kc <= tt + 1) gv = H[(t - kc) + tt * LDH];
-                xv = (t - kc == tt) ? 1.0 : 0.0;          // V_{jd+1}^T V_jd = I_{jd+1,jd}, C^T V = 0
-            }
-            G[t + c * LDG] = gv;
-            X[t + c * LDG] = xv;
+            G[t + c * LDG] = 0.0;
+            X[t + c * LDG] = (c >= kc && t == c) ? 1.0 : 0.0;   // V_{jd+1}^T V_jd = I_{jd+1,jd}, C^T V = 0
         }
+    __syncthreads();
+    {
+        // Hbar (rows 0..jd, columns 0..jd-1, Hessenberg) -> G[kc + r][kc + c]
+        const int nh = (jd + 1) * jd;
+        for (int e0 = 0; e0 < nh; e0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / (jd + 1), r = e - c * (jd + 1);
+                v[u] = (e < nh && r <= c + 1) ? H[r + c * LDH] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / (jd + 1), r = e - c * (jd + 1);
+                if (e < nh) G[kc + r + (kc + c) * LDG] = v[u];
+            }
+        }
+        // B (kc x jd) -> G[r][kc + c]
+        const int nbm = kc * jd;
+        for (int e0 = 0; e0 < nbm; e0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / max(kc, 1), r = e - c * kc;
+                v[u] = (e < nbm) ? Bm[r + c * KMAX] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / max(kc, 1), r = e - c * kc;
+                if (e < nbm) G[r + (kc + c) * LDG] = v[u];
+            }
+        }
+        __syncthreads();
+        // [C V]^T U (rows 0..d, columns 0..kc-1) -> X[r][c] D_c;  D_k -> G[c][c]
+        const int ng = (d + 1) * kc;
+        for (int e0 = 0; e0 < ng; e0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / (d + 1), r = e - c * (d + 1);
+                v[u] = (e < ng) ? gram[r * nr + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 64 + t, c = e / (d + 1), r = e - c * (d + 1);
+                if (e < ng) X[r + c * LDG] = v[u] * Dk[c];
+            }
+        }
+        if (t < kc) G[t + t * LDG] = Dk[t];
     }
     if (t <= d) rhs[t] = (t < kc) ? gram[t * nr + kc] : (t == kc ? beta : 0.0);
     __syncthreads();
@@ -150,18 +207,248 @@ __global__ __launch_bounds__(64) void k_cycle_dense(const double* __restrict__ H
 
     const bool recycle = k_target > 0 && (kc > 0 || jd > k_target);
     if (!recycle) {
-        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; }
+        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; dw->mode = DW_NONE; }
         return;
     }
+    // hand over R_G (d x d, upper), X'' (d x d), rotations and D_k
+    for (int c = 0; c < d; ++c)
+        if (t < d) {
+            dw->R[t + c * DMAX] = (t <= c) ? G[t + c * LDG] : 0.0;
+            dw->X[t + c * DMAX] = X[t + c * LDG];
+        }
+    if (t < d) { dw->gcs[t] = gcs[t]; dw->gsn[t] = gsn[t]; }
+    if (t < kc) dw->Dk[t] = Dk[t];
+    if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_PENDING; }
+}
 
-    // ---- M = X'' R_G^{-1} (row t of M by forward substitution along the row), kept in X
-    if (t < d) {
-        for (int c = 0; c < d; ++c) {
-            double s = X[t + c * LDG];
-            for (int q = 0; q < c; ++q) s = fma(-X[t + q * LDG], G[q + c * LDG], s);
-            X[t + c * LDG] = s / G[c + c * LDG];
+// Stage 2, symmetric case (4 wavefronts). M = X'' R_G^{-1} is formed; for symmetric A it is
+// symmetric in exact arithmetic (G^T G and G^T W-hat^T V-hat = V-hat^T A V-hat are), and when the
+// computed M is symmetric to 1e-10 relative, the eigenpairs of (M + M^T)/2 are found by the cyclic
+// Jacobi method (round-robin ordering: each round rotates d/2 disjoint pairs in parallel). Its
+// eigenvectors are orthonormal, so the selected ones form Q_w directly. Otherwise M is handed to
+// the general stage.
+constexpr int DT = 256;         // threads of the symmetric stage
+constexpr int LDS_ = DMAX + 1;  // leading dimension of S and V in LDS
+
+__global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    if (dw->mode != DW_PENDING) return;
+    __shared__ double S[LDS_ * DMAX];
+    __shared__ double V[LDS_ * DMAX];
+    __shared__ double R[LDS_ * DMAX];
+    __shared__ double Wq[LDS_ * KMAX];
+    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX];
+    __shared__ double red[DT / 64], red2[DT / 64];
+    __shared__ double jc[DMAX / 2], js[DMAX / 2];
+    __shared__ int jp[DMAX / 2], jq[DMAX / 2];
+    __shared__ int sel[KMAX];
+    __shared__ int nsel_s, sym_s;
+    const int t = threadIdx.x;
+    const int d = dw->d, kc = dw->kc;
+    const int dp = d + (d & 1);                 // even size (a zero row/column pads an odd d)
+    // load R_G, X'', the rotations of Q_G and D_k
+    stage_block(R, LDS_, dw->R, DMAX, d, d, t, DT);
+    stage_block(S, LDS_, dw->X, DMAX, d, d, t, DT);
+    if (t < d) { gcs[t] = dw->gcs[t]; gsn[t] = dw->gsn[t]; }
+    if (t < kc) Dk[t] = dw->Dk[t];
+    __syncthreads();
+    // M = X'' R^{-1}: column c of M = (X''_c - sum_{q<c} M_q R_qc) / R_cc, right-looking over c
+    for (int c = 0; c < d; ++c) {
+        const double inv = 1.0 / R[c + c * LDS_];
+        for (int r = t; r < d; r += DT) S[r + c * LDS_] *= inv;
+        __syncthreads();
+        for (int e = t; e < d * (d - c - 1); e += DT) {
+            const int r = e % d, c2 = c + 1 + e / d;
+            S[r + c2 * LDS_] = fma(-S[r + c * LDS_], R[c + c2 * LDS_], S[r + c2 * LDS_]);
+        }
+        __syncthreads();
+    }
+    // symmetry test: max |M - M^T| <= 1e-10 max |M|
+    double amax = 0.0, dmax = 0.0;
+    for (int e = t; e < d * d; e += DT) {
+        const int r = e % d, c = e / d;
+        const double a = S[r + c * LDS_];
+        amax = fmax(amax, fabs(a));
+        dmax = fmax(dmax, fabs(a - S[c + r * LDS_]));
+    }
+    amax = wave_max64(amax);
+    dmax = wave_max64(dmax);
+    if ((t & 63) == 0) { red[t >> 6] = amax; red2[t >> 6] = dmax; }
+    __syncthreads();
+    if (t == 0) {
+        double ga = red[0], gd = red2[0];
+        for (int q = 1; q < DT / 64; ++q) { ga = fmax(ga, red[q]); gd = fmax(gd, red2[q]); }
+        sym_s = (gd <= 1e-10 * ga) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sym_s) {
+        for (int e = t; e < d * d; e += DT) {
+            const int r = e % d, c = e / d;
+            dw->X[r + c * DMAX] = S[r + c * LDS_];
+        }
+        if (t == 0) dw->mode = DW_GEN;
+        return;
+    }
+    // S = (M + M^T) / 2 in place (each unordered pair by one thread), padded to dp; V = I
+    for (int e = t; e < dp * dp; e += DT) {
+        const int r = e % dp, c = e / dp;
+        V[r + c * LDS_] = (r == c) ? 1.0 : 0.0;
+        if (r < c) {
+            const double v = (c < d) ? 0.5 * (S[r + c * LDS_] + S[c + r * LDS_]) : 0.0;
+            S[r + c * LDS_] = v;
+            S[c + r * LDS_] = v;
+        } else if (r == c && c >= d) {
+            S[r + c * LDS_] = 0.0;
         }
     }
+    __syncthreads();
+    // cyclic Jacobi sweeps until off(S) <= 1e-13 ||diag(S)|| (a rotation is skipped when
+    // |S_pq| <= 1e-16 sqrt(|S_pp S_qq|)). Thread t works on pair t >> 3 and every 8th row/column
+    // starting at t & 7.
+    const int np = dp / 2;
+    const int my_pair = t >> 3, my_g = t & 7;
+    for (int sweep = 0; sweep < 20; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int c = my_pair; c < dp; c += DT / 8)
+            for (int r = my_g; r < dp; r += 8) {
+                const double a = S[r + c * LDS_];
+                if (r != c) off = fma(a, a, off);
+                else dia = fma(a, a, dia);
+            }
+        off = wave_sum64(off);
+        dia = wave_sum64(dia);
+        if ((t & 63) == 0) { red[t >> 6] = off; red2[t >> 6] = dia; }
+        __syncthreads();
+        double offt = 0.0, diat = 0.0;
+        for (int q = 0; q < DT / 64; ++q) { offt += red[q]; diat += red2[q]; }
+        __syncthreads();
+        if (!(offt > 1e-26 * diat)) break;
+        for (int round = 0; round < dp - 1; ++round) {
+            if (t < np) {
+                // circle method: position 0 fixed, the others rotate
+                const int a = t, b = dp - 1 - t;
+                const int pa = (a == 0) ? 0 : 1 + (a - 1 + round) % (dp - 1);
+                const int pb = (b == 0) ? 0 : 1 + (b - 1 + round) % (dp - 1);
+                const int p = min(pa, pb), q = max(pa, pb);
+                const double spq = S[p + q * LDS_], spp = S[p + p * LDS_], sqq = S[q + q * LDS_];
+                double c = 1.0, s = 0.0;
+                if (fabs(spq) > 1e-16 * sqrt(fabs(spp * sqq))) {
+                    const double tau = (sqq - spp) / (2.0 * spq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                jp[t] = p; jq[t] = q; jc[t] = c; js[t] = s;
+            }
+            __syncthreads();
+            if (my_pair < np && js[my_pair] != 0.0) {
+                const int p = jp[my_pair], q = jq[my_pair];
+                const double c = jc[my_pair], s = js[my_pair];
+                // rows: S <- J^T S
+                for (int col = my_g; col < dp; col += 8) {
+                    const double sp = S[p + col * LDS_], sq = S[q + col * LDS_];
+                    S[p + col * LDS_] = c * sp - s * sq;
+                    S[q + col * LDS_] = s * sp + c * sq;
+                }
+            }
+            __syncthreads();
+            if (my_pair < np && js[my_pair] != 0.0) {
+                const int p = jp[my_pair], q = jq[my_pair];
+                const double c = jc[my_pair], s = js[my_pair];
+                // columns: S <- S J, V <- V J
+                for (int row = my_g; row < dp; row += 8) {
+                    const double sp = S[row + p * LDS_], sq = S[row + q * LDS_];
+                    S[row + p * LDS_] = c * sp - s * sq;
+                    S[row + q * LDS_] = s * sp + c * sq;
+                    const double vp = V[row + p * LDS_], vq = V[row + q * LDS_];
+                    V[row + p * LDS_] = c * vp - s * vq;
+                    V[row + q * LDS_] = s * vp + c * vq;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // select the k_target eigenvalues of largest |mu| (smallest |theta| = 1/|mu|), ties by index
+    if (t < 64) {
+        int ns = 0;
+        unsigned long long used = 0ull;
+        for (int it = 0; it < k_target; ++it) {
+            double key = -1.0;
+            int idx = t;
+            if (t < d && !((used >> t) & 1ull)) {
+                const double mag = fabs(S[t + t * LDS_]);
+                if (mag > 0.0) key = mag;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ok = __shfl_xor(key, off, 64);
+                const int oi = __shfl_xor(idx, off, 64);
+                if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+            }
+            if (key <= 0.0) break;
+            used |= 1ull << idx;
+            if (t == 0) sel[ns] = idx;
+            ++ns;
+        }
+        if (t == 0) nsel_s = ns;
+    }
+    __syncthreads();
+    const int kn = nsel_s;
+    // Qu = R_G^{-1} Q_w with Q_w = V[:, sel]: back-substitution, parallel over (row, column)
+    for (int e = t; e < d * kn; e += DT) {
+        const int r = e % d, o = e / d;
+        Wq[r + o * LDS_] = V[r + sel[o] * LDS_];
+    }
+    __syncthreads();
+    for (int c = d - 1; c >= 0; --c) {
+        const double rcc = R[c + c * LDS_];
+        for (int o = t; o < kn; o += DT) Wq[c + o * LDS_] /= rcc;
+        __syncthreads();
+        for (int e = t; e < c * kn; e += DT) {
+            const int r = e % c, o = e / c;
+            Wq[r + o * LDS_] = fma(-R[r + c * LDS_], Wq[c + o * LDS_], Wq[r + o * LDS_]);
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < d * kn; e += DT) {
+        const int r = e % d, o = e / d;
+        coef->Qu[r + o * LDQU] = (r < kc ? Dk[r] : 1.0) * Wq[r + o * LDS_];
+    }
+    // Qc = Q_G [Q_w; 0] (one thread per column, rotations in reverse order)
+    if (t < kn) {
+        const int o = t, col = sel[o];
+        double carry = 0.0;
+        for (int c = d - 1; c >= kc; --c) {
+            const double a = V[c + col * LDS_];
+            coef->Qc[c + 1 + o * LDQC] = gsn[c] * a + gcs[c] * carry;
+            carry = gcs[c] * a - gsn[c] * carry;
+        }
+        coef->Qc[kc + o * LDQC] = carry;
+        for (int c = 0; c < kc; ++c) coef->Qc[c + o * LDQC] = V[c + col * LDS_];
+    }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+}
+
+// Stage 2, general (nonsymmetric) case, one wavefront: M = X'' R_G^{-1} was formed by the
+// symmetric stage, which found it nonsymmetric. Householder reduction to Hessenberg form, Francis
+// double-shift QR, eigenvectors of the selected eigenvalues by back-substitution, an orthonormal
+// basis Q_w of them, and the recycle-space coefficients Qu = R_G^{-1} Q_w, Qc = Q_G [Q_w; 0].
+__global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    if (dw->mode != DW_GEN) return;
+    __shared__ double G[LDG * DMAX];
+    __shared__ double X[LDG * DMAX];
+    __shared__ double Z[DMAX * DMAX];
+    __shared__ double Wv[LDW * KMAX];
+    __shared__ double Uq[LDW * KMAX];
+    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX], wr[DMAX], wi[DMAX], hv[DMAX + 1];
+    __shared__ int taken[DMAX], sel_pos[KMAX], sel_cplx[KMAX], sel_col[KMAX];
+    const int t = threadIdx.x;
+    const int d = dw->d, kc = dw->kc;
+    const double eps = 2.220446049250313e-16;
+    stage_block(G, LDG, dw->R, DMAX, d, d, t, 64);
+    stage_block(X, LDG, dw->X, DMAX, d, d, t, 64);
+    if (t < d) { gcs[t] = dw->gcs[t]; gsn[t] = dw->gsn[t]; }
+    if (t < kc) Dk[t] = dw->Dk[t];
+    __syncthreads();
     // Z = I
     for (int c = 0; c < d; ++c)
         if (t < d) Z[t + c * DMAX] = (t == c) ? 1.0 : 0.0;
@@ -381,7 +668,7 @@ __global__ __launch_bounds__(64) void k_cycle_dense(const double* __restrict__ H
                 coef->Qc[r + o * LDQC] = (r == o) ? 1.0 : 0.0;
                 if (r < d) coef->Qu[r + o * LDQU] = (r == o) ? 1.0 : 0.0;
             }
-        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; }
+        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; dw->mode = DW_DONE; }
         return;
     }
 
@@ -546,7 +833,7 @@ __global__ __launch_bounds__(64) void k_cycle_dense(const double* __restrict__ H
         if (kc < d || d == 0) coef->Qc[kc + t * LDQC] = carry;
         for (int c = 0; c < kc; ++c) coef->Qc[c + t * LDQC] = Wv[c + t * LDW];
     }
-    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -598,9 +885,13 @@ __global__ __launch_bounds__(64) void k_chol(const double* __restrict__ gram, in
     }
 }
 
-void launch_cycle_dense(hipStream_t s, const Work& w, int jd_max, int k_target) {
-    hipLaunchKernelGGL(k_cycle_dense, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
-                       (const double*)w.gram, jd_max, k_target, w.coef, w.ctrl);
+void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_target) {
+    hipLaunchKernelGGL(k_dense_prep, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
+                       (const double*)w.gram, kc, jd_max, k_target, w.coef, w.dense, w.ctrl);
+    if (k_target > 0) {
+        hipLaunchKernelGGL(k_dense_sym, dim3(1), dim3(DT), 0, s, k_target, w.coef, w.dense, w.ctrl);
+        hipLaunchKernelGGL(k_dense_gen, dim3(1), dim3(64), 0, s, k_target, w.coef, w.dense, w.ctrl);
+    }
 }
 void launch_chol(hipStream_t s, const Work& w, int kin, int with_drop) {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(64), 0, s, (const double*)w.gram, kin, with_drop, w.coef);

@@ -101,6 +101,15 @@ struct Coef {
     int k_eff;
     int pad;
 };
+// Hand-over from the first cycle-end stage to the eigen stages (device).
+enum { DW_NONE = 0, DW_PENDING = 1, DW_GEN = 2, DW_DONE = 3 };
+struct DenseWork {
+    int mode, d, kc, pad;
+    double Dk[KMAX];
+    double gcs[DMAX], gsn[DMAX];
+    double R[DMAX * DMAX];    // R_G (upper triangular), column-major, ld DMAX
+    double X[DMAX * DMAX];    // top d rows of Q_G^T X, then M = X'' R_G^{-1} for the general stage
+};
 constexpr int LDQC = KMAX + MMAX + 2;
 constexpr int LDQU = KMAX + MMAX + 1;
 
@@ -110,11 +119,12 @@ constexpr int LDQU = KMAX + MMAX + 1;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
-// Butterfly reduce-scatter over one wavefront: on return lane l holds the wave-wide sum of
-// column l (v[0]). The order of additions is fixed, so results are bitwise reproducible. Each
-// stage is a separate template instance so that every register index is a compile-time constant.
-template <int HALF>
-__device__ __forceinline__ void rs_stage(double (&v)[NC], int lane) {
+// Butterfly reduce-scatter over one wavefront of NR (a power of two <= 64) column values per lane:
+// on return lane l holds the wave-wide sum of column (l mod NR) in v[0]. Offsets >= NR are plain
+// all-reduce stages; the remaining stages halve the columns each lane keeps. The order of additions
+// is fixed, so results are bitwise reproducible. Every register index is a compile-time constant.
+template <int HALF, int NR>
+__device__ __forceinline__ void rs_stage(double (&v)[NR], int lane) {
     const bool upper = (lane & HALF) != 0;
 #pragma unroll
     for (int i = 0; i < HALF; ++i) {
@@ -124,16 +134,24 @@ __device__ __forceinline__ void rs_stage(double (&v)[NC], int lane) {
     }
 }
 
-__device__ __forceinline__ double wave_reduce_scatter64(double (&v)[NC]) {
+template <int NR>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NR]) {
     const int lane = lane_id();
-    rs_stage<32>(v, lane);
-    rs_stage<16>(v, lane);
-    rs_stage<8>(v, lane);
-    rs_stage<4>(v, lane);
-    rs_stage<2>(v, lane);
-    rs_stage<1>(v, lane);
+#pragma unroll
+    for (int off = 32; off >= NR; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] += __shfl_xor(v[i], off, 64);
+    }
+    if constexpr (NR >= 64) rs_stage<32, NR>(v, lane);
+    if constexpr (NR >= 32) rs_stage<16, NR>(v, lane);
+    if constexpr (NR >= 16) rs_stage<8, NR>(v, lane);
+    if constexpr (NR >= 8) rs_stage<4, NR>(v, lane);
+    if constexpr (NR >= 4) rs_stage<2, NR>(v, lane);
+    if constexpr (NR >= 2) rs_stage<1, NR>(v, lane);
     return v[0];
 }
+
+__device__ __forceinline__ double wave_reduce_scatter64(double (&v)[NC]) { return wave_reduce_scatter<NC>(v); }
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -158,18 +176,29 @@ __device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nb
     return is_last != 0;
 }
 
-// Column sums over the per-workgroup partials part[b * NC + c] (b < nblk), fixed order:
-// each wave sums a contiguous range of workgroups, then the waves are added in order.
-// Must be called by all ROWS threads of the last workgroup; result in out[0..NC).
-__device__ __forceinline__ void final_reduce64(const double* part, int nblk, double* sh, double* out) {
+// Column sums over the per-workgroup partials part[b * NC + c] (b < nblk, c < nr <= NC), fixed
+// order: each wave sums a contiguous range of workgroups (loads issued 16 at a time so that their
+// latencies overlap), then the waves are added in order. Called by all ROWS threads of the last
+// workgroup; result in out[0..nr).
+__device__ __forceinline__ void final_reduce(const double* part, int nblk, int nr, double* sh, double* out) {
     const int lane = lane_id(), w = wave_id();
     const int per = (nblk + NWAVE - 1) / NWAVE;
     const int b0 = w * per, b1 = min(nblk, b0 + per);
     double s = 0.0;
-    for (int b = b0; b < b1; ++b) s += __builtin_nontemporal_load(&part[b * NC + lane]);
+    if (lane < nr) {
+        int b = b0;
+        for (; b + 16 <= b1; b += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(&part[(b + u) * NC + lane]);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += v[u];
+        }
+        for (; b < b1; ++b) s += __builtin_nontemporal_load(&part[b * NC + lane]);
+    }
     sh[w * NC + lane] = s;
     __syncthreads();
-    if (threadIdx.x < NC) {
+    if (threadIdx.x < nr) {
         double t = sh[lane];
 #pragma unroll
         for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + lane];
@@ -178,10 +207,19 @@ __device__ __forceinline__ void final_reduce64(const double* part, int nblk, dou
     __syncthreads();
 }
 
-// Sum of one value per thread over the grid: partial per workgroup, fixed-order final sum in the
-// last workgroup. Returns true in the last workgroup, where *result holds the total.
-__device__ __forceinline__ bool grid_sum1(double v, double* part, unsigned* counter, int nblk, int lb,
-                                          double* sh, double* result) {
+__device__ __forceinline__ void final_reduce64(const double* part, int nblk, double* sh, double* out) {
+    final_reduce(part, nblk, NC, sh, out);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fence-free grid reductions. A kernel writes one partial per workgroup; every workgroup of the
+// next kernel (launched on the same stream, so the partials are visible) sums all partials itself
+// in the same fixed order, so all workgroups hold bitwise identical totals. This avoids device-scope
+// fences and atomics, which cost far more than a kernel boundary on a multi-XCD GPU.
+// ---------------------------------------------------------------------------------------------
+
+// Per-workgroup sum of one value per thread into part[lb] (fixed order).
+__device__ __forceinline__ void block_partial1(double v, double* part, int lb, double* sh) {
     const double ws = wave_sum(v);
     if (lane_id() == 0) sh[wave_id()] = ws;
     __syncthreads();
@@ -192,17 +230,64 @@ __device__ __forceinline__ bool grid_sum1(double v, double* part, unsigned* coun
         part[lb] = t;
     }
     __syncthreads();
-    if (!last_block_arrive(counter, (unsigned)nblk)) return false;
-    // fixed order: each lane sums a strided subset, then a fixed butterfly over the wave
+}
+
+// Sum of part[0..nblk) in a fixed order (lane-strided, four loads in flight per lane, then a
+// wave butterfly). Called by all threads of a workgroup; every thread gets the total.
+__device__ __forceinline__ double sum_partials1(const double* part, int nblk, double* sh) {
     if (threadIdx.x < 64) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 64) s += __builtin_nontemporal_load(&part[b]);
+        int b = threadIdx.x;
+        for (; b + 192 < nblk; b += 256) {
+            const double v0 = part[b], v1 = part[b + 64], v2 = part[b + 128], v3 = part[b + 192];
+            s += v0; s += v1; s += v2; s += v3;
+        }
+        for (; b < nblk; b += 64) s += part[b];
         s = wave_sum(s);
         if (threadIdx.x == 0) sh[0] = s;
     }
     __syncthreads();
-    *result = sh[0];
+    const double r = sh[0];
     __syncthreads();
+    return r;
+}
+
+// Column sums of part[b * NC + c] (b < nblk, c < nr) into out[0..nr) (LDS), fixed order: each wave
+// sums a contiguous quarter of the workgroups (up to 64 loads in flight per lane), then the quarters
+// are added in order. Called by all threads of a workgroup.
+__device__ __forceinline__ void sum_partials(const double* part, int nblk, int nr, double* sh, double* out) {
+    const int lane = lane_id(), w = wave_id();
+    const int per = (nblk + NWAVE - 1) / NWAVE;
+    const int b0 = w * per, b1 = min(nblk, b0 + per);
+    double s = 0.0;
+    if (lane < nr) {
+        for (int b = b0; b < b1; b += 64) {
+            double v[64];
+#pragma unroll
+            for (int u = 0; u < 64; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + lane] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 64; ++u) s += v[u];
+        }
+    }
+    sh[w * NC + lane] = s;
+    __syncthreads();
+    if (threadIdx.x < nr) {
+        double t = sh[lane];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + lane];
+        out[lane] = t;
+    }
+    __syncthreads();
+}
+
+// Sum of one value per thread over the grid, for kernels that run once per system: the partial of
+// each workgroup goes to part[lb] (so a following kernel may re-sum it with sum_partials1) and the
+// last workgroup to arrive forms the total in the same order. Returns true in that workgroup.
+__device__ __forceinline__ bool grid_sum1(double v, double* part, unsigned* counter, int nblk, int lb,
+                                          double* sh, double* result) {
+    block_partial1(v, part, lb, sh);
+    if (!last_block_arrive(counter, (unsigned)nblk)) return false;
+    *result = sum_partials1(part, nblk, sh);
     return true;
 }
 
@@ -224,8 +309,10 @@ struct Work {
     double* U = nullptr;         // k cols
     double* W[2] = {nullptr, nullptr};
     double* r = nullptr;
-    double* part = nullptr;      // nblk * NC partials
-    double* part1 = nullptr;     // nblk scalar partials
+    double* part_a = nullptr;    // nblk * NC partials written by step pass A (read by pass B)
+    double* part_b = nullptr;    // nblk * NC partials written by step pass B (read by pass C)
+    double* part_n = nullptr;    // nblk scalar partials of a squared norm (read by the next kernel)
+    double* part = nullptr;      // nblk * NC partials of the start-up projection
     double* gpart = nullptr;     // Gram partials: ngblk * gram_max
     double* gram = nullptr;      // reduced Gram result
     double* red1 = nullptr;      // NC
@@ -234,6 +321,7 @@ struct Work {
     double* Bm = nullptr;        // KMAX x MMAX
     Ctrl* ctrl = nullptr;
     Coef* coef = nullptr;
+    DenseWork* dense = nullptr;
     unsigned* counters = nullptr;  // 8 counters
     size_t gram_max = 0;
     int ngblk = 0;

@@ -73,163 +73,263 @@ __global__ __launch_bounds__(ROWS) void k_zero(double* __restrict__ x, int n) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Arnoldi step, pass A
+// Arnoldi step kernels. NL (a multiple of 8, >= the columns used) is the number of basis loads per
+// row, fixed at compile time so that all loads of a row are unconditional and in flight together:
+// columns past the last one used re-read the last column (same address, a cache hit) and get a zero
+// coefficient. Rows past n re-read row n-1 and contribute zero. NR is the reduction width.
 // ---------------------------------------------------------------------------------------------
+template <int NL>
+struct Width {
+    static constexpr int NR = NL <= 16 ? 16 : (NL <= 32 ? 32 : 64);
+};
+
+__device__ __forceinline__ size_t qoff(int c, int kc, int vbase, int ld) {
+    return (size_t)(c < kc ? c : vbase + c - kc) * (size_t)ld;
+}
+
+// Block-combine NR column values (one reduce-scattered value per lane) into the per-workgroup
+// partial part[lb * NC + c], c < NR.
+template <int NR>
+__device__ __forceinline__ void block_partials(double s, double* sh, double* part, int lb) {
+    if (lane_id() < NR) sh[wave_id() * NR + lane_id()] = s;
+    __syncthreads();
+    if (threadIdx.x < NR) {
+        double t = sh[threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q) t += sh[q * NR + threadIdx.x];
+        part[lb * NC + threadIdx.x] = t;
+    }
+}
+
+// Close step jj of the current cycle once tot = ||w||^2 is known (Eq. 6): column jj of B (rows of
+// C) and of Hbar (rows of V) are the sums of the two CGS passes h1 + h2, h_{jj+1,jj} = ||w|| (zero
+// at a happy breakdown, h <= 1e-14 ||A v_jj||), and the progressive Givens QR of Hbar gives the
+// least-squares residual estimate |g_{jj+1}|. Run by wave 0 of every calling workgroup on identical
+// inputs, so all get identical results; only the writer workgroup stores the column, the new
+// rotation and g_{jj+1}. Only the running entry of the rotated column is needed: after rotation q
+// it is a_{q+1} = -sn_q a_q + cs_q col[q+1], with lane q holding (cs_q, sn_q, col[q+1]).
+__device__ __forceinline__ double close_step(int jj, int kc, double tot, const double* __restrict__ h1,
+                                             const double* __restrict__ h2, double* H, double* Bm, Ctrl* ctrl,
+                                             bool writer, int& brk_out, double& hnorm_out) {
+    const int t = threadIdx.x;
+    const int ncol = kc + jj + 1;
+    const double hnorm = sqrt(tot);
+    const double anorm = sqrt(h1[ncol]);
+    const int brk = (hnorm <= 1e-14 * anorm) ? 1 : 0;
+    const double hlast = brk ? 0.0 : hnorm;
+    double colt = 0.0;
+    if (t <= jj) colt = h1[kc + t] + h2[kc + t];
+    if (writer) {
+        if (t < kc) Bm[t + jj * KMAX] = h1[t] + h2[t];
+        if (t <= jj) H[t + jj * LDH] = colt;
+        if (t == 0) H[jj + 1 + jj * LDH] = hlast;
+    }
+    const double up = __shfl(colt, (t + 1) & 63, 64);
+    const double cnext = (t < jj) ? up : (t == jj ? hlast : 0.0);
+    const double cs_t = (t < jj) ? ctrl->cs[t] : 0.0;
+    const double sn_t = (t < jj) ? ctrl->sn[t] : 0.0;
+    double a = __shfl(colt, 0, 64);
+    for (int q = 0; q < jj; ++q) {
+        const double mq = __shfl(sn_t, q, 64), cq = __shfl(cs_t, q, 64), bq = __shfl(cnext, q, 64);
+        a = fma(-mq, a, cq * bq);
+    }
+    const double rho = hypot(a, hlast);
+    const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? hlast / rho : 0.0;
+    const double gj = ctrl->g[jj];
+    const double est = fabs(sn * gj);
+    if (writer && t == 0) {
+        ctrl->cs[jj] = cs;
+        ctrl->sn[jj] = sn;
+        ctrl->g[jj + 1] = -sn * gj;
+        ctrl->est = est;
+    }
+    brk_out = brk;
+    hnorm_out = hnorm;
+    return est;
+}
+
+// Pass A of step j: first closes step j-1 from the partials of ||w||^2 left by pass C (for j = 0,
+// the partials of ||r||^2 left by the kernel that prepared r give beta), stopping the cycle when
+// the estimate meets the tolerance or the step broke down; then v_j = w * inv_h (stored as a basis
+// column), w = A v_j, and partials of Q^T w (Q = [C, V_0..V_j], ncol = kc + j + 1 columns) and of
+// ||w||^2 (reduction column ncol).
+template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
                                                  double* __restrict__ dst, double* __restrict__ basis,
                                                  int ld, int kc, int vbase, int j, int nblk,
-                                                 double* part, unsigned* counter, double* red_out,
-                                                 const Ctrl* ctrl) {
-    if (ctrl->stop) return;
+                                                 const double* __restrict__ part_n, double* __restrict__ part_a,
+                                                 const double* __restrict__ red1, const double* __restrict__ red2,
+                                                 double* H, double* Bm, Ctrl* ctrl) {
+    constexpr int NR = Width<NL>::NR;
     __shared__ double sh[NWAVE * NC];
+    __shared__ double s_scale;
+    __shared__ int s_stop;
+    const bool writer = blockIdx.x == 0;
     const int n = op.n;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     const bool valid = i < n;
-    const double scale = ctrl->inv_h;
-    double vj = 0.0, w = 0.0;
-    if (valid) {
-        vj = src[i] * scale;
-        basis[(size_t)(vbase + j) * ld + i] = vj;
-        w = op_row(op, src, i, scale);
-        dst[i] = w;
-    }
+    const int ii = valid ? i : n - 1;
     const int ncol = kc + j + 1;
-    double acc[NC];
+    const int nst = ncol - 1;                 // stored columns (v_j itself is formed here)
+    double q[NL];
+    if (nst > 0) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double q = 0.0;
-        if (valid && c < ncol) q = (c == ncol - 1) ? vj : qcol(basis, ld, kc, vbase, c)[i];
-        acc[c] = q * w;
+        for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < nst ? c : nst - 1, kc, vbase, ld) + ii];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NL; ++c) q[c] = 0.0;
     }
-    acc[NORM_COL] = w * w;
-    const double s = wave_reduce_scatter64(acc);
-    sh[wave_id() * NC + lane_id()] = s;
+    if (ctrl->stop) return;   // checked after the loads are issued so that the two latencies overlap
+    const double tot = sum_partials1(part_n, nblk, sh);
+    if (j == 0) {
+        if (threadIdx.x == 0) {
+            const double bt = sqrt(tot);
+            s_scale = bt > 0.0 ? 1.0 / bt : 0.0;
+            s_stop = 0;
+            if (writer) {
+                ctrl->beta = bt;
+                ctrl->g[0] = bt;
+                ctrl->inv_h = s_scale;
+            }
+        }
+    } else if (threadIdx.x < 64) {
+        int brk;
+        double hn;
+        const double est = close_step(j - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn);
+        if (threadIdx.x == 0) {
+            const int stop = (brk || !(est > ctrl->tol_abs)) ? 1 : 0;
+            s_stop = stop;
+            s_scale = brk ? 0.0 : 1.0 / hn;
+            if (writer) {
+                ctrl->inv_h = s_scale;
+                if (stop) {
+                    ctrl->j_done = j;
+                    ctrl->breakdown = brk;
+                    ctrl->stop = 1;
+                }
+            }
+        }
+    }
     __syncthreads();
-    if (threadIdx.x < NC) {
-        double t = sh[threadIdx.x];
-#pragma unroll
-        for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + threadIdx.x];
-        part[lb * NC + threadIdx.x] = t;
+    if (s_stop) return;
+    const double scale = s_scale;
+    const double vj = src[ii] * scale;
+    double w = op_row(op, src, ii, scale);
+    if (valid) {
+        basis[(size_t)(vbase + j) * ld + i] = vj;
+        dst[i] = w;
+    } else {
+        w = 0.0;
     }
-    if (last_block_arrive(counter, (unsigned)nblk)) final_reduce64(part, nblk, sh, red_out);
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
+        acc[c] = (c < nst) ? qc * w : (c == nst ? vj * w : (c == ncol ? w * w : 0.0));
+    }
+    const double s = wave_reduce_scatter<NR>(acc);
+    block_partials<NR>(s, sh, part_a, lb);
 }
 
-// ---------------------------------------------------------------------------------------------
-// Arnoldi step, pass B: w -= Q h1, partial Q^T w
-// ---------------------------------------------------------------------------------------------
+// Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
+// partials of Q^T w.
+template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const double* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk,
-                                                 const double* __restrict__ h1, double* part,
-                                                 unsigned* counter, double* red_out, const Ctrl* ctrl) {
-    if (ctrl->stop) return;
+                                                 const double* __restrict__ part_a, double* __restrict__ part_b,
+                                                 double* __restrict__ red1, const Ctrl* ctrl) {
+    constexpr int NR = Width<NL>::NR;
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
-    if (threadIdx.x < NC) hs[threadIdx.x] = h1[threadIdx.x];
-    __syncthreads();
+    const int ncol = kc + j + 1;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     const bool valid = i < n;
-    const int ncol = kc + j + 1;
-    double q[NC];
+    const int ii = valid ? i : n - 1;
+    double q[NL];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = (valid && c < ncol) ? qcol(basis, ld, kc, vbase, c)[i] : 0.0;
-    double w = valid ? w_io[i] : 0.0;
+    for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
+    double w = w_io[ii];
+    if (ctrl->stop) return;
+    sum_partials(part_a, nblk, ncol + 1, sh, hs);
+    if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (c < ncol) w = fma(-q[c], hs[c], w);
+    for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
     if (valid) w_io[i] = w;
+    else w = 0.0;
+    double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] *= w;
-    const double s = wave_reduce_scatter64(q);
-    sh[wave_id() * NC + lane_id()] = s;
-    __syncthreads();
-    if (threadIdx.x < NC) {
-        double t = sh[threadIdx.x];
-#pragma unroll
-        for (int qq = 1; qq < NWAVE; ++qq) t += sh[qq * NC + threadIdx.x];
-        part[lb * NC + threadIdx.x] = t;
-    }
-    if (last_block_arrive(counter, (unsigned)nblk)) final_reduce64(part, nblk, sh, red_out);
+    for (int c = 0; c < NR; ++c) acc[c] = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
+    const double s = wave_reduce_scatter<NR>(acc);
+    block_partials<NR>(s, sh, part_b, lb);
 }
 
-// ---------------------------------------------------------------------------------------------
-// Arnoldi step, pass C: w -= Q h2, ||w||; the last workgroup closes the step.
-// ---------------------------------------------------------------------------------------------
+// Pass C: h2 = Q^T w (sum of pass B's partials, stored), w -= Q h2, partials of ||w||^2.
+template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const double* __restrict__ basis,
-                                                 int n, int ld, int kc, int vbase, int j, int s_cycle,
-                                                 int nblk, const double* __restrict__ h1,
-                                                 const double* __restrict__ h2, double* part1,
-                                                 unsigned* counter, double* H, double* Bm, Ctrl* ctrl) {
-    if (ctrl->stop) return;
+                                                 int n, int ld, int kc, int vbase, int j, int nblk,
+                                                 const double* __restrict__ part_b, double* __restrict__ part_n,
+                                                 double* __restrict__ red2, const Ctrl* ctrl) {
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
-    if (threadIdx.x < NC) hs[threadIdx.x] = h2[threadIdx.x];
-    __syncthreads();
+    const int ncol = kc + j + 1;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     const bool valid = i < n;
-    const int ncol = kc + j + 1;
-    double w = valid ? w_io[i] : 0.0;
+    const int ii = valid ? i : n - 1;
+    double q[NL];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (valid && c < ncol) w = fma(-qcol(basis, ld, kc, vbase, c)[i], hs[c], w);
+    for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
+    double w = w_io[ii];
+    if (ctrl->stop) return;
+    sum_partials(part_b, nblk, ncol, sh, hs);
+    if (blockIdx.x == 0 && threadIdx.x < ncol) red2[threadIdx.x] = hs[threadIdx.x];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
     if (valid) w_io[i] = w;
-    double tot;
-    if (!grid_sum1(w * w, part1, counter, nblk, lb, sh, &tot)) return;
-    if (threadIdx.x >= 64) return;
-    // Wave 0 closes the step; lane t handles row t of the new column (j + 2 <= 64 rows).
-    const int t = threadIdx.x;
-    const double hnorm = sqrt(tot);
-    const double anorm = sqrt(h1[NORM_COL]);
-    const int brk = (hnorm <= 1e-14 * anorm) ? 1 : 0;
-    const double hlast = brk ? 0.0 : hnorm;
-    // Column j of B (rows of C) and of Hbar (rows of V): sums of both CGS passes (Eq. 6).
-    if (t < kc) Bm[t + j * KMAX] = h1[t] + h2[t];
-    double colt = 0.0;
-    if (t <= j) {
-        colt = h1[kc + t] + h2[kc + t];
-        H[t + j * LDH] = colt;
-    }
-    if (t == 0) H[j + 1 + j * LDH] = hlast;
-    // Progressive Givens QR of Hbar. Only the running entry is needed: after rotation q it is
-    // a_{q+1} = -sn_q a_q + cs_q col[q+1]; lane q holds (cs_q, sn_q, col[q+1]).
-    const double up = __shfl(colt, (t + 1) & 63, 64);
-    const double cnext = (t < j) ? up : (t == j ? hlast : 0.0);
-    const double cs_t = (t < j) ? ctrl->cs[t] : 0.0;
-    const double sn_t = (t < j) ? ctrl->sn[t] : 0.0;
-    double a = __shfl(colt, 0, 64);
-    for (int q = 0; q < j; ++q) {
-        const double mq = __shfl(sn_t, q, 64), cq = __shfl(cs_t, q, 64), bq = __shfl(cnext, q, 64);
-        a = fma(-mq, a, cq * bq);
-    }
-    if (t != 0) return;
-    const double rho = hypot(a, hlast);
-    const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? hlast / rho : 0.0;
-    ctrl->cs[j] = cs;
-    ctrl->sn[j] = sn;
-    const double gj = ctrl->g[j];
-    ctrl->g[j] = cs * gj;
-    ctrl->g[j + 1] = -sn * gj;
-    const double est = fabs(sn * gj);
-    ctrl->est = est;
-    ctrl->inv_h = brk ? 0.0 : 1.0 / hnorm;
-    if (brk || !(est > ctrl->tol_abs) || j + 1 >= s_cycle) {
-        ctrl->stop = 1;
-        ctrl->j_done = j + 1;
-        ctrl->breakdown = brk;
-    }
+    else w = 0.0;
+    block_partial1(w * w, part_n, lb, sh);
 }
 
-// v_{j_done} = w_last / h (zero after a breakdown), closing the basis of the cycle.
+// Cycle end: closes the last step when no pass A did (the cycle ran all s_cycle steps), then stores
+// v_{j_done} = w_last * inv_h (zero after a breakdown), the last column of the cycle's basis.
 __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__ w0, const double* __restrict__ w1,
-                                                      double* __restrict__ basis, int n, int ld, int vbase,
-                                                      const Ctrl* ctrl) {
+                                                      double* __restrict__ basis, int n, int ld, int kc, int vbase,
+                                                      int s_cycle, int nblk, const double* __restrict__ part_n,
+                                                      const double* __restrict__ red1, const double* __restrict__ red2,
+                                                      double* H, double* Bm, Ctrl* ctrl) {
+    __shared__ double sh[NWAVE * NC];
+    __shared__ double s_scale;
+    __shared__ int s_jd, s_brk;
+    const bool writer = blockIdx.x == 0;
+    if (!ctrl->stop) {
+        const double tot = sum_partials1(part_n, nblk, sh);
+        if (threadIdx.x < 64) {
+            int brk;
+            double hn;
+            close_step(s_cycle - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn);
+            if (threadIdx.x == 0) {
+                s_jd = s_cycle;
+                s_brk = brk;
+                s_scale = brk ? 0.0 : 1.0 / hn;
+                if (writer) {
+                    ctrl->j_done = s_cycle;
+                    ctrl->breakdown = brk;
+                    ctrl->inv_h = s_scale;
+                }
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        s_jd = ctrl->j_done;
+        s_brk = ctrl->breakdown;
+        s_scale = ctrl->inv_h;
+    }
+    __syncthreads();
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i >= n) return;
-    const int jd = ctrl->j_done;
-    const double* wl = ((jd - 1) & 1) ? w1 : w0;
-    basis[(size_t)(vbase + jd) * ld + i] = ctrl->breakdown ? 0.0 : wl[i] * ctrl->inv_h;
+    const double* wl = ((s_jd - 1) & 1) ? w1 : w0;
+    basis[(size_t)(vbase + s_jd) * ld + i] = s_brk ? 0.0 : wl[i] * s_scale;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -268,13 +368,40 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
     for (int c0 = r0; c0 < r1; c0 += GCHUNK) {
         const int rows = min(GCHUNK, r1 - c0);
         __syncthreads();
-        for (int e = threadIdx.x; e < nl * GCHUNK; e += ROWS) {
-            const int a = e / GCHUNK, rr = e - a * GCHUNK;
-            Ls[a * (GCHUNK + 1) + rr] = rr < rows ? col_of(L, a, ld)[c0 + rr] : 0.0;
-        }
-        for (int e = threadIdx.x; e < nr * GCHUNK; e += ROWS) {
-            const int a = e / GCHUNK, rr = e - a * GCHUNK;
-            Rs[a * (GCHUNK + 1) + rr] = rr < rows ? col_of(R, a, ld)[c0 + rr] : 0.0;
+        // stage the chunk: each thread loads up to GST values with all loads in flight together
+        {
+            constexpr int GST = (GL_MAX * GCHUNK + ROWS - 1) / ROWS;
+            double vl[GST];
+#pragma unroll
+            for (int u = 0; u < GST; ++u) {
+                const int e = threadIdx.x + u * ROWS;
+                const int a = e / GCHUNK, rr = e - a * GCHUNK;
+                vl[u] = (e < nl * GCHUNK && rr < rows) ? col_of(L, a, ld)[c0 + rr] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < GST; ++u) {
+                const int e = threadIdx.x + u * ROWS;
+                if (e < nl * GCHUNK) {
+                    const int a = e / GCHUNK, rr = e - a * GCHUNK;
+                    Ls[a * (GCHUNK + 1) + rr] = vl[u];
+                }
+            }
+            constexpr int GSR = (GR_MAX * GCHUNK + ROWS - 1) / ROWS;
+            double vr[GSR];
+#pragma unroll
+            for (int u = 0; u < GSR; ++u) {
+                const int e = threadIdx.x + u * ROWS;
+                const int a = e / GCHUNK, rr = e - a * GCHUNK;
+                vr[u] = (e < nr * GCHUNK && rr < rows) ? col_of(R, a, ld)[c0 + rr] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < GSR; ++u) {
+                const int e = threadIdx.x + u * ROWS;
+                if (e < nr * GCHUNK) {
+                    const int a = e / GCHUNK, rr = e - a * GCHUNK;
+                    Rs[a * (GCHUNK + 1) + rr] = vr[u];
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -297,93 +424,131 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
     }
 }
 
+// out[e] = sum_b gpart[b][e]: one workgroup per 64 outputs; wave w sums a contiguous quarter of
+// the partials (loads issued 16 at a time), then the quarters are added in order.
 __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__ gpart, int nb, int E,
                                                       double* __restrict__ out) {
-    const int e = blockIdx.x * ROWS + threadIdx.x;
-    if (e >= E) return;
+    __shared__ double sh[NWAVE * 64];
+    const int lane = lane_id(), w = wave_id();
+    const int e = blockIdx.x * 64 + lane;
+    const int per = (nb + NWAVE - 1) / NWAVE;
+    const int b0 = w * per, b1 = min(nb, b0 + per);
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += gpart[(size_t)b * E + e];
-    out[e] = s;
+    if (e < E) {
+        int b = b0;
+        for (; b + 16 <= b1; b += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = gpart[(size_t)(b + u) * E + e];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += v[u];
+        }
+        for (; b < b1; ++b) s += gpart[(size_t)b * E + e];
+    }
+    sh[w * 64 + lane] = s;
+    __syncthreads();
+    if (w == 0 && e < E) {
+        double t = sh[lane];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q) t += sh[q * 64 + lane];
+        out[e] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Cycle end: x += [U V] y, r -= [C V] (G y), C <- [C V] Qc, U <- [U V] Qu (in place, row-wise),
-// then ||r|| for the next cycle (Alg. 2: x_i, r_i and the recycle-space update).
+// Cycle end (Alg. 2): x += V-hat y, r -= W-hat G y, C <- W-hat Qc, U <- V-hat P_k R^{-1} (all
+// row-wise and in place), as one tall-skinny product [C, U, V] W with W held in LDS: row q of W
+// maps input column q to the outputs (C_new[0..KB), U_new[0..KB), dx, dr). KB is the bucket of
+// the new recycle size (0, 8, 16, 24 or 32). The partials of ||r_new||^2 are left for the next
+// cycle's first pass A.
 // ---------------------------------------------------------------------------------------------
+template <int KB>
 __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ basis, double* __restrict__ U,
-                                                       int n, int ld, int vbase, int nblk, const Coef* coef,
-                                                       double* part1, unsigned* counter, Ctrl* ctrl) {
-    __shared__ double sQc[LDQC * KMAX];
-    __shared__ double sQu[LDQU * KMAX];
-    __shared__ double sy[KMAX + MMAX + 1];
-    __shared__ double sr[KMAX + MMAX + 2];
+                                                       int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
+                                                       double* part_n, Ctrl* ctrl) {
+    constexpr int NO = 2 * KB + 2;
+    constexpr int MAXQ = 2 * KMAX + MMAX + 1;
+    __shared__ double Wc[MAXQ * NO];
     __shared__ double sh[NWAVE * NC];
-    const int kc = ctrl->kc, jd = ctrl->j_done, brk = ctrl->breakdown, kn = ctrl->k_new;
-    const int nv = jd + (brk ? 0 : 1);     // V columns of W-hat that enter (v_{jd} is zero after a breakdown)
-    for (int e = threadIdx.x; e < LDQC * kn; e += ROWS) sQc[e] = coef->Qc[e];
-    for (int e = threadIdx.x; e < LDQU * kn; e += ROWS) sQu[e] = coef->Qu[e];
-    for (int e = threadIdx.x; e < kc; e += ROWS) {
-        sy[e] = coef->yU[e];
-        sr[e] = coef->rC[e];
+    const int jd = ctrl->j_done, brk = ctrl->breakdown, kn = ctrl->k_new;
+    const int nv = jd + (brk ? 0 : 1);     // V columns of W-hat (v_{jd} is zero after a breakdown)
+    const int ncl = 2 * kc + nv;           // input columns: C (kc), U (kc), V (nv)
+    // build W: eight global loads in flight per thread
+    for (int e0 = 0; e0 < ncl * NO; e0 += 8 * ROWS) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * ROWS + threadIdx.x;
+            const int q = e / NO, o = e - q * NO;
+            double val = 0.0;
+            if (e < ncl * NO) {
+                if (q < kc) {                                    // C column q
+                    if (o < KB) val = o < kn ? coef->Qc[q + o * LDQC] : 0.0;
+                    else if (o == 2 * KB + 1) val = -coef->rC[q];
+                } else if (q < 2 * kc) {                         // U column c
+                    const int c = q - kc;
+                    if (o >= KB && o < 2 * KB) val = (o - KB) < kn ? coef->Qu[c + (o - KB) * LDQU] : 0.0;
+                    else if (o == 2 * KB) val = coef->yU[c];
+                } else {                                         // V column t
+                    const int t = q - 2 * kc;
+                    if (o < KB) val = o < kn ? coef->Qc[kc + t + o * LDQC] : 0.0;
+                    else if (o < 2 * KB) val = (t < jd && (o - KB) < kn) ? coef->Qu[kc + t + (o - KB) * LDQU] : 0.0;
+                    else if (o == 2 * KB) val = t < jd ? coef->yV[t] : 0.0;
+                    else val = -coef->rV[t];
+                }
+            }
+            v[u] = val;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * ROWS + threadIdx.x;
+            if (e < ncl * NO) Wc[e] = v[u];
+        }
     }
-    for (int e = threadIdx.x; e < jd; e += ROWS) sy[kc + e] = coef->yV[e];
-    for (int e = threadIdx.x; e < nv; e += ROWS) sr[kc + e] = coef->rV[e];
     __syncthreads();
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : n - 1;
+    double acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+    const double xi = x[ii], ri = r[ii];
+    for (int q0 = 0; q0 < ncl; q0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = min(q0 + u, ncl - 1);
+            const double* colp = q < kc ? basis + (size_t)q * ld
+                                        : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
+            v[u] = colp[ii];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (q0 + u < ncl) {
+                const double* wrow = Wc + (q0 + u) * NO;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) acc[o] = fma(v[u], wrow[o], acc[o]);
+            }
+        }
+    }
     double rn2 = 0.0;
-    if (i < n) {
-        double xi = x[i], ri = r[i];
-        double cn[KMAX], un[KMAX];
+    if (valid) {
+        const double rn = ri + acc[2 * KB + 1];
+        x[i] = xi + acc[2 * KB];
+        r[i] = rn;
 #pragma unroll
-        for (int o = 0; o < KMAX; ++o) { cn[o] = 0.0; un[o] = 0.0; }
-        for (int c = 0; c < kc; ++c) {
-            const double cv = basis[(size_t)c * ld + i];
-            ri = fma(-cv, sr[c], ri);
-#pragma unroll
-            for (int o = 0; o < KMAX; ++o)
-                if (o < kn) cn[o] = fma(cv, sQc[c + o * LDQC], cn[o]);
-        }
-        for (int c = 0; c < kc; ++c) {
-            const double uv = U[(size_t)c * ld + i];
-            xi = fma(uv, sy[c], xi);
-#pragma unroll
-            for (int o = 0; o < KMAX; ++o)
-                if (o < kn) un[o] = fma(uv, sQu[c + o * LDQU], un[o]);
-        }
-        for (int t = 0; t < nv; ++t) {
-            const double vv = basis[(size_t)(vbase + t) * ld + i];
-            ri = fma(-vv, sr[kc + t], ri);
-#pragma unroll
-            for (int o = 0; o < KMAX; ++o)
-                if (o < kn) cn[o] = fma(vv, sQc[kc + t + o * LDQC], cn[o]);
-            if (t < jd) {
-                xi = fma(vv, sy[kc + t], xi);
-#pragma unroll
-                for (int o = 0; o < KMAX; ++o)
-                    if (o < kn) un[o] = fma(vv, sQu[kc + t + o * LDQU], un[o]);
-            }
-        }
-        x[i] = xi;
-        r[i] = ri;
-#pragma unroll
-        for (int o = 0; o < KMAX; ++o)
+        for (int o = 0; o < KB; ++o)
             if (o < kn) {
-                basis[(size_t)o * ld + i] = cn[o];
-                U[(size_t)o * ld + i] = un[o];
+                basis[(size_t)o * ld + i] = acc[o];
+                U[(size_t)o * ld + i] = acc[KB + o];
             }
-        rn2 = ri * ri;
+        rn2 = rn * rn;
     }
-    double tot;
-    if (grid_sum1(rn2, part1, counter, nblk, lb, sh, &tot) && threadIdx.x == 0) {
-        const double bt = sqrt(tot);
-        ctrl->beta = bt;
-        ctrl->inv_h = bt > 0.0 ? 1.0 / bt : 0.0;
-        ctrl->g[0] = bt;
-        ctrl->stop = 0;
-        ctrl->kc = kn;
-    }
+    // partials of ||r||^2: the first pass A of the next cycle forms beta from them
+    block_partial1(rn2, part_n, lb, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->stop = 0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -539,7 +704,7 @@ __global__ __launch_bounds__(ROWS) void k_spmv(DevOp op, const double* __restric
 static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
 
 void launch_init(hipStream_t s, const Work& w, const double* b, double* x, double rtol) {
-    hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, rtol, w.part1,
+    hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, rtol, w.part_n,
                        w.counters + 0, w.ctrl);
 }
 void launch_clear_nonfinite(hipStream_t s, const Work& w) {
@@ -553,29 +718,68 @@ void launch_check_finite(hipStream_t s, const Work& w, const double* v, long cou
 void launch_zero(hipStream_t s, double* x, int n) {
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(n)), dim3(ROWS), 0, s, x, n);
 }
-void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle) {
-    const int vbase = w.k;
+static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
+
+template <int NL>
+static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j) {
+    hipLaunchKernelGGL(k_step_a<NL>, dim3(w.nblk), dim3(ROWS), 0, s, op, src, dst, w.basis, w.ld, kc, w.k, j,
+                       w.nblk, (const double*)w.part_n, w.part_a, (const double*)w.red1, (const double*)w.red2,
+                       w.H, w.Bm, w.ctrl);
+}
+template <int NL>
+static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j) {
+    hipLaunchKernelGGL(k_step_b<NL>, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
+                       w.k, j, w.nblk, (const double*)w.part_a, w.part_b, w.red1, (const Ctrl*)w.ctrl);
+}
+template <int NL>
+static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j) {
+    hipLaunchKernelGGL(k_step_c<NL>, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
+                       w.k, j, w.nblk, (const double*)w.part_b, w.part_n, w.red2, (const Ctrl*)w.ctrl);
+}
+
+#define SKR_DISPATCH8(NLV, CALL)                        \
+    switch (NLV) {                                      \
+        case 8: CALL(8); break;                         \
+        case 16: CALL(16); break;                       \
+        case 24: CALL(24); break;                       \
+        case 32: CALL(32); break;                       \
+        case 40: CALL(40); break;                       \
+        case 48: CALL(48); break;                       \
+        case 56: CALL(56); break;                       \
+        default: CALL(64); break;                       \
+    }
+
+// One Arnoldi step (three kernels). With ev != nullptr, hipEvents ev[0..3] bracket the kernels.
+void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle, hipEvent_t* ev) {
     const double* src = (j == 0) ? w.r : w.W[(j - 1) & 1];
     double* dst = w.W[j & 1];
-    hipLaunchKernelGGL(k_step_a, dim3(w.nblk), dim3(ROWS), 0, s, op, src, dst, w.basis, w.ld, kc, vbase, j,
-                       w.nblk, w.part, w.counters + 1, w.red1, w.ctrl);
-    hipLaunchKernelGGL(k_step_b, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
-                       vbase, j, w.nblk, (const double*)w.red1, w.part, w.counters + 2, w.red2,
-                       (const Ctrl*)w.ctrl);
-    hipLaunchKernelGGL(k_step_c, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
-                       vbase, j, s_cycle, w.nblk, (const double*)w.red1, (const double*)w.red2, w.part1,
-                       w.counters + 3, w.H, w.Bm, w.ctrl);
+    const int ncol = kc + j + 1;
+    const int nla = bucket8(ncol + 1), nlb = bucket8(ncol);
+    if (ev) (void)hipEventRecord(ev[0], s);
+#define CALL_A(NL) step_a<NL>(s, w, op, src, dst, kc, j)
+    SKR_DISPATCH8(nla, CALL_A)
+#undef CALL_A
+    if (ev) (void)hipEventRecord(ev[1], s);
+#define CALL_B(NL) step_b<NL>(s, w, dst, kc, j)
+    SKR_DISPATCH8(nlb, CALL_B)
+#undef CALL_B
+    if (ev) (void)hipEventRecord(ev[2], s);
+#define CALL_C(NL) step_c<NL>(s, w, dst, kc, j)
+    SKR_DISPATCH8(nlb, CALL_C)
+#undef CALL_C
+    if (ev) (void)hipEventRecord(ev[3], s);
 }
-void launch_close_basis(hipStream_t s, const Work& w) {
-    hipLaunchKernelGGL(k_close_basis, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, (const double*)w.W[0],
-                       (const double*)w.W[1], w.basis, w.n, w.ld, w.k, (const Ctrl*)w.ctrl);
+void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
+    hipLaunchKernelGGL(k_close_basis, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0], (const double*)w.W[1],
+                       w.basis, w.n, w.ld, kc, w.k, s_cycle, w.nblk, (const double*)w.part_n,
+                       (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
 }
 void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const ColList& R, int nr, double* out) {
     const int E = nl * nr;
     const int rpb = ((w.n + w.ngblk - 1) / w.ngblk + GCHUNK - 1) / GCHUNK * GCHUNK;
     const int nb = (w.n + rpb - 1) / rpb;
     hipLaunchKernelGGL(k_gram_partial, dim3(nb), dim3(ROWS), 0, s, L, nl, R, nr, w.n, w.ld, rpb, w.gpart);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(blocks_for(E)), dim3(ROWS), 0, s, (const double*)w.gpart, nb, E, out);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((E + 63) / 64), dim3(ROWS), 0, s, (const double*)w.gpart, nb, E, out);
 }
 void launch_cycle_gram(hipStream_t s, const Work& w, int kc, int jd_max) {
     // L = [C (kc), V_0..V_jd (jd+1), U (kc)], R = [U (kc), r]; jd is bounded on the host by the
@@ -584,12 +788,21 @@ void launch_cycle_gram(hipStream_t s, const Work& w, int kc, int jd_max) {
     ColList R = {{w.U, w.r, nullptr, nullptr}, {kc, 1, 0, 0}};
     launch_gram(s, w, L, 2 * kc + jd_max + 1, R, kc + 1, w.gram);
 }
-void launch_cycle_update(hipStream_t s, const Work& w, double* x) {
-    hipLaunchKernelGGL(k_cycle_update, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, w.basis, w.U, w.n, w.ld, w.k,
-                       w.nblk, (const Coef*)w.coef, w.part1, w.counters + 4, w.ctrl);
+void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_bucket) {
+#define SKR_UPD(KB)                                                                                        \
+    hipLaunchKernelGGL(k_cycle_update<KB>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, w.basis, w.U, w.n, w.ld, w.k, \
+                       kc, w.nblk, (const Coef*)w.coef, w.part_n, w.ctrl)
+    switch (k_bucket) {
+        case 0: SKR_UPD(0); break;
+        case 8: SKR_UPD(8); break;
+        case 16: SKR_UPD(16); break;
+        case 24: SKR_UPD(24); break;
+        default: SKR_UPD(32); break;
+    }
+#undef SKR_UPD
 }
 void launch_true_residual(hipStream_t s, const Work& w, const DevOp& op, const double* b, const double* x) {
-    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part1,
+    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n,
                        w.counters + 5, w.ctrl);
 }
 void launch_spmm(hipStream_t s, const Work& w, const DevOp& op, int kin) {
@@ -608,10 +821,14 @@ void launch_startup_project(hipStream_t s, const Work& w, double* x) {
                        w.ld, w.nblk, (const Coef*)w.coef, w.part, w.counters + 6, w.red1);
     hipLaunchKernelGGL(k_startup_project, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, (const double*)w.basis,
                        (const double*)w.U, w.n, w.ld, w.nblk, (const Coef*)w.coef, (const double*)w.red1,
-                       w.part1, w.counters + 7, w.ctrl);
+                       w.part_n, w.counters + 7, w.ctrl);
 }
 void launch_spmv(hipStream_t s, const DevOp& op, const double* x, double* y) {
     hipLaunchKernelGGL(k_spmv, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, x, y);
+}
+void launch_spmv_repeat(hipStream_t s, const DevOp& op, const double* x, double* y, int repeats) {
+    for (int q = 0; q < repeats; ++q)
+        hipLaunchKernelGGL(k_spmv, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, x, y);
 }
 
 int gram_cols_max(int m, int k) { return (2 * k + m + 2) * (k + 1); }

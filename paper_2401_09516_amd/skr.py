@@ -30,8 +30,10 @@ SKR_NONFINITE = 3
 SKR_OP_CSR = 0
 SKR_OP_STENCIL5 = 1
 
+SKR_FLAG_PROFILE = 1
+
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
-            "skr_solve_sequence", "skr_spmv")
+            "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset")
 
 
 class SkrError(RuntimeError):
@@ -56,6 +58,15 @@ class skr_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("k_start", ctypes.c_int32),
                 ("rank_dropped", ctypes.c_int32), ("iters", ctypes.c_int64), ("spmv", ctypes.c_int64),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double)]
+
+
+class skr_kernel_stat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class skr_profile(ctypes.Structure):
+    _fields_ = [("step_a", skr_kernel_stat), ("step_b", skr_kernel_stat), ("step_c", skr_kernel_stat),
+                ("steps", ctypes.c_int64), ("cycles", ctypes.c_int64), ("step_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -87,6 +98,12 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.skr_solve_sequence.restype = i32
     lib.skr_spmv.argtypes = [vp, ctypes.POINTER(skr_op), vp, vp]
     lib.skr_spmv.restype = i32
+    lib.skr_spmv_repeat.argtypes = [vp, ctypes.POINTER(skr_op), vp, vp, ctypes.c_int32, ctypes.POINTER(dbl)]
+    lib.skr_spmv_repeat.restype = i32
+    lib.skr_profile_get.argtypes = [vp, ctypes.POINTER(skr_profile)]
+    lib.skr_profile_get.restype = i32
+    lib.skr_profile_reset.argtypes = [vp]
+    lib.skr_profile_reset.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -182,3 +199,23 @@ def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 
 def skr_spmv(ctx: int, op: Operator, x, y) -> None:
     """y = A x on the device."""
     _check(load_library().skr_spmv(ctx, ctypes.byref(op.c), _ptr(x), _ptr(y)))
+
+
+def skr_spmv_repeat(ctx: int, op: Operator, x, y, repeats: int) -> float:
+    """Mean device time (ms) of one SpMV launch over ``repeats`` back-to-back launches."""
+    ms = ctypes.c_double()
+    _check(load_library().skr_spmv_repeat(ctx, ctypes.byref(op.c), _ptr(x), _ptr(y), repeats, ctypes.byref(ms)))
+    return ms.value
+
+
+def skr_profile_get(ctx: int) -> dict:
+    """Kernel statistics of solves run with SKR_FLAG_PROFILE since the last reset."""
+    p = skr_profile()
+    _check(load_library().skr_profile_get(ctx, ctypes.byref(p)))
+    ks = {name: dict(launches=getattr(p, name).launches, ms=getattr(p, name).ms, bytes=getattr(p, name).bytes)
+          for name in ("step_a", "step_b", "step_c")}
+    return dict(kernels=ks, steps=p.steps, cycles=p.cycles, step_bytes=p.step_bytes)
+
+
+def skr_profile_reset(ctx: int) -> None:
+    _check(load_library().skr_profile_reset(ctx))

@@ -49,6 +49,10 @@ int main(void) {
   F(skr_opts, m); F(skr_opts, k); F(skr_opts, rtol); F(skr_opts, maxit); F(skr_opts, flags);
   F(skr_result, status); F(skr_result, cycles); F(skr_result, k_start); F(skr_result, rank_dropped);
   F(skr_result, iters); F(skr_result, spmv); F(skr_result, relres_true); F(skr_result, relres_est);
+  printf("skr_kernel_stat %zu\nskr_profile %zu\n", sizeof(skr_kernel_stat), sizeof(skr_profile));
+  F(skr_kernel_stat, launches); F(skr_kernel_stat, ms); F(skr_kernel_stat, bytes);
+  F(skr_profile, step_a); F(skr_profile, step_b); F(skr_profile, step_c); F(skr_profile, steps);
+  F(skr_profile, cycles); F(skr_profile, step_bytes);
   return 0;
 }
 ''')
@@ -56,7 +60,8 @@ int main(void) {
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe), "-o", str(exe)], check=True)
     out = dict(ln.rsplit(" ", 1) for ln in subprocess.run([str(exe)], capture_output=True, text=True,
                                                           check=True).stdout.splitlines())
-    for cname, ct in (("skr_op", skr.skr_op), ("skr_opts", skr.skr_opts), ("skr_result", skr.skr_result)):
+    for cname, ct in (("skr_op", skr.skr_op), ("skr_opts", skr.skr_opts), ("skr_result", skr.skr_result),
+                      ("skr_kernel_stat", skr.skr_kernel_stat), ("skr_profile", skr.skr_profile)):
         assert int(out[cname]) == ctypes.sizeof(ct), cname
         for f, _ in ct._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)

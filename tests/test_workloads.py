@@ -60,3 +60,29 @@ def test_param_matrix_layout():
     P = param_matrix(seq)
     assert P.shape == (3, 36) and P.flags.c_contiguous
     assert np.array_equal(P[1], seq[1].a.ravel())
+
+
+def test_advdiff_operator():
+    from workloads.advdiff import advdiff_matrix, advdiff_sequence, stream_velocity
+    Nf = 64
+    hf = 1.0 / (Nf + 1)
+    bxf, byf = stream_velocity(Nf, 3)
+    # the sampled velocity of a stream function is divergence-free up to the O(h^2) difference error
+    dbx = np.gradient(bxf, hf, axis=1)
+    div = dbx + np.gradient(byf, hf, axis=0)
+    assert np.abs(div[2:-2, 2:-2]).max() < 0.02 * np.abs(dbx).max()
+    N = 9
+    h = 1.0 / (N + 1)
+    bx, by = stream_velocity(N, 3)
+    A = advdiff_matrix(N, 0.01, bx, by, 1e-2).toarray()
+    # constant velocity check against a hand-built upwind row
+    A2 = advdiff_matrix(N, 0.5, np.full((N, N), 2.0), np.full((N, N), -1.0), 0.1).toarray()
+    r = 4 * N + 4
+    assert np.isclose(A2[r, r], 10 + 2.0 / h ** 2 + 3.0 / h)
+    assert np.isclose(A2[r, r - 1], -0.5 / h ** 2 - 2.0 / h)       # west, bx > 0 upwind
+    assert np.isclose(A2[r, r + 1], -0.5 / h ** 2)                 # east
+    assert np.isclose(A2[r, r + N], -0.5 / h ** 2 - 1.0 / h)       # north, by < 0 upwind
+    assert np.isclose(A2[r, r - N], -0.5 / h ** 2)                 # south
+    assert not np.allclose(A, A.T)
+    seq = advdiff_sequence(6, 3)
+    assert all(1e-3 <= s.nu <= 1e-2 for s in seq) and seq[0].A.shape == (36, 36)
