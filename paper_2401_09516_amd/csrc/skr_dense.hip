@@ -223,12 +223,15 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 
 // Stage 2, symmetric case (4 wavefronts). M = X'' R_G^{-1} is formed; for symmetric A it is
 // symmetric in exact arithmetic (G^T G and G^T W-hat^T V-hat = V-hat^T A V-hat are), and when the
-// computed M is symmetric to 1e-10 relative, the eigenpairs of (M + M^T)/2 are found by the cyclic
-// Jacobi method (round-robin ordering: each round rotates d/2 disjoint pairs in parallel). Its
-// eigenvectors are orthonormal, so the selected ones form Q_w directly. Otherwise M is handed to
-// the general stage.
+// computed M is symmetric to 1e-10 relative, the wanted eigenpairs of S = (M + M^T)/2 are found by
+// Householder reduction to tridiagonal form T, multisection with Sturm counts for the eigenvalues
+// of T, twisted factorizations of T - lambda I for their eigenvectors, back-transformation through
+// the reflectors and modified Gram-Schmidt (a second pass when a column lost more than 30 % of
+// its norm). Otherwise, or when an eigenvector comes out dependent on the others (a cluster) or
+// not finite, M is handed to the general stage.
 constexpr int DT = 256;         // threads of the symmetric stage
 constexpr int LDS_ = DMAX + 1;  // leading dimension of S and V in LDS
+constexpr int NSHIFT = 16;      // multisection: shifts per eigenvalue interval and round
 
 __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     if (dw->mode != DW_PENDING) return;
@@ -238,10 +241,12 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     __shared__ double Wq[LDS_ * KMAX];
     __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX];
     __shared__ double red[DT / 64], red2[DT / 64];
-    __shared__ double jc[DMAX / 2], js[DMAX / 2];
-    __shared__ int jp[DMAX / 2], jq[DMAX / 2];
+    __shared__ double ta[DMAX], tb[DMAX], tb2[DMAX], hb[DMAX], hv0[DMAX], hP[DMAX];
+    __shared__ double blo[DMAX], bhi[DMAX], lam[DMAX], lsel[KMAX];
+    __shared__ double bsh[DMAX * NSHIFT];
+    __shared__ int bcnt[DMAX * NSHIFT];
     __shared__ int sel[KMAX];
-    __shared__ int nsel_s, sym_s;
+    __shared__ int nsel_s, sym_s, need2_s, fail_s;
     const int t = threadIdx.x;
     const int d = dw->d, kc = dw->kc;
     const int dp = d + (d & 1);                 // even size (a zero row/column pads an odd d)
@@ -280,119 +285,345 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         sym_s = (gd <= 1e-10 * ga) ? 1 : 0;
     }
     __syncthreads();
+    // M goes to the general stage's input in any case: that stage takes over if this one declines
+    for (int e = t; e < d * d; e += DT) {
+        const int r = e % d, c = e / d;
+        dw->X[r + c * DMAX] = S[r + c * LDS_];
+    }
     if (!sym_s) {
-        for (int e = t; e < d * d; e += DT) {
-            const int r = e % d, c = e / d;
-            dw->X[r + c * DMAX] = S[r + c * LDS_];
-        }
         if (t == 0) dw->mode = DW_GEN;
         return;
     }
-    // S = (M + M^T) / 2 in place (each unordered pair by one thread), padded to dp; V = I
-    for (int e = t; e < dp * dp; e += DT) {
-        const int r = e % dp, c = e / dp;
-        V[r + c * LDS_] = (r == c) ? 1.0 : 0.0;
+    // S = (M + M^T) / 2 in place (each unordered pair by one thread)
+    for (int e = t; e < d * d; e += DT) {
+        const int r = e % d, c = e / d;
         if (r < c) {
-            const double v = (c < d) ? 0.5 * (S[r + c * LDS_] + S[c + r * LDS_]) : 0.0;
+            const double v = 0.5 * (S[r + c * LDS_] + S[c + r * LDS_]);
             S[r + c * LDS_] = v;
             S[c + r * LDS_] = v;
-        } else if (r == c && c >= d) {
-            S[r + c * LDS_] = 0.0;
         }
     }
     __syncthreads();
-    // cyclic Jacobi sweeps until off(S) <= 1e-13 ||diag(S)|| (a rotation is skipped when
-    // |S_pq| <= 1e-16 sqrt(|S_pp S_qq|)). Thread t works on pair t >> 3 and every 8th row/column
-    // starting at t & 7.
-    const int np = dp / 2;
-    const int my_pair = t >> 3, my_g = t & 7;
-    for (int sweep = 0; sweep < 20; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int c = my_pair; c < dp; c += DT / 8)
-            for (int r = my_g; r < dp; r += 8) {
-                const double a = S[r + c * LDS_];
-                if (r != c) off = fma(a, a, off);
-                else dia = fma(a, a, dia);
-            }
-        off = wave_sum64(off);
-        dia = wave_sum64(dia);
-        if ((t & 63) == 0) { red[t >> 6] = off; red2[t >> 6] = dia; }
-        __syncthreads();
-        double offt = 0.0, diat = 0.0;
-        for (int q = 0; q < DT / 64; ++q) { offt += red[q]; diat += red2[q]; }
-        __syncthreads();
-        if (!(offt > 1e-26 * diat)) break;
-        for (int round = 0; round < dp - 1; ++round) {
-            if (t < np) {
-                // circle method: position 0 fixed, the others rotate
-                const int a = t, b = dp - 1 - t;
-                const int pa = (a == 0) ? 0 : 1 + (a - 1 + round) % (dp - 1);
-                const int pb = (b == 0) ? 0 : 1 + (b - 1 + round) % (dp - 1);
-                const int p = min(pa, pb), q = max(pa, pb);
-                const double spq = S[p + q * LDS_], spp = S[p + p * LDS_], sqq = S[q + q * LDS_];
-                double c = 1.0, s = 0.0;
-                if (fabs(spq) > 1e-16 * sqrt(fabs(spp * sqq))) {
-                    const double tau = (sqq - spp) / (2.0 * spq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s = tt * c;
-                }
-                jp[t] = p; jq[t] = q; jc[t] = c; js[t] = s;
-            }
-            __syncthreads();
-            if (my_pair < np && js[my_pair] != 0.0) {
-                const int p = jp[my_pair], q = jq[my_pair];
-                const double c = jc[my_pair], s = js[my_pair];
-                // rows: S <- J^T S
-                for (int col = my_g; col < dp; col += 8) {
-                    const double sp = S[p + col * LDS_], sq = S[q + col * LDS_];
-                    S[p + col * LDS_] = c * sp - s * sq;
-                    S[q + col * LDS_] = s * sp + c * sq;
-                }
-            }
-            __syncthreads();
-            if (my_pair < np && js[my_pair] != 0.0) {
-                const int p = jp[my_pair], q = jq[my_pair];
-                const double c = jc[my_pair], s = js[my_pair];
-                // columns: S <- S J, V <- V J
-                for (int row = my_g; row < dp; row += 8) {
-                    const double sp = S[row + p * LDS_], sq = S[row + q * LDS_];
-                    S[row + p * LDS_] = c * sp - s * sq;
-                    S[row + q * LDS_] = s * sp + c * sq;
-                    const double vp = V[row + p * LDS_], vq = V[row + q * LDS_];
-                    V[row + p * LDS_] = c * vp - s * vq;
-                    V[row + q * LDS_] = s * vp + c * vq;
-                }
-            }
-            __syncthreads();
+
+    // ---- Householder tridiagonalization. Step j maps x = S[j+1:d, j] to alpha e_1 with
+    // H_j = I - beta v v^T, v = x - alpha e_1: the first entry of v is kept in hv0[j], the others
+    // stay in S[j+2:d, j]. Trailing block update S' -= v w^T + w v^T with p = beta S' v,
+    // w = p - (beta p^T v / 2) v; the two products are added without contraction so that S stays
+    // exactly symmetric.
+    for (int j = 0; j + 2 < d; ++j) {
+        const int j1 = j + 1;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int r0 = j + 2;
+        for (; r0 + 3 < d; r0 += 4) {
+            const double x0 = S[r0 + j * LDS_], x1 = S[r0 + 1 + j * LDS_];
+            const double x2 = S[r0 + 2 + j * LDS_], x3 = S[r0 + 3 + j * LDS_];
+            s0 = fma(x0, x0, s0); s1 = fma(x1, x1, s1); s2 = fma(x2, x2, s2); s3 = fma(x3, x3, s3);
         }
-    }
-    // select the k_target eigenvalues of largest |mu| (smallest |theta| = 1/|mu|), ties by index
-    if (t < 64) {
-        int ns = 0;
-        unsigned long long used = 0ull;
-        for (int it = 0; it < k_target; ++it) {
-            double key = -1.0;
-            int idx = t;
-            if (t < d && !((used >> t) & 1ull)) {
-                const double mag = fabs(S[t + t * LDS_]);
-                if (mag > 0.0) key = mag;
+        for (; r0 < d; ++r0) { const double x0 = S[r0 + j * LDS_]; s0 = fma(x0, x0, s0); }
+        const double sig = (s0 + s1) + (s2 + s3);
+        const double xh = S[j1 + j * LDS_];
+        double beta = 0.0, v0 = 0.0, alpha = xh;
+        if (sig > 0.0) {
+            const double mu = sqrt(fma(xh, xh, sig));
+            v0 = (xh >= 0.0) ? xh + mu : xh - mu;
+            alpha = (xh >= 0.0) ? -mu : mu;
+            beta = 2.0 / fma(v0, v0, sig);
+        }
+        if (t == 0) { ta[j] = S[j + j * LDS_]; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; }
+        if (beta == 0.0) continue;   // same in every thread
+        {   // p = beta S' v: four threads per row, sixteen columns each
+            const int r = j1 + (t >> 2), q = t & 3;
+            const int rr = min(r, d - 1);
+            double sv[16], vv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = min(j1 + q + 4 * u, d - 1);
+                sv[u] = S[rr + c * LDS_];
+                vv[u] = S[c + j * LDS_];
+            }
+            double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = j1 + q + 4 * u;
+                const double vc = (c == j1) ? v0 : vv[u];
+                if (c < d) {
+                    if (u & 1) acc1 = fma(sv[u], vc, acc1);
+                    else acc0 = fma(sv[u], vc, acc0);
+                }
+            }
+            double acc = acc0 + acc1;
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (q == 0 && r < d) hP[r] = beta * acc;
+        }
+        __syncthreads();
+        {   // K = beta p^T v / 2 (every thread, same order), then the rank-2 update
+            double k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
+            k0 = hP[j1] * v0;
+            int r1 = j1 + 1;
+            for (; r1 + 3 < d; r1 += 4) {
+                k0 = fma(hP[r1], S[r1 + j * LDS_], k0);
+                k1 = fma(hP[r1 + 1], S[r1 + 1 + j * LDS_], k1);
+                k2 = fma(hP[r1 + 2], S[r1 + 2 + j * LDS_], k2);
+                k3 = fma(hP[r1 + 3], S[r1 + 3 + j * LDS_], k3);
+            }
+            for (; r1 < d; ++r1) k0 = fma(hP[r1], S[r1 + j * LDS_], k0);
+            const double K = 0.5 * beta * ((k0 + k1) + (k2 + k3));
+            const int r = j1 + (t & 63), rr = min(r, d - 1);
+            const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
+            const double wr = fma(-K, vr, hP[rr]);
+            double sv[16], vc[16], pc[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = min(j1 + (t >> 6) + 4 * u, d - 1);
+                sv[u] = S[rr + c * LDS_];
+                vc[u] = S[c + j * LDS_];
+                pc[u] = hP[c];
             }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ok = __shfl_xor(key, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+            for (int u = 0; u < 16; ++u) {
+                const int c = j1 + (t >> 6) + 4 * u;
+                if (r < d && c < d) {
+                    const double vcc = (c == j1) ? v0 : vc[u];
+                    const double wc = fma(-K, vcc, pc[u]);
+                    S[r + c * LDS_] = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
+                }
             }
-            if (key <= 0.0) break;
-            used |= 1ull << idx;
-            if (t == 0) sel[ns] = idx;
-            ++ns;
         }
-        if (t == 0) nsel_s = ns;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (d >= 2) { ta[d - 2] = S[d - 2 + (d - 2) * LDS_]; tb[d - 2] = S[d - 1 + (d - 2) * LDS_]; }
+        ta[d - 1] = S[d - 1 + (d - 1) * LDS_];
+    }
+    __syncthreads();
+    if (t < d - 1) tb2[t] = tb[t] * tb[t];
+    __syncthreads();
+
+    // ---- eigenvalues of T by multisection: each round splits every interval [lo_i, hi_i] holding
+    // the i-th smallest eigenvalue at NSHIFT points (four threads per eigenvalue, four interleaved
+    // Sturm recurrences per thread); count(sigma) = number of negative pivots of T - sigma I.
+    const double eps = 2.220446049250313e-16;
+    double tnorm = 0.0, pivmin = 0.0;
+    {
+        double glo = __builtin_inf(), ghi = -__builtin_inf(), bm2 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            const double rad = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < d ? fabs(tb[i]) : 0.0);
+            glo = fmin(glo, ta[i] - rad);
+            ghi = fmax(ghi, ta[i] + rad);
+            if (i + 1 < d) bm2 = fmax(bm2, tb2[i]);
+        }
+        tnorm = fmax(fabs(glo), fabs(ghi));
+        pivmin = 2.2250738585072014e-308 * fmax(1.0, bm2);
+        const double widen = 2.0 * eps * tnorm * d + 2.0 * pivmin;
+        if (t < d) { blo[t] = glo - widen; bhi[t] = ghi + widen; }
+    }
+    __syncthreads();
+    for (int round = 0; round < 48; ++round) {
+        const int i = t & 63, q = t >> 6;
+        const int ii = min(i, d - 1);
+        const double lo = blo[ii], hi = bhi[ii], wdt = hi - lo;
+        double sh[4], D[4];
+        int cnt[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            sh[s4] = lo + wdt * ((double)(q * 4 + s4 + 1) / (double)(NSHIFT + 1));
+            D[s4] = ta[0] - sh[s4];
+            if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+            cnt[s4] = D[s4] < 0.0;
+        }
+        for (int m2 = 1; m2 < d; ++m2) {
+            const double a = ta[m2], b2 = tb2[m2 - 1];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                double rc = __builtin_amdgcn_rcp(D[s4]);
+                rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                D[s4] = fma(-b2, rc, a - sh[s4]);
+                if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+                cnt[s4] += D[s4] < 0.0;
+            }
+        }
+        if (i < d) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                bsh[i * NSHIFT + q * 4 + s4] = sh[s4];
+                bcnt[i * NSHIFT + q * 4 + s4] = cnt[s4];
+            }
+        }
+        __syncthreads();
+        int open = 0;
+        if (q == 0 && i < d) {
+            double nl = lo, nh = hi;
+            for (int p2 = 0; p2 < NSHIFT; ++p2)
+                if (bcnt[i * NSHIFT + p2] <= i) nl = bsh[i * NSHIFT + p2];
+            for (int p2 = NSHIFT - 1; p2 >= 0; --p2)
+                if (bcnt[i * NSHIFT + p2] > i) nh = bsh[i * NSHIFT + p2];
+            if (nh < nl) nh = nl;
+            blo[i] = nl;
+            bhi[i] = nh;
+            open = (nh - nl) > fmax(2.0 * eps * fmax(fabs(nl), fabs(nh)), 4.0 * eps * tnorm);
+        }
+        if (!__syncthreads_or(open)) break;
+    }
+    if (t < d) lam[t] = 0.5 * (blo[t] + bhi[t]);
+    __syncthreads();
+
+    // ---- the k_target eigenvalues of largest |mu| (smallest |theta| = 1/|mu|): the eigenvalues are
+    // ascending, so the largest magnitudes are taken from both ends; at equal magnitude the
+    // positive one first; zero eigenvalues (theta infinite) are never taken.
+    if (t == 0) {
+        int lo = 0, hi = d - 1, ns = 0;
+        while (ns < k_target && lo <= hi) {
+            const int pick = (fabs(lam[hi]) >= fabs(lam[lo])) ? hi-- : lo++;
+            if (!(fabs(lam[pick]) > 0.0)) break;
+            lsel[ns++] = lam[pick];
+        }
+        nsel_s = ns;
+        need2_s = 0;
+        fail_s = 0;
     }
     __syncthreads();
     const int kn = nsel_s;
+
+    // ---- eigenvectors of T (one thread per selected eigenvalue): T - lambda I = L+ D+ L+^T =
+    // U- D- U-^T, twist index r = argmin |D+_r + D-_r - (a_r - lambda)|, then z_r = 1 and
+    // z_i = -b_i z_{i+1} / D+_i (i < r), z_{i+1} = -b_i z_i / D-_{i+1} (i >= r). D+ and D- live in
+    // V (columns of 32), z overwrites D+.
+    double* Fp = V;
+    double* Fm = V + DMAX * KMAX;
+    if (t < kn) {
+        const int o = t;
+        const double lm = lsel[o];
+        double dp = ta[0] - lm, dm = ta[d - 1] - lm;
+        if (fabs(dp) < pivmin) dp = -pivmin;
+        if (fabs(dm) < pivmin) dm = -pivmin;
+        Fp[o] = dp;
+        Fm[(d - 1) * KMAX + o] = dm;
+        for (int s2 = 1; s2 < d; ++s2) {
+            const int ib = d - 1 - s2;
+            dp = (ta[s2] - lm) - tb2[s2 - 1] / dp;
+            dm = (ta[ib] - lm) - tb2[ib] / dm;
+            if (fabs(dp) < pivmin) dp = -pivmin;
+            if (fabs(dm) < pivmin) dm = -pivmin;
+            Fp[s2 * KMAX + o] = dp;
+            Fm[ib * KMAX + o] = dm;
+        }
+        int rt = 0;
+        double gb = __builtin_inf();
+        for (int i = 0; i < d; ++i) {
+            const double g = fabs(Fp[i * KMAX + o] + Fm[i * KMAX + o] - (ta[i] - lm));
+            if (g < gb) { gb = g; rt = i; }
+        }
+        double z = 1.0;
+        for (int i = rt - 1; i >= 0; --i) {
+            z = -tb[i] * z / Fp[i * KMAX + o];
+            Fp[i * KMAX + o] = z;
+        }
+        Fp[rt * KMAX + o] = 1.0;
+        z = 1.0;
+        for (int i = rt; i + 1 < d; ++i) {
+            z = -tb[i] * z / Fm[(i + 1) * KMAX + o];
+            Fp[(i + 1) * KMAX + o] = z;
+        }
+    }
+    __syncthreads();
+
+    // ---- back-transformation z <- H_0 ... H_{d-3} z and modified Gram-Schmidt, eight lanes per
+    // column (column c = t / 8, rows t % 8 + 8 i in registers); the finished columns go to V.
+    const int zc = t >> 3, part = t & 7;
+    double zr[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = part + 8 * i;
+        zr[i] = (zc < kn && r < d) ? Fp[r * KMAX + zc] : 0.0;
+    }
+    __syncthreads();
+    for (int j = d - 3; j >= 0; --j) {
+        const double beta = hb[j];
+        if (beta == 0.0) continue;
+        const double v0 = hv0[j];
+        double vr[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int r = part + 8 * i;
+            const double sv = S[min(r, d - 1) + j * LDS_];
+            vr[i] = (r == j + 1) ? v0 : ((r > j + 1 && r < d) ? sv : 0.0);
+        }
+        double dt0 = 0.0, dt1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) { dt0 = fma(vr[i], zr[i], dt0); dt1 = fma(vr[i + 1], zr[i + 1], dt1); }
+        double dot = dt0 + dt1;
+        dot += __shfl_xor(dot, 1, 64);
+        dot += __shfl_xor(dot, 2, 64);
+        dot += __shfl_xor(dot, 4, 64);
+        dot *= beta;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) zr[i] = fma(-dot, vr[i], zr[i]);
+    }
+    double n0;
+    {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) { a0 = fma(zr[i], zr[i], a0); a1 = fma(zr[i + 1], zr[i + 1], a1); }
+        n0 = a0 + a1;
+        n0 += __shfl_xor(n0, 1, 64);
+        n0 += __shfl_xor(n0, 2, 64);
+        n0 += __shfl_xor(n0, 4, 64);
+        n0 = sqrt(n0);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < kn; ++j) {
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) { a0 = fma(zr[i], zr[i], a0); a1 = fma(zr[i + 1], zr[i + 1], a1); }
+            double nr = a0 + a1;
+            nr += __shfl_xor(nr, 1, 64);
+            nr += __shfl_xor(nr, 2, 64);
+            nr += __shfl_xor(nr, 4, 64);
+            nr = sqrt(nr);
+            if (zc == j) {
+                if (pass == 0) {
+                    if (!(nr > 1e-8 * n0) || !(n0 < __builtin_inf())) fail_s = 1;
+                    else if (nr < 0.7 * n0) need2_s = 1;
+                }
+                const double inv = (nr > 0.0) ? 1.0 / nr : 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    zr[i] *= inv;
+                    const int r = part + 8 * i;
+                    if (r < d) V[r + j * LDS_] = zr[i];
+                }
+            }
+            __syncthreads();
+            double qv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = part + 8 * i;
+                qv[i] = (r < d) ? V[r + j * LDS_] : 0.0;
+            }
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) { d0 = fma(qv[i], zr[i], d0); d1 = fma(qv[i + 1], zr[i + 1], d1); }
+            double dot = d0 + d1;
+            dot += __shfl_xor(dot, 1, 64);
+            dot += __shfl_xor(dot, 2, 64);
+            dot += __shfl_xor(dot, 4, 64);
+            if (zc > j && zc < kn) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) zr[i] = fma(-dot, qv[i], zr[i]);
+            }
+        }
+        __syncthreads();
+        if (fail_s || !need2_s) break;
+    }
+    if (fail_s) {
+        if (t == 0) dw->mode = DW_GEN;
+        return;
+    }
+    if (t < kn) sel[t] = t;
+    __syncthreads();
     // Qu = R_G^{-1} Q_w with Q_w = V[:, sel]: back-substitution, parallel over (row, column)
     for (int e = t; e < d * kn; e += DT) {
         const int r = e % d, o = e / d;
