@@ -22,6 +22,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_a_traffic_darcy256.txt")
+STEP_SOURCES = [os.path.join(ROOT, "paper_2401_09516_amd", "csrc", f) for f in ("skr_solver.hip", "skr_internal.hpp")]
+
+
+def step_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_step_a launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
+    the summary is missing or was taken on a different version of the step-kernel source."""
+    try:
+        kv = dict(ln.split(":", 1) for ln in open(TRAFFIC_FILE) if ":" in ln and not ln.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != step_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -40,6 +65,11 @@ def parse():
     ap.add_argument("--cpu-systems", type=int, default=2, help="oracle sample: first systems of the sorted chain")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--spmv-grid", type=int, default=2048, help="grid of the > 256 MB SpMV bandwidth case")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="untimed: one pass of the hot path over --systems systems, then a device copy of "
+                         "--copy-mib MiB (the reference kernel that scales hardware byte counters); for "
+                         "rocprofv3 --pmc runs")
+    ap.add_argument("--copy-mib", type=int, default=512)
     return ap.parse_args()
 
 
@@ -77,6 +107,25 @@ def main():
     ctx = skr.skr_ctx_create(0, stream.cuda_stream)
     N, p = P.shape
 
+    if a.pmc_probe:
+        order, _ = skr.skr_sort(ctx, Pd, N, p, 0, want_dist=False)
+        rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
+                                         flags=skr.SKR_FLAG_PROFILE)
+        torch.cuda.synchronize()
+        sa = skr.skr_profile_get(ctx)["kernels"]["step_a"]
+        nb = a.copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        skr.skr_ctx_destroy(ctx)
+        print(json.dumps({"pmc_probe": True, "systems": a.systems, "iters": [r["iters"] for r in res],
+                          "k_step_a_algorithmic_bytes_per_launch": sa["bytes"] / max(sa["launches"], 1),
+                          "copy_bytes_read": nb, "copy_bytes_written": nb, "copies": 3,
+                          "step_source_sha256": step_source_hash()}), flush=True)
+        return
+
     def step(flags):
         order, _ = skr.skr_sort(ctx, Pd, N, p, 0, want_dist=False)
         rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
@@ -113,8 +162,10 @@ def main():
     roofline = None
     if dom:
         ach = kern[dom]["gbs"]
+        traffic = measured_traffic() if dom == "step_a" else None
         roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel_names[dom],
+                        frac=round(ach / HBM_PEAK_GBS, 4),
+                        traffic=round(traffic) if traffic is not None else None, kernel=kernel_names[dom],
                         avg_us=round(kern[dom]["avg_us"], 2), bytes_per_launch=round(kern[dom]["avg_bytes"]))
     # timing of the sort alone
     torch.cuda.synchronize()

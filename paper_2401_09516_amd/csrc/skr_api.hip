@@ -67,7 +67,7 @@ struct skr_ctx {
     double* dist_d = nullptr;
     size_t sortN_cap = 0;
     // profiling
-    hipEvent_t ev[PROF_MAXSAMP * 4] = {};
+    hipEvent_t ev[PROF_MAXSAMP * 6] = {};
     bool ev_ok = false;
     int64_t step_counter = 0;
     skr_profile prof = {};
@@ -222,7 +222,7 @@ int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
         return fail(SKR_EHIP, "pinned host allocation failed");
     }
     c->ev_ok = true;
-    for (int q = 0; q < PROF_MAXSAMP * 4; ++q)
+    for (int q = 0; q < PROF_MAXSAMP * 6; ++q)
         if (hipEventCreate(&c->ev[q]) != hipSuccess) c->ev_ok = false;
     *out = c;
     g_err.clear();
@@ -239,7 +239,7 @@ int skr_ctx_destroy(skr_ctx* ctx) {
     if (ctx->dist_d) (void)hipFree(ctx->dist_d);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
     if (ctx->hkeff) (void)hipHostFree(ctx->hkeff);
-    for (int q = 0; q < PROF_MAXSAMP * 4; ++q)
+    for (int q = 0; q < PROF_MAXSAMP * 6; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
     delete ctx;
     return SKR_OK;
@@ -443,7 +443,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
             for (int j = 0; j < scyc; ++j) {
                 hipEvent_t* ev = nullptr;
                 if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
-                    ev = ctx->ev + 4 * nsamp;
+                    ev = ctx->ev + 6 * nsamp;
                     samp_j[nsamp++] = j;
                 }
                 launch_step(s, w, op, kc, j, scyc, ev);
@@ -464,7 +464,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
                     if (samp_j[q] >= jd) continue;   // steps after the stop are skipped launches
                     float t[3];
                     for (int e = 0; e < 3; ++e)
-                        HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[4 * q + e], ctx->ev[4 * q + e + 1]));
+                        HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[6 * q + 2 * e], ctx->ev[6 * q + 2 * e + 1]));
                     double ba, bb, bc;
                     step_bytes(op, nvals, kc + samp_j[q] + 1, ba, bb, bc);
                     pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;

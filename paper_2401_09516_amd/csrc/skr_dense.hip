@@ -231,18 +231,17 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 // not finite, M is handed to the general stage.
 constexpr int DT = 256;         // threads of the symmetric stage
 constexpr int LDS_ = DMAX + 1;  // leading dimension of S and V in LDS
-constexpr int NSHIFT = 16;      // multisection: shifts per eigenvalue interval and round
+constexpr int NSHIFT = 8;       // multisection: shifts per eigenvalue interval and round
 
 __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     if (dw->mode != DW_PENDING) return;
     __shared__ double S[LDS_ * DMAX];
     __shared__ double V[LDS_ * DMAX];
     __shared__ double R[LDS_ * DMAX];
-    __shared__ double Wq[LDS_ * KMAX];
-    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX];
+    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX], Rd[DMAX];
     __shared__ double red[DT / 64], red2[DT / 64];
     __shared__ double ta[DMAX], tb[DMAX], tb2[DMAX], hb[DMAX], hv0[DMAX], hP[DMAX];
-    __shared__ double blo[DMAX], bhi[DMAX], lam[DMAX], lsel[KMAX];
+    __shared__ double blo[DMAX], bhi[DMAX], lam[DMAX], lsel[KMAX], hsig[1], hkp[DT / 64];
     __shared__ double bsh[DMAX * NSHIFT];
     __shared__ int bcnt[DMAX * NSHIFT];
     __shared__ int sel[KMAX];
@@ -256,17 +255,43 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     if (t < d) { gcs[t] = dw->gcs[t]; gsn[t] = dw->gsn[t]; }
     if (t < kc) Dk[t] = dw->Dk[t];
     __syncthreads();
-    // M = X'' R^{-1}: column c of M = (X''_c - sum_{q<c} M_q R_qc) / R_cc, right-looking over c
-    for (int c = 0; c < d; ++c) {
-        const double inv = 1.0 / R[c + c * LDS_];
-        for (int r = t; r < d; r += DT) S[r + c * LDS_] *= inv;
-        __syncthreads();
-        for (int e = t; e < d * (d - c - 1); e += DT) {
-            const int r = e % d, c2 = c + 1 + e / d;
-            S[r + c2 * LDS_] = fma(-S[r + c * LDS_], R[c + c2 * LDS_], S[r + c2 * LDS_]);
+    // M = X'' R^{-1}: row r of M solves m R = x'' (forward over the columns, right-looking). Four
+    // lanes per row, lane part p holding columns 16p..16p+15 in registers; m_c is broadcast from
+    // the lane that owns column c.
+    if (t < d) Rd[t] = 1.0 / R[t + t * LDS_];
+    __syncthreads();
+    {
+        const int r = t >> 2, p = t & 3;
+        const int rr = min(r, d - 1);
+        double acc[16];
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) acc[s2] = S[rr + min(16 * p + s2, d - 1) * LDS_];
+        for (int c0 = 0; c0 < d; c0 += 16) {
+            const int owner = c0 >> 4;
+#pragma unroll
+            for (int s1 = 0; s1 < 16; ++s1) {
+                const int c = c0 + s1;
+                if (c < d) {
+                    const double ml = acc[s1] * Rd[c];
+                    if (p == owner) acc[s1] = ml;
+                    const double mc = __shfl(ml, (t & ~3) | owner, 64);
+#pragma unroll
+                    for (int s2 = 0; s2 < 16; ++s2) {
+                        const int c2 = 16 * p + s2;
+                        const double rc = R[c + c2 * LDS_];
+                        acc[s2] = (c2 > c) ? fma(-mc, rc, acc[s2]) : acc[s2];
+                    }
+                }
+            }
         }
         __syncthreads();
+        if (r < d) {
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2)
+                if (16 * p + s2 < d) S[r + (16 * p + s2) * LDS_] = acc[s2];
+        }
     }
+    __syncthreads();
     // symmetry test: max |M - M^T| <= 1e-10 max |M|
     double amax = 0.0, dmax = 0.0;
     for (int e = t; e < d * d; e += DT) {
@@ -309,18 +334,16 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     // H_j = I - beta v v^T, v = x - alpha e_1: the first entry of v is kept in hv0[j], the others
     // stay in S[j+2:d, j]. Trailing block update S' -= v w^T + w v^T with p = beta S' v,
     // w = p - (beta p^T v / 2) v; the two products are added without contraction so that S stays
-    // exactly symmetric.
+    // exactly symmetric. sigma = ||x(2:)||^2 of the next step and p^T v come from wave reductions.
+    if (t < 64) {
+        const double x = (t >= 2 && t < d) ? S[t] : 0.0;
+        const double sg = wave_sum64(x * x);
+        if (t == 0) hsig[0] = sg;
+    }
+    __syncthreads();
     for (int j = 0; j + 2 < d; ++j) {
         const int j1 = j + 1;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int r0 = j + 2;
-        for (; r0 + 3 < d; r0 += 4) {
-            const double x0 = S[r0 + j * LDS_], x1 = S[r0 + 1 + j * LDS_];
-            const double x2 = S[r0 + 2 + j * LDS_], x3 = S[r0 + 3 + j * LDS_];
-            s0 = fma(x0, x0, s0); s1 = fma(x1, x1, s1); s2 = fma(x2, x2, s2); s3 = fma(x3, x3, s3);
-        }
-        for (; r0 < d; ++r0) { const double x0 = S[r0 + j * LDS_]; s0 = fma(x0, x0, s0); }
-        const double sig = (s0 + s1) + (s2 + s3);
+        const double sig = hsig[0];
         const double xh = S[j1 + j * LDS_];
         double beta = 0.0, v0 = 0.0, alpha = xh;
         if (sig > 0.0) {
@@ -330,65 +353,67 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
             beta = 2.0 / fma(v0, v0, sig);
         }
         if (t == 0) { ta[j] = S[j + j * LDS_]; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; }
-        if (beta == 0.0) continue;   // same in every thread
-        {   // p = beta S' v: four threads per row, sixteen columns each
-            const int r = j1 + (t >> 2), q = t & 3;
-            const int rr = min(r, d - 1);
-            double sv[16], vv[16];
+        if (beta != 0.0) {   // same in every thread
+            {   // p = beta S' v: four threads per row, sixteen columns each; partial sums of p^T v per wave
+                const int r = j1 + (t >> 2), q = t & 3;
+                const int rr = min(r, d - 1);
+                double sv[16], vv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int c = min(j1 + q + 4 * u, d - 1);
-                sv[u] = S[rr + c * LDS_];
-                vv[u] = S[c + j * LDS_];
+                for (int u = 0; u < 16; ++u) {
+                    const int c = min(j1 + q + 4 * u, d - 1);
+                    sv[u] = S[rr + c * LDS_];
+                    vv[u] = S[c + j * LDS_];
+                }
+                double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int c = j1 + q + 4 * u;
+                    const double vc = (c == j1) ? v0 : vv[u];
+                    if (c < d) {
+                        if (u & 1) acc1 = fma(sv[u], vc, acc1);
+                        else acc0 = fma(sv[u], vc, acc0);
+                    }
+                }
+                double acc = acc0 + acc1;
+                acc += __shfl_xor(acc, 1, 64);
+                acc += __shfl_xor(acc, 2, 64);
+                const double pr = beta * acc;
+                const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
+                const double kp = wave_sum64((q == 0 && r < d) ? pr * vr : 0.0);
+                if (q == 0 && r < d) hP[r] = pr;
+                if ((t & 63) == 0) hkp[t >> 6] = kp;
             }
-            double acc0 = 0.0, acc1 = 0.0;
+            __syncthreads();
+            {   // rank-2 update, thread (row j1 + t % 64, columns j1 + t / 64 + 4u)
+                const double K = 0.5 * beta * ((hkp[0] + hkp[1]) + (hkp[2] + hkp[3]));
+                const int r = j1 + (t & 63), rr = min(r, d - 1);
+                const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
+                const double wr = fma(-K, vr, hP[rr]);
+                double sv[16], vc[16], pc[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int c = j1 + q + 4 * u;
-                const double vc = (c == j1) ? v0 : vv[u];
-                if (c < d) {
-                    if (u & 1) acc1 = fma(sv[u], vc, acc1);
-                    else acc0 = fma(sv[u], vc, acc0);
+                for (int u = 0; u < 16; ++u) {
+                    const int c = min(j1 + (t >> 6) + 4 * u, d - 1);
+                    sv[u] = S[rr + c * LDS_];
+                    vc[u] = S[c + j * LDS_];
+                    pc[u] = hP[c];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int c = j1 + (t >> 6) + 4 * u;
+                    if (r < d && c < d) {
+                        const double vcc = (c == j1) ? v0 : vc[u];
+                        const double wc = fma(-K, vcc, pc[u]);
+                        S[r + c * LDS_] = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
+                    }
                 }
             }
-            double acc = acc0 + acc1;
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            if (q == 0 && r < d) hP[r] = beta * acc;
         }
-        __syncthreads();
-        {   // K = beta p^T v / 2 (every thread, same order), then the rank-2 update
-            double k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
-            k0 = hP[j1] * v0;
-            int r1 = j1 + 1;
-            for (; r1 + 3 < d; r1 += 4) {
-                k0 = fma(hP[r1], S[r1 + j * LDS_], k0);
-                k1 = fma(hP[r1 + 1], S[r1 + 1 + j * LDS_], k1);
-                k2 = fma(hP[r1 + 2], S[r1 + 2 + j * LDS_], k2);
-                k3 = fma(hP[r1 + 3], S[r1 + 3 + j * LDS_], k3);
-            }
-            for (; r1 < d; ++r1) k0 = fma(hP[r1], S[r1 + j * LDS_], k0);
-            const double K = 0.5 * beta * ((k0 + k1) + (k2 + k3));
-            const int r = j1 + (t & 63), rr = min(r, d - 1);
-            const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
-            const double wr = fma(-K, vr, hP[rr]);
-            double sv[16], vc[16], pc[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int c = min(j1 + (t >> 6) + 4 * u, d - 1);
-                sv[u] = S[rr + c * LDS_];
-                vc[u] = S[c + j * LDS_];
-                pc[u] = hP[c];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int c = j1 + (t >> 6) + 4 * u;
-                if (r < d && c < d) {
-                    const double vcc = (c == j1) ? v0 : vc[u];
-                    const double wc = fma(-K, vcc, pc[u]);
-                    S[r + c * LDS_] = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
-                }
-            }
+        // sigma of the next step from column j1 (wave 0 wrote or holds rows j1 + lane of it)
+        if (t < 64) {
+            const int r = j1 + t;
+            const double x = (r >= j1 + 2 && r < d) ? S[r + j1 * LDS_] : 0.0;
+            const double sg = wave_sum64(x * x);
+            if (t == 0) hsig[0] = sg;
         }
         __syncthreads();
     }
@@ -402,7 +427,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     __syncthreads();
 
     // ---- eigenvalues of T by multisection: each round splits every interval [lo_i, hi_i] holding
-    // the i-th smallest eigenvalue at NSHIFT points (four threads per eigenvalue, four interleaved
+    // the i-th smallest eigenvalue at NSHIFT points (four threads per eigenvalue, two interleaved
     // Sturm recurrences per thread); count(sigma) = number of negative pivots of T - sigma I.
     const double eps = 2.220446049250313e-16;
     double tnorm = 0.0, pivmin = 0.0;
@@ -424,32 +449,43 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         const int i = t & 63, q = t >> 6;
         const int ii = min(i, d - 1);
         const double lo = blo[ii], hi = bhi[ii], wdt = hi - lo;
-        double sh[4], D[4];
-        int cnt[4];
+        double sh[2], D[2];
+        int cnt[2];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            sh[s4] = lo + wdt * ((double)(q * 4 + s4 + 1) / (double)(NSHIFT + 1));
+        for (int s4 = 0; s4 < 2; ++s4) {
+            sh[s4] = lo + wdt * ((double)(q * 2 + s4 + 1) / (double)(NSHIFT + 1));
             D[s4] = ta[0] - sh[s4];
             if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
             cnt[s4] = D[s4] < 0.0;
         }
-        for (int m2 = 1; m2 < d; ++m2) {
-            const double a = ta[m2], b2 = tb2[m2 - 1];
+        for (int m0 = 1; m0 < d; m0 += 8) {
+            double av[8], bv[8];
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                double rc = __builtin_amdgcn_rcp(D[s4]);
-                rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                D[s4] = fma(-b2, rc, a - sh[s4]);
-                if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
-                cnt[s4] += D[s4] < 0.0;
+            for (int u = 0; u < 8; ++u) {
+                const int mm = min(m0 + u, d - 1);
+                av[u] = ta[mm];
+                bv[u] = tb2[mm - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (m0 + u < d) {
+#pragma unroll
+                    for (int s4 = 0; s4 < 2; ++s4) {
+                        double rc = __builtin_amdgcn_rcp(D[s4]);
+                        rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                        rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                        D[s4] = fma(-bv[u], rc, av[u] - sh[s4]);
+                        if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+                        cnt[s4] += D[s4] < 0.0;
+                    }
+                }
             }
         }
         if (i < d) {
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                bsh[i * NSHIFT + q * 4 + s4] = sh[s4];
-                bcnt[i * NSHIFT + q * 4 + s4] = cnt[s4];
+            for (int s4 = 0; s4 < 2; ++s4) {
+                bsh[i * NSHIFT + q * 2 + s4] = sh[s4];
+                bcnt[i * NSHIFT + q * 2 + s4] = cnt[s4];
             }
         }
         __syncthreads();
@@ -624,27 +660,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     }
     if (t < kn) sel[t] = t;
     __syncthreads();
-    // Qu = R_G^{-1} Q_w with Q_w = V[:, sel]: back-substitution, parallel over (row, column)
-    for (int e = t; e < d * kn; e += DT) {
-        const int r = e % d, o = e / d;
-        Wq[r + o * LDS_] = V[r + sel[o] * LDS_];
-    }
-    __syncthreads();
-    for (int c = d - 1; c >= 0; --c) {
-        const double rcc = R[c + c * LDS_];
-        for (int o = t; o < kn; o += DT) Wq[c + o * LDS_] /= rcc;
-        __syncthreads();
-        for (int e = t; e < c * kn; e += DT) {
-            const int r = e % c, o = e / c;
-            Wq[r + o * LDS_] = fma(-R[r + c * LDS_], Wq[c + o * LDS_], Wq[r + o * LDS_]);
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < d * kn; e += DT) {
-        const int r = e % d, o = e / d;
-        coef->Qu[r + o * LDQU] = (r < kc ? Dk[r] : 1.0) * Wq[r + o * LDS_];
-    }
-    // Qc = Q_G [Q_w; 0] (one thread per column, rotations in reverse order)
+    // Qc = Q_G [Q_w; 0], Q_w = V[:, sel]: one lane per column, the rotations of Q_G in reverse order
     if (t < kn) {
         const int o = t, col = sel[o];
         double carry = 0.0;
@@ -656,6 +672,44 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         coef->Qc[kc + o * LDQC] = carry;
         for (int c = 0; c < kc; ++c) coef->Qc[c + o * LDQC] = V[c + col * LDS_];
     }
+    // Qu = R_G^{-1} Q_w by back-substitution, eight lanes per column with lane part p holding rows
+    // 8p..8p+7 in registers (y_i broadcast from its owner); the rows of the recycled part carry D_k
+    {
+        const int o = t >> 3, p = t & 7;
+        const int col = sel[min(o, KMAX - 1)];
+        double y[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 8 * p + s2;
+            y[s2] = (o < kn && r < d) ? V[r + col * LDS_] : 0.0;
+        }
+        for (int i0 = ((d - 1) >> 3) << 3; i0 >= 0; i0 -= 8) {
+            const int owner = i0 >> 3;
+#pragma unroll
+            for (int s1 = 7; s1 >= 0; --s1) {
+                const int i = i0 + s1;
+                if (i < d) {
+                    const double yl = y[s1] * Rd[i];
+                    if (p == owner) y[s1] = yl;
+                    const double yi = __shfl(yl, (t & ~7) | owner, 64);
+#pragma unroll
+                    for (int s2 = 0; s2 < 8; ++s2) {
+                        const int q = 8 * p + s2;
+                        const double rq = R[q + i * LDS_];
+                        y[s2] = (q < i) ? fma(-rq, yi, y[s2]) : y[s2];
+                    }
+                }
+            }
+        }
+        if (o < kn) {
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) {
+                const int r = 8 * p + s2;
+                if (r < d) coef->Qu[r + o * LDQU] = (r < kc ? Dk[r < KMAX ? r : 0] : 1.0) * y[s2];
+            }
+        }
+    }
+    __syncthreads();
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
 }
 

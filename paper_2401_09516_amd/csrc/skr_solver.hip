@@ -11,6 +11,8 @@
 //   B: w -= Q h1, partial Q^T w            (the basis row is loaded once and used twice)
 //   C: w -= Q h2, partial ||w||^2; the last workgroup assembles column j of B and H,
 //      advances the progressive Givens QR of H and decides whether the cycle stops.
+#include <hip/hip_ext.h>
+
 #include "skr_internal.hpp"
 
 namespace skr {
@@ -720,21 +722,26 @@ void launch_zero(hipStream_t s, double* x, int n) {
 }
 static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
 
+// With e0/e1 non-null the launch goes through hipExtLaunchKernelGGL, whose events take the start
+// and end timestamps of the kernel's own dispatch (no marker packets around it).
 template <int NL>
-static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j) {
-    hipLaunchKernelGGL(k_step_a<NL>, dim3(w.nblk), dim3(ROWS), 0, s, op, src, dst, w.basis, w.ld, kc, w.k, j,
-                       w.nblk, (const double*)w.part_n, w.part_a, (const double*)w.red1, (const double*)w.red2,
-                       w.H, w.Bm, w.ctrl);
+static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
+                   hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_step_a<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst, w.basis, w.ld,
+                          kc, w.k, j, w.nblk, (const double*)w.part_n, w.part_a, (const double*)w.red1,
+                          (const double*)w.red2, w.H, w.Bm, w.ctrl);
 }
 template <int NL>
-static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j) {
-    hipLaunchKernelGGL(k_step_b<NL>, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
-                       w.k, j, w.nblk, (const double*)w.part_a, w.part_b, w.red1, (const Ctrl*)w.ctrl);
+static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_step_b<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
+                          w.n, w.ld, kc, w.k, j, w.nblk, (const double*)w.part_a, w.part_b, w.red1,
+                          (const Ctrl*)w.ctrl);
 }
 template <int NL>
-static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j) {
-    hipLaunchKernelGGL(k_step_c<NL>, dim3(w.nblk), dim3(ROWS), 0, s, dst, (const double*)w.basis, w.n, w.ld, kc,
-                       w.k, j, w.nblk, (const double*)w.part_b, w.part_n, w.red2, (const Ctrl*)w.ctrl);
+static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_step_c<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
+                          w.n, w.ld, kc, w.k, j, w.nblk, (const double*)w.part_b, w.part_n, w.red2,
+                          (const Ctrl*)w.ctrl);
 }
 
 #define SKR_DISPATCH8(NLV, CALL)                        \
@@ -749,25 +756,25 @@ static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j) {
         default: CALL(64); break;                       \
     }
 
-// One Arnoldi step (three kernels). With ev != nullptr, hipEvents ev[0..3] bracket the kernels.
+// One Arnoldi step (three kernels). With ev != nullptr, ev[2q], ev[2q+1] take the start and end of
+// kernel q (A, B, C).
 void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle, hipEvent_t* ev) {
     const double* src = (j == 0) ? w.r : w.W[(j - 1) & 1];
     double* dst = w.W[j & 1];
     const int ncol = kc + j + 1;
     const int nla = bucket8(ncol + 1), nlb = bucket8(ncol);
-    if (ev) (void)hipEventRecord(ev[0], s);
-#define CALL_A(NL) step_a<NL>(s, w, op, src, dst, kc, j)
+    hipEvent_t e[6] = {};
+    if (ev)
+        for (int q = 0; q < 6; ++q) e[q] = ev[q];
+#define CALL_A(NL) step_a<NL>(s, w, op, src, dst, kc, j, e[0], e[1])
     SKR_DISPATCH8(nla, CALL_A)
 #undef CALL_A
-    if (ev) (void)hipEventRecord(ev[1], s);
-#define CALL_B(NL) step_b<NL>(s, w, dst, kc, j)
+#define CALL_B(NL) step_b<NL>(s, w, dst, kc, j, e[2], e[3])
     SKR_DISPATCH8(nlb, CALL_B)
 #undef CALL_B
-    if (ev) (void)hipEventRecord(ev[2], s);
-#define CALL_C(NL) step_c<NL>(s, w, dst, kc, j)
+#define CALL_C(NL) step_c<NL>(s, w, dst, kc, j, e[4], e[5])
     SKR_DISPATCH8(nlb, CALL_C)
 #undef CALL_C
-    if (ev) (void)hipEventRecord(ev[3], s);
 }
 void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
     hipLaunchKernelGGL(k_close_basis, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0], (const double*)w.W[1],
