@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--matrix", choices=["csr", "stencil"], default="csr")
+    ap.add_argument("--chains", type=int, default=1,
+                    help="split the sorted order into this many contiguous chains, solved concurrently on "
+                         "their own contexts and streams (the sorted-partition parallel scheme, App. E)")
     ap.add_argument("--gmres-systems", type=int, default=4, help="prefix of the sorted chain solved by GMRES(m)")
     ap.add_argument("--cpu-systems", type=int, default=2, help="oracle sample: first systems of the sorted chain")
     ap.add_argument("--no-cpu", action="store_true")
@@ -126,17 +129,52 @@ def main():
                           "step_source_sha256": step_source_hash()}), flush=True)
         return
 
+    C = max(1, min(a.chains, N))
+    streams = [stream] + [torch.cuda.Stream() for _ in range(C - 1)]
+    ctxs = [ctx] + [skr.skr_ctx_create(0, st.cuda_stream) for st in streams[1:]]
+
+    def solve_chains(order, flags):
+        if C == 1:
+            return skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
+                                          flags=flags)
+        import threading
+        slices = [[int(i) for i in sl] for sl in np.array_split(np.asarray(order), C)]
+        out = [None] * C
+
+        def run(c):
+            try:
+                sl = slices[c]
+                out[c] = skr.skr_solve_sequence(ctxs[c], [ops[i] for i in sl], [bs[i] for i in sl],
+                                                [xs[i] for i in sl], None, m=a.m, k=a.k, rtol=a.rtol,
+                                                maxit=a.maxit, flags=flags)
+            except BaseException as e:   # re-raised in the calling thread
+                out[c] = e
+        th = [threading.Thread(target=run, args=(c,)) for c in range(C)]
+        for t_ in th:
+            t_.start()
+        for t_ in th:
+            t_.join()
+        res = [None] * N
+        rc = 0
+        for c in range(C):
+            if isinstance(out[c], BaseException):
+                raise out[c]
+            rc = max(rc, out[c][0])
+            for i, r in zip(slices[c], out[c][1]):
+                res[i] = r
+        return rc, res
+
     def step(flags):
         order, _ = skr.skr_sort(ctx, Pd, N, p, 0, want_dist=False)
-        rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
-                                         flags=flags)
+        rc, res = solve_chains(order, flags)
         return order, rc, res
 
     for w in range(a.warmup):
         t = time.perf_counter()
         step(0)
         log(f"warmup step {w}: {time.perf_counter() - t:.2f}s")
-    skr.skr_profile_reset(ctx)
+    for c_ in ctxs:
+        skr.skr_profile_reset(c_)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s_ in range(a.steps):
@@ -216,7 +254,8 @@ def main():
         spmv[f"stencil_{a.spmv_grid}"] = dict(us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1),
                                               bytes=byt, frac_hbm=round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3))
         del bops, bbs, bxs, bops2
-    skr.skr_ctx_destroy(ctx)
+    for c_ in ctxs:
+        skr.skr_ctx_destroy(c_)
 
     cpu = None
     if not a.no_cpu and a.cpu_systems > 0:
@@ -248,9 +287,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"darcy2d-{a.grid}x{a.grid}-{a.systems}sys-sorted-gcrodr({a.m},{a.k})-{a.matrix}",
+        "config": {"workload": f"darcy2d-{a.grid}x{a.grid}-{a.systems}sys-sorted-gcrodr({a.m},{a.k})-{a.matrix}"
+                               + (f"-{C}chains" if C > 1 else ""),
                    "grid": a.grid, "n": systems[0].n, "nnz": nnz, "systems": a.systems, "m": a.m, "k": a.k,
-                   "rtol": a.rtol, "matrix": a.matrix, "parallelism": "single chain"},
+                   "rtol": a.rtol, "matrix": a.matrix, "chains": C,
+                   "parallelism": "single chain" if C == 1 else f"{C} contiguous chains of the sorted order, "
+                                                                 "one stream each"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "converged": converged,

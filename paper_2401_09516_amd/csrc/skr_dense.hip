@@ -243,6 +243,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     __shared__ double ta[DMAX], tb[DMAX], tb2[DMAX], hb[DMAX], hv0[DMAX], hP[DMAX];
     __shared__ double blo[DMAX], bhi[DMAX], lam[DMAX], lsel[KMAX], hsig[1], hkp[DT / 64];
     __shared__ double bsh[DMAX * NSHIFT];
+    __shared__ double junk[DT];
     __shared__ int bcnt[DMAX * NSHIFT];
     __shared__ int sel[KMAX];
     __shared__ int nsel_s, sym_s, need2_s, fail_s;
@@ -272,14 +273,18 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
             for (int s1 = 0; s1 < 16; ++s1) {
                 const int c = c0 + s1;
                 if (c < d) {
+                    // loads first and a masked coefficient instead of a branch, so that nothing
+                    // waits on an LDS load inside a divergent block
+                    double rc[16];
+#pragma unroll
+                    for (int s2 = 0; s2 < 16; ++s2) rc[s2] = R[c + (16 * p + s2) * LDS_];
                     const double ml = acc[s1] * Rd[c];
-                    if (p == owner) acc[s1] = ml;
+                    acc[s1] = (p == owner) ? ml : acc[s1];
                     const double mc = __shfl(ml, (t & ~3) | owner, 64);
 #pragma unroll
                     for (int s2 = 0; s2 < 16; ++s2) {
-                        const int c2 = 16 * p + s2;
-                        const double rc = R[c + c2 * LDS_];
-                        acc[s2] = (c2 > c) ? fma(-mc, rc, acc[s2]) : acc[s2];
+                        const double f = (16 * p + s2 > c) ? mc : 0.0;
+                        acc[s2] = fma(-f, rc[s2], acc[s2]);
                     }
                 }
             }
@@ -368,11 +373,9 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int c = j1 + q + 4 * u;
-                    const double vc = (c == j1) ? v0 : vv[u];
-                    if (c < d) {
-                        if (u & 1) acc1 = fma(sv[u], vc, acc1);
-                        else acc0 = fma(sv[u], vc, acc0);
-                    }
+                    const double vc = (c == j1) ? v0 : ((c < d) ? vv[u] : 0.0);
+                    if (u & 1) acc1 = fma(sv[u], vc, acc1);
+                    else acc0 = fma(sv[u], vc, acc0);
                 }
                 double acc = acc0 + acc1;
                 acc += __shfl_xor(acc, 1, 64);
@@ -400,11 +403,11 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int c = j1 + (t >> 6) + 4 * u;
-                    if (r < d && c < d) {
-                        const double vcc = (c == j1) ? v0 : vc[u];
-                        const double wc = fma(-K, vcc, pc[u]);
-                        S[r + c * LDS_] = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
-                    }
+                    const double vcc = (c == j1) ? v0 : vc[u];
+                    const double wc = fma(-K, vcc, pc[u]);
+                    const double nv = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
+                    double* dst = (r < d && c < d) ? &S[r + c * LDS_] : &junk[t];
+                    *dst = nv;
                 }
             }
         }
@@ -491,11 +494,17 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         __syncthreads();
         int open = 0;
         if (q == 0 && i < d) {
-            double nl = lo, nh = hi;
-            for (int p2 = 0; p2 < NSHIFT; ++p2)
-                if (bcnt[i * NSHIFT + p2] <= i) nl = bsh[i * NSHIFT + p2];
-            for (int p2 = NSHIFT - 1; p2 >= 0; --p2)
-                if (bcnt[i * NSHIFT + p2] > i) nh = bsh[i * NSHIFT + p2];
+            double nl = lo, nh = hi, shv[NSHIFT];
+            int cv[NSHIFT];
+#pragma unroll
+            for (int p2 = 0; p2 < NSHIFT; ++p2) {
+                shv[p2] = bsh[i * NSHIFT + p2];
+                cv[p2] = bcnt[i * NSHIFT + p2];
+            }
+#pragma unroll
+            for (int p2 = 0; p2 < NSHIFT; ++p2) nl = (cv[p2] <= i) ? shv[p2] : nl;
+#pragma unroll
+            for (int p2 = NSHIFT - 1; p2 >= 0; --p2) nh = (cv[p2] > i) ? shv[p2] : nh;
             if (nh < nl) nh = nl;
             blo[i] = nl;
             bhi[i] = nh;
@@ -585,7 +594,8 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         for (int i = 0; i < 8; ++i) {
             const int r = part + 8 * i;
             const double sv = S[min(r, d - 1) + j * LDS_];
-            vr[i] = (r == j + 1) ? v0 : ((r > j + 1 && r < d) ? sv : 0.0);
+            const double m1 = (r > j + 1 && r < d) ? 1.0 : 0.0, m0 = (r == j + 1) ? 1.0 : 0.0;
+            vr[i] = fma(m1, sv, m0 * v0);
         }
         double dt0 = 0.0, dt1 = 0.0;
 #pragma unroll
@@ -646,10 +656,9 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
             dot += __shfl_xor(dot, 1, 64);
             dot += __shfl_xor(dot, 2, 64);
             dot += __shfl_xor(dot, 4, 64);
-            if (zc > j && zc < kn) {
+            const double f = (zc > j && zc < kn) ? dot : 0.0;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) zr[i] = fma(-dot, qv[i], zr[i]);
-            }
+            for (int i = 0; i < 8; ++i) zr[i] = fma(-f, qv[i], zr[i]);
         }
         __syncthreads();
         if (fail_s || !need2_s) break;
@@ -689,14 +698,16 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
             for (int s1 = 7; s1 >= 0; --s1) {
                 const int i = i0 + s1;
                 if (i < d) {
+                    double rq[8];
+#pragma unroll
+                    for (int s2 = 0; s2 < 8; ++s2) rq[s2] = R[8 * p + s2 + i * LDS_];
                     const double yl = y[s1] * Rd[i];
-                    if (p == owner) y[s1] = yl;
+                    y[s1] = (p == owner) ? yl : y[s1];
                     const double yi = __shfl(yl, (t & ~7) | owner, 64);
 #pragma unroll
                     for (int s2 = 0; s2 < 8; ++s2) {
-                        const int q = 8 * p + s2;
-                        const double rq = R[q + i * LDS_];
-                        y[s2] = (q < i) ? fma(-rq, yi, y[s2]) : y[s2];
+                        const double f = (8 * p + s2 < i) ? yi : 0.0;
+                        y[s2] = fma(-f, rq[s2], y[s2]);
                     }
                 }
             }

@@ -109,10 +109,10 @@ __device__ __forceinline__ void block_partials(double s, double* sh, double* par
 // least-squares residual estimate |g_{jj+1}|. Run by wave 0 of every calling workgroup on identical
 // inputs, so all get identical results; only the writer workgroup stores the column, the new
 // rotation and g_{jj+1}. Only the running entry of the rotated column is needed: after rotation q
-// it is a_{q+1} = -sn_q a_q + cs_q col[q+1], with lane q holding (cs_q, sn_q, col[q+1]).
+// it is a_{q+1} = -sn_q a_q + cs_q col[q+1], run by lane 0 from LDS copies (shc, 3 x 64 doubles).
 __device__ __forceinline__ double close_step(int jj, int kc, double tot, const double* __restrict__ h1,
                                              const double* __restrict__ h2, double* H, double* Bm, Ctrl* ctrl,
-                                             bool writer, int& brk_out, double& hnorm_out) {
+                                             bool writer, int& brk_out, double& hnorm_out, double* shc) {
     const int t = threadIdx.x;
     const int ncol = kc + jj + 1;
     const double hnorm = sqrt(tot);
@@ -126,15 +126,17 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
         if (t <= jj) H[t + jj * LDH] = colt;
         if (t == 0) H[jj + 1 + jj * LDH] = hlast;
     }
-    const double up = __shfl(colt, (t + 1) & 63, 64);
-    const double cnext = (t < jj) ? up : (t == jj ? hlast : 0.0);
-    const double cs_t = (t < jj) ? ctrl->cs[t] : 0.0;
-    const double sn_t = (t < jj) ? ctrl->sn[t] : 0.0;
-    double a = __shfl(colt, 0, 64);
-    for (int q = 0; q < jj; ++q) {
-        const double mq = __shfl(sn_t, q, 64), cq = __shfl(cs_t, q, 64), bq = __shfl(cnext, q, 64);
-        a = fma(-mq, a, cq * bq);
+    shc[t] = colt;
+    shc[64 + t] = (t < jj) ? ctrl->cs[t] : 0.0;
+    shc[128 + t] = (t < jj) ? ctrl->sn[t] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    double a = 0.0;
+    if (t == 0) {
+        a = shc[0];
+        for (int q = 0; q < jj; ++q) a = fma(-shc[128 + q], a, shc[64 + q] * shc[q + 1]);
     }
+    a = __shfl(a, 0, 64);
     const double rho = hypot(a, hlast);
     const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? hlast / rho : 0.0;
     const double gj = ctrl->g[jj];
@@ -174,6 +176,10 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     const int ii = valid ? i : n - 1;
     const int ncol = kc + j + 1;
     const int nst = ncol - 1;                 // stored columns (v_j itself is formed here)
+    // Every global load of the kernel is issued before the first decision that waits on one: the
+    // stop flag, the basis rows, the product with the unscaled previous vector (A is linear, so the
+    // scale is applied afterwards) and the partials of ||w||^2.
+    const int stopped = ctrl->stop;
     double q[NL];
     if (nst > 0) {
 #pragma unroll
@@ -182,8 +188,31 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 #pragma unroll
         for (int c = 0; c < NL; ++c) q[c] = 0.0;
     }
-    if (ctrl->stop) return;   // checked after the loads are issued so that the two latencies overlap
-    const double tot = sum_partials1(part_n, nblk, sh);
+    double pn[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool few = nblk <= 4 * 64;
+    if (few && threadIdx.x < 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = threadIdx.x + 64 * u;
+            pn[u] = (b < nblk) ? part_n[b] : 0.0;
+        }
+    }
+    const double xi = src[ii];
+    const double wraw = op_row(op, src, ii, 1.0);
+    if (stopped) return;
+    double tot;
+    if (few) {
+        // same order as sum_partials1: lane-strided sums, then the wave butterfly
+        if (threadIdx.x < 64) {
+            const double ws = wave_sum(((pn[0] + pn[1]) + pn[2]) + pn[3]);
+            if (threadIdx.x == 0) sh[0] = ws;
+        }
+        __syncthreads();
+        tot = sh[0];
+        __syncthreads();
+    } else {
+        tot = sum_partials1(part_n, nblk, sh);
+    }
     if (j == 0) {
         if (threadIdx.x == 0) {
             const double bt = sqrt(tot);
@@ -198,7 +227,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     } else if (threadIdx.x < 64) {
         int brk;
         double hn;
-        const double est = close_step(j - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn);
+        const double est = close_step(j - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn, sh + 64);
         if (threadIdx.x == 0) {
             const int stop = (brk || !(est > ctrl->tol_abs)) ? 1 : 0;
             s_stop = stop;
@@ -216,8 +245,8 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     __syncthreads();
     if (s_stop) return;
     const double scale = s_scale;
-    const double vj = src[ii] * scale;
-    double w = op_row(op, src, ii, scale);
+    const double vj = xi * scale;
+    double w = wraw * scale;
     if (valid) {
         basis[(size_t)(vbase + j) * ld + i] = vj;
         dst[i] = w;
@@ -253,8 +282,9 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
 #pragma unroll
     for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
-    if (ctrl->stop) return;
+    const int stopped = ctrl->stop;
     sum_partials(part_a, nblk, ncol + 1, sh, hs);
+    if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
     for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
@@ -284,8 +314,9 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
 #pragma unroll
     for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
-    if (ctrl->stop) return;
+    const int stopped = ctrl->stop;
     sum_partials(part_b, nblk, ncol, sh, hs);
+    if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x < ncol) red2[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
     for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
@@ -310,7 +341,7 @@ __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__
         if (threadIdx.x < 64) {
             int brk;
             double hn;
-            close_step(s_cycle - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn);
+            close_step(s_cycle - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn, sh + 64);
             if (threadIdx.x == 0) {
                 s_jd = s_cycle;
                 s_brk = brk;
