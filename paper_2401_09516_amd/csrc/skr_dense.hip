@@ -19,15 +19,16 @@ namespace skr {
 constexpr int LDG = DMAX + 1;   // leading dimension of G and X/M in LDS
 constexpr int LDW = DMAX + 1;   // leading dimension of the eigenvector / Q_w / Qu work arrays
 
-__device__ __forceinline__ double wave_sum64(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+__device__ __forceinline__ double wave_sum64(double x) { return wave_sum(x); }
+__device__ __forceinline__ double wave_max64(double x) { return wave_max(x); }
+// Sums over aligned groups of 4 and 8 lanes (every lane of a group gets the same bits).
+__device__ __forceinline__ double group4_sum(double x) {
+    x += row_partner<1>(x);
+    return x + row_partner<2>(x);
 }
-__device__ __forceinline__ double wave_max64(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-    return x;
+__device__ __forceinline__ double group8_sum(double x) {
+    x = group4_sum(x);
+    return x + row_partner<4>(x);
 }
 
 // Copy a rows x cols column-major block from global (leading dimension lds) to LDS (leading
@@ -378,8 +379,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
                     else acc0 = fma(sv[u], vc, acc0);
                 }
                 double acc = acc0 + acc1;
-                acc += __shfl_xor(acc, 1, 64);
-                acc += __shfl_xor(acc, 2, 64);
+                acc = group4_sum(acc);
                 const double pr = beta * acc;
                 const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
                 const double kp = wave_sum64((q == 0 && r < d) ? pr * vr : 0.0);
@@ -601,9 +601,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
         for (int i = 0; i < 8; i += 2) { dt0 = fma(vr[i], zr[i], dt0); dt1 = fma(vr[i + 1], zr[i + 1], dt1); }
         double dot = dt0 + dt1;
-        dot += __shfl_xor(dot, 1, 64);
-        dot += __shfl_xor(dot, 2, 64);
-        dot += __shfl_xor(dot, 4, 64);
+        dot = group8_sum(dot);
         dot *= beta;
 #pragma unroll
         for (int i = 0; i < 8; ++i) zr[i] = fma(-dot, vr[i], zr[i]);
@@ -614,9 +612,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
         for (int i = 0; i < 8; i += 2) { a0 = fma(zr[i], zr[i], a0); a1 = fma(zr[i + 1], zr[i + 1], a1); }
         n0 = a0 + a1;
-        n0 += __shfl_xor(n0, 1, 64);
-        n0 += __shfl_xor(n0, 2, 64);
-        n0 += __shfl_xor(n0, 4, 64);
+        n0 = group8_sum(n0);
         n0 = sqrt(n0);
     }
     for (int pass = 0; pass < 2; ++pass) {
@@ -625,9 +621,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
             for (int i = 0; i < 8; i += 2) { a0 = fma(zr[i], zr[i], a0); a1 = fma(zr[i + 1], zr[i + 1], a1); }
             double nr = a0 + a1;
-            nr += __shfl_xor(nr, 1, 64);
-            nr += __shfl_xor(nr, 2, 64);
-            nr += __shfl_xor(nr, 4, 64);
+            nr = group8_sum(nr);
             nr = sqrt(nr);
             if (zc == j) {
                 if (pass == 0) {
@@ -653,9 +647,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
 #pragma unroll
             for (int i = 0; i < 8; i += 2) { d0 = fma(qv[i], zr[i], d0); d1 = fma(qv[i + 1], zr[i + 1], d1); }
             double dot = d0 + d1;
-            dot += __shfl_xor(dot, 1, 64);
-            dot += __shfl_xor(dot, 2, 64);
-            dot += __shfl_xor(dot, 4, 64);
+            dot = group8_sum(dot);
             const double f = (zc > j && zc < kn) ? dot : 0.0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) zr[i] = fma(-f, qv[i], zr[i]);

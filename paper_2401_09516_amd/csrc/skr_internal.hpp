@@ -119,45 +119,143 @@ constexpr int LDQU = KMAX + MMAX + 1;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// ---------------------------------------------------------------------------------------------
+// Cross-lane exchanges without the LDS crossbar. A double moves as two 32-bit halves.
+//  * swap32(a, b): v_permlane32_swap: r0 = (a in lanes 0-31 | b of lanes 0-31 in lanes 32-63),
+//    r1 = (a of lanes 32-63 in lanes 0-31 | b in lanes 32-63). With a = the values a lane keeps when
+//    it is in the lower half and b = those it keeps when in the upper half, r0 + r1 is, in every
+//    lane, its kept value plus the partner's (lane l ^ 32) value of the same column.
+//  * swap16: the same between the 16-lane rows 0<->1 and 2<->3 (partner l ^ 16).
+//  * DPP row_ror:8 (partner l ^ 8), row_half_mirror (partner 7 - (l % 8) in each group of 8),
+//    quad_perm (partners l ^ 2, l ^ 1).
+// Every stage adds a value and its partner's, and addition commutes, so both partners hold the
+// same bits: the reductions are deterministic and identical in every lane that holds a result.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void swap32_f64(double a, double b, double& r0, double& r1) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    r0 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    r1 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16_f64(double a, double b, double& r0, double& r1) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    r0 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    r1 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Value of the first active lane (lane 0 when the whole wavefront is active), in every lane.
+__device__ __forceinline__ double first_lane(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+constexpr int DPP_ROW_ROR8 = 0x128, DPP_ROW_HALF_MIRROR = 0x141, DPP_QP_XOR2 = 0x4E, DPP_QP_XOR1 = 0xB1;
+
+// Partner value at a stage whose partner lies inside a 16-lane row (HALF = 8, 4, 2, 1).
+template <int HALF>
+__device__ __forceinline__ double row_partner(double x) {
+    if constexpr (HALF == 8) return dpp_f64<DPP_ROW_ROR8>(x);
+    else if constexpr (HALF == 4) return dpp_f64<DPP_ROW_HALF_MIRROR>(x);
+    else if constexpr (HALF == 2) return dpp_f64<DPP_QP_XOR2>(x);
+    else return dpp_f64<DPP_QP_XOR1>(x);
+}
+
+// Sum over the wavefront; every lane gets the same bits.
+__device__ __forceinline__ double wave_sum(double x) {
+    double r0, r1;
+    swap32_f64(x, x, r0, r1);
+    x = r0 + r1;
+    swap16_f64(x, x, r0, r1);
+    x = r0 + r1;
+    x += row_partner<8>(x);
+    x += row_partner<4>(x);
+    x += row_partner<2>(x);
+    x += row_partner<1>(x);
+    return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+    double r0, r1;
+    swap32_f64(x, x, r0, r1);
+    x = fmax(r0, r1);
+    swap16_f64(x, x, r0, r1);
+    x = fmax(r0, r1);
+    x = fmax(x, row_partner<8>(x));
+    x = fmax(x, row_partner<4>(x));
+    x = fmax(x, row_partner<2>(x));
+    x = fmax(x, row_partner<1>(x));
+    return x;
+}
+
 // Butterfly reduce-scatter over one wavefront of NR (a power of two <= 64) column values per lane:
-// on return lane l holds the wave-wide sum of column (l mod NR) in v[0]. Offsets >= NR are plain
-// all-reduce stages; the remaining stages halve the columns each lane keeps. The order of additions
-// is fixed, so results are bitwise reproducible. Every register index is a compile-time constant.
+// on return lane l holds the wave-wide sum of column (l mod NR) in v[0]. Stages with HALF >= NR
+// are plain all-reduce stages; the remaining stages halve the columns each lane keeps (a lane whose
+// HALF bit is set keeps the upper half). The order of additions is fixed, so results are bitwise
+// reproducible. Every register index is a compile-time constant.
 template <int HALF, int NR>
 __device__ __forceinline__ void rs_stage(double (&v)[NR], int lane) {
-    const bool upper = (lane & HALF) != 0;
+    if constexpr (HALF >= 16) {
 #pragma unroll
-    for (int i = 0; i < HALF; ++i) {
-        const double send = upper ? v[i] : v[i + HALF];
-        const double keep = upper ? v[i + HALF] : v[i];
-        v[i] = keep + __shfl_xor(send, HALF, 64);
+        for (int i = 0; i < HALF; ++i) {
+            double r0, r1;
+            if constexpr (HALF == 32) swap32_f64(v[i], v[i + HALF], r0, r1);
+            else swap16_f64(v[i], v[i + HALF], r0, r1);
+            v[i] = r0 + r1;
+        }
+    } else {
+        const bool upper = (lane & HALF) != 0;
+#pragma unroll
+        for (int i = 0; i < HALF; ++i) {
+            const double send = upper ? v[i] : v[i + HALF];
+            const double keep = upper ? v[i + HALF] : v[i];
+            v[i] = keep + row_partner<HALF>(send);
+        }
+    }
+}
+
+template <int OFF, int NR>
+__device__ __forceinline__ void allreduce_stage(double (&v)[NR]) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        double r0, r1;
+        if constexpr (OFF == 32) swap32_f64(v[i], v[i], r0, r1);
+        else swap16_f64(v[i], v[i], r0, r1);
+        v[i] = r0 + r1;
     }
 }
 
 template <int NR>
 __device__ __forceinline__ double wave_reduce_scatter(double (&v)[NR]) {
+    static_assert(NR >= 16, "reduction widths are 16, 32 or 64");
     const int lane = lane_id();
-#pragma unroll
-    for (int off = 32; off >= NR; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) v[i] += __shfl_xor(v[i], off, 64);
+    if constexpr (NR <= 16) {
+        allreduce_stage<32, NR>(v);
+        allreduce_stage<16, NR>(v);
+    } else if constexpr (NR == 32) {
+        allreduce_stage<32, NR>(v);
     }
     if constexpr (NR >= 64) rs_stage<32, NR>(v, lane);
     if constexpr (NR >= 32) rs_stage<16, NR>(v, lane);
-    if constexpr (NR >= 16) rs_stage<8, NR>(v, lane);
-    if constexpr (NR >= 8) rs_stage<4, NR>(v, lane);
-    if constexpr (NR >= 4) rs_stage<2, NR>(v, lane);
-    if constexpr (NR >= 2) rs_stage<1, NR>(v, lane);
+    rs_stage<8, NR>(v, lane);
+    rs_stage<4, NR>(v, lane);
+    rs_stage<2, NR>(v, lane);
+    rs_stage<1, NR>(v, lane);
     return v[0];
 }
 
 __device__ __forceinline__ double wave_reduce_scatter64(double (&v)[NC]) { return wave_reduce_scatter<NC>(v); }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
 
 // Arrive at the end of a grid-wide reduction. Returns true in exactly one workgroup, the last
 // one to arrive, after which it may read every workgroup's partials. The caller's partial stores

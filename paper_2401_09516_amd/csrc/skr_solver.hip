@@ -136,7 +136,7 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
         a = shc[0];
         for (int q = 0; q < jj; ++q) a = fma(-shc[128 + q], a, shc[64 + q] * shc[q + 1]);
     }
-    a = __shfl(a, 0, 64);
+    a = first_lane(a);
     const double rho = hypot(a, hlast);
     const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? hlast / rho : 0.0;
     const double gj = ctrl->g[jj];
