@@ -453,7 +453,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
             launch_cycle_dense(s, w, kc, scyc, k);
             // the new recycle size is at most k (0 when no recycle space is formed this cycle)
             const bool forms = k > 0 && (kc > 0 || scyc > k);
-            launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : (k + 7) / 8 * 8) : 0);
+            launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : 32) : 0);
             HIPLAUNCHCHK();
             if ((rc = read_ctrl(ctx))) return rc;
             const int jd = hc.j_done;

@@ -376,7 +376,6 @@ struct ColList {
 constexpr int GCHUNK = 32;               // rows staged per LDS chunk
 constexpr int GL_MAX = 2 * KMAX + MMAX + 2;   // max columns on the left
 constexpr int GR_MAX = KMAX + 1;              // max columns on the right
-constexpr int GQ = (GL_MAX * GR_MAX + ROWS - 1) / ROWS;
 
 __device__ __forceinline__ const double* col_of(const ColList& L, int a, int ld) {
     int base = 0;
@@ -388,72 +387,93 @@ __device__ __forceinline__ const double* col_of(const ColList& L, int a, int ld)
     return nullptr;
 }
 
+// Block partial of L^T R over rows [r0, r1) on the FP64 matrix cores. The output is cut into 16 x 16
+// tiles (TA x TB); each wave takes a quarter of the block's rows and accumulates every tile with
+// v_mfma_f64_16x16x4f64, four rows per instruction, so each loaded operand feeds TB (A) or TA (B)
+// instructions. Operand layout of that instruction: lane l holds A[l % 16][l / 16] (here
+// L[row + l / 16][16 ta + l % 16]) and B[l / 16][l % 16] (R[row + l / 16][16 tb + l % 16]); item t of the
+// result holds D[4 t + l / 16][l % 16]. Operands of four row steps are loaded while the previous four
+// are multiplied; rows past the block end are zeroed in A. The four waves' tiles are added in LDS
+// in a fixed order at the end.
+typedef double skr_d4 __attribute__((ext_vector_type(4)));
+template <int TA, int TB>
 __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColList R, int nr, int n, int ld,
                                                        int rows_per_block, double* __restrict__ gpart) {
-    __shared__ double Ls[GL_MAX * (GCHUNK + 1)];
-    __shared__ double Rs[GR_MAX * (GCHUNK + 1)];
+    constexpr int NT = TA * TB, KS = NT > 12 ? 2 : 4;   // row steps (of 4 rows) per operand batch
+    __shared__ double red[(NWAVE - 1) * NT * 4 * 64];
+    const int w = wave_id(), l = lane_id();
+    const int rsub = l >> 4, csub = l & 15;
     const int r0 = blockIdx.x * rows_per_block;
     const int r1 = min(n, r0 + rows_per_block);
-    const int E = nl * nr;
-    double acc[GQ];
+    const int per = (rows_per_block / NWAVE + 3) / 4 * 4;
+    const int w0 = r0 + w * per, w1 = min(r1, w0 + per);
+    const double* lp[TA];
+    const double* rp[TB];
 #pragma unroll
-    for (int q = 0; q < GQ; ++q) acc[q] = 0.0;
-    for (int c0 = r0; c0 < r1; c0 += GCHUNK) {
-        const int rows = min(GCHUNK, r1 - c0);
-        __syncthreads();
-        // stage the chunk: each thread loads up to GST values with all loads in flight together
-        {
-            constexpr int GST = (GL_MAX * GCHUNK + ROWS - 1) / ROWS;
-            double vl[GST];
+    for (int ta = 0; ta < TA; ++ta) lp[ta] = col_of(L, min(16 * ta + csub, nl - 1), ld);
 #pragma unroll
-            for (int u = 0; u < GST; ++u) {
-                const int e = threadIdx.x + u * ROWS;
-                const int a = e / GCHUNK, rr = e - a * GCHUNK;
-                vl[u] = (e < nl * GCHUNK && rr < rows) ? col_of(L, a, ld)[c0 + rr] : 0.0;
-            }
+    for (int tb = 0; tb < TB; ++tb) rp[tb] = col_of(R, min(16 * tb + csub, nr - 1), ld);
+    skr_d4 acc[TA][TB];
 #pragma unroll
-            for (int u = 0; u < GST; ++u) {
-                const int e = threadIdx.x + u * ROWS;
-                if (e < nl * GCHUNK) {
-                    const int a = e / GCHUNK, rr = e - a * GCHUNK;
-                    Ls[a * (GCHUNK + 1) + rr] = vl[u];
-                }
-            }
-            constexpr int GSR = (GR_MAX * GCHUNK + ROWS - 1) / ROWS;
-            double vr[GSR];
+    for (int ta = 0; ta < TA; ++ta)
 #pragma unroll
-            for (int u = 0; u < GSR; ++u) {
-                const int e = threadIdx.x + u * ROWS;
-                const int a = e / GCHUNK, rr = e - a * GCHUNK;
-                vr[u] = (e < nr * GCHUNK && rr < rows) ? col_of(R, a, ld)[c0 + rr] : 0.0;
-            }
+        for (int tb = 0; tb < TB; ++tb) acc[ta][tb] = skr_d4{0.0, 0.0, 0.0, 0.0};
+    double av[KS][TA], bv[KS][TB];
+    auto fetch = [&](int row0) {
 #pragma unroll
-            for (int u = 0; u < GSR; ++u) {
-                const int e = threadIdx.x + u * ROWS;
-                if (e < nr * GCHUNK) {
-                    const int a = e / GCHUNK, rr = e - a * GCHUNK;
-                    Rs[a * (GCHUNK + 1) + rr] = vr[u];
-                }
-            }
+        for (int u = 0; u < KS; ++u) {
+            const int row = row0 + 4 * u + rsub;
+            const int rc = min(row, r1 - 1);
+#pragma unroll
+            for (int ta = 0; ta < TA; ++ta) av[u][ta] = lp[ta][rc];
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb) bv[u][tb] = rp[tb][rc];
         }
-        __syncthreads();
+    };
+    if (w0 < w1) fetch(w0);
+    for (int row0 = w0; row0 < w1; row0 += 4 * KS) {
+        double ac[KS][TA], bc[KS][TB];
 #pragma unroll
-        for (int q = 0; q < GQ; ++q) {
-            const int e = threadIdx.x + q * ROWS;
-            if (e < E) {
-                const int a = e / nr, b = e - a * nr;
-                const double* lp = Ls + a * (GCHUNK + 1);
-                const double* rp = Rs + b * (GCHUNK + 1);
-                double s = acc[q];
-                for (int rr = 0; rr < GCHUNK; ++rr) s = fma(lp[rr], rp[rr], s);
-                acc[q] = s;
-            }
+        for (int u = 0; u < KS; ++u) {
+            const bool rok = row0 + 4 * u + rsub < w1;
+#pragma unroll
+            for (int ta = 0; ta < TA; ++ta) ac[u][ta] = rok ? av[u][ta] : 0.0;
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb) bc[u][tb] = bv[u][tb];
         }
+        if (row0 + 4 * KS < w1) fetch(row0 + 4 * KS);
+#pragma unroll
+        for (int u = 0; u < KS; ++u)
+#pragma unroll
+            for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < TB; ++tb)
+                    acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u][ta], bc[u][tb], acc[ta][tb], 0, 0, 0);
     }
+    // waves 1..3 hand their tiles to wave 0, which adds them in wave order and stores the partial
+    if (w > 0) {
 #pragma unroll
-    for (int q = 0; q < GQ; ++q) {
-        const int e = threadIdx.x + q * ROWS;
-        if (e < E) gpart[(size_t)blockIdx.x * E + e] = acc[q];
+        for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                for (int i2 = 0; i2 < 4; ++i2) red[(((w - 1) * NT + ta * TB + tb) * 4 + i2) * 64 + l] = acc[ta][tb][i2];
+    }
+    __syncthreads();
+    if (w == 0) {
+        const int E = nl * nr;
+#pragma unroll
+        for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                for (int i2 = 0; i2 < 4; ++i2) {
+                    double v = acc[ta][tb][i2];
+#pragma unroll
+                    for (int q = 1; q < NWAVE; ++q) v += red[(((q - 1) * NT + ta * TB + tb) * 4 + i2) * 64 + l];
+                    const int a = 16 * ta + 4 * i2 + rsub, b = 16 * tb + csub;
+                    if (a < nl && b < nr) gpart[(size_t)blockIdx.x * E + a * nr + b] = v;
+                }
     }
 }
 
@@ -495,6 +515,12 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
 // the new recycle size (0, 8, 16, 24 or 32). The partials of ||r_new||^2 are left for the next
 // cycle's first pass A.
 // ---------------------------------------------------------------------------------------------
+// Cycle update in one pass over the basis rows: [C_new | U_new | dx | dr] = [C U V] W, then
+// x += dx, r += dr (W carries the signs), the new C and U overwrite the old, and the partials of
+// ||r||^2 are written for the next cycle. W (ncl x NO, row q = input column q) is gathered into LDS:
+// every entry is one load from the flat coefficient block at an index chosen by integer selects, so
+// no load sits inside a divergent branch. Input columns are read in batches of 16, the next batch
+// loading while the current one is applied.
 template <int KB>
 __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ basis, double* __restrict__ U,
@@ -502,36 +528,43 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
                                                        double* part_n, Ctrl* ctrl) {
     constexpr int NO = 2 * KB + 2;
     constexpr int MAXQ = 2 * KMAX + MMAX + 1;
+    constexpr int OQC = offsetof(Coef, Qc) / sizeof(double), OQU = offsetof(Coef, Qu) / sizeof(double);
+    constexpr int OYU = offsetof(Coef, yU) / sizeof(double), OYV = offsetof(Coef, yV) / sizeof(double);
+    constexpr int ORC = offsetof(Coef, rC) / sizeof(double), ORV = offsetof(Coef, rV) / sizeof(double);
     __shared__ double Wc[MAXQ * NO];
     __shared__ double sh[NWAVE * NC];
     const int jd = ctrl->j_done, brk = ctrl->breakdown, kn = ctrl->k_new;
     const int nv = jd + (brk ? 0 : 1);     // V columns of W-hat (v_{jd} is zero after a breakdown)
     const int ncl = 2 * kc + nv;           // input columns: C (kc), U (kc), V (nv)
-    // build W: eight global loads in flight per thread
+    const double* cf = reinterpret_cast<const double*>(coef);
     for (int e0 = 0; e0 < ncl * NO; e0 += 8 * ROWS) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * ROWS + threadIdx.x;
             const int q = e / NO, o = e - q * NO;
-            double val = 0.0;
-            if (e < ncl * NO) {
-                if (q < kc) {                                    // C column q
-                    if (o < KB) val = o < kn ? coef->Qc[q + o * LDQC] : 0.0;
-                    else if (o == 2 * KB + 1) val = -coef->rC[q];
-                } else if (q < 2 * kc) {                         // U column c
-                    const int c = q - kc;
-                    if (o >= KB && o < 2 * KB) val = (o - KB) < kn ? coef->Qu[c + (o - KB) * LDQU] : 0.0;
-                    else if (o == 2 * KB) val = coef->yU[c];
-                } else {                                         // V column t
-                    const int t = q - 2 * kc;
-                    if (o < KB) val = o < kn ? coef->Qc[kc + t + o * LDQC] : 0.0;
-                    else if (o < 2 * KB) val = (t < jd && (o - KB) < kn) ? coef->Qu[kc + t + (o - KB) * LDQU] : 0.0;
-                    else if (o == 2 * KB) val = t < jd ? coef->yV[t] : 0.0;
-                    else val = -coef->rV[t];
-                }
+            const bool inC = q < kc, inU = !inC && q < 2 * kc;
+            const int c = q - kc, t = q - 2 * kc;
+            const bool oC = o < KB, oU = o >= KB && o < 2 * KB, oX = o == 2 * KB, oR = o == 2 * KB + 1;
+            int idx = 0;
+            bool ok = false;
+            double sg = 1.0;
+            if (inC) {
+                idx = oC ? OQC + q + o * LDQC : ORC + q;
+                ok = (oC && o < kn) || oR;
+                sg = oR ? -1.0 : 1.0;
+            } else if (inU) {
+                idx = oU ? OQU + c + (o - KB) * LDQU : OYU + c;
+                ok = (oU && (o - KB) < kn) || oX;
+            } else {
+                idx = oC ? OQC + kc + t + o * LDQC
+                         : (oU ? OQU + kc + t + (o - KB) * LDQU : (oX ? OYV + t : ORV + t));
+                ok = (oC && o < kn) || (oU && t < jd && (o - KB) < kn) || (oX && t < jd) || oR;
+                sg = oR ? -1.0 : 1.0;
             }
-            v[u] = val;
+            ok = ok && e < ncl * NO;
+            const double ld_ = cf[ok ? idx : 0];
+            v[u] = ok ? sg * ld_ : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -548,23 +581,27 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
     const double xi = x[ii], ri = r[ii];
-    for (int q0 = 0; q0 < ncl; q0 += 16) {
-        double v[16];
+    auto colp = [&](int q) {
+        return q < kc ? basis + (size_t)q * ld
+                      : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
+    };
+    double vb[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = min(q0 + u, ncl - 1);
-            const double* colp = q < kc ? basis + (size_t)q * ld
-                                        : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
-            v[u] = colp[ii];
-        }
+    for (int u = 0; u < 16; ++u) vb[u] = colp(min(u, ncl - 1))[ii];
+    for (int q0 = 0; q0 < ncl; q0 += 16) {
+        double vn[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) vn[u] = colp(min(q0 + 16 + u, ncl - 1))[ii];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             if (q0 + u < ncl) {
                 const double* wrow = Wc + (q0 + u) * NO;
 #pragma unroll
-                for (int o = 0; o < NO; ++o) acc[o] = fma(v[u], wrow[o], acc[o]);
+                for (int o = 0; o < NO; ++o) acc[o] = fma(vb[u], wrow[o], acc[o]);
             }
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) vb[u] = vn[u];
     }
     double rn2 = 0.0;
     if (valid) {
@@ -816,7 +853,24 @@ void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const C
     const int E = nl * nr;
     const int rpb = ((w.n + w.ngblk - 1) / w.ngblk + GCHUNK - 1) / GCHUNK * GCHUNK;
     const int nb = (w.n + rpb - 1) / rpb;
-    hipLaunchKernelGGL(k_gram_partial, dim3(nb), dim3(ROWS), 0, s, L, nl, R, nr, w.n, w.ld, rpb, w.gpart);
+    const int la = nl <= 32 ? 2 : (nl <= 64 ? 4 : (nl <= 96 ? 6 : 8));
+    const int lbk = nr <= 16 ? 1 : (nr <= 32 ? 2 : 3);
+#define SKR_GP(LA, LB)                                                                                   \
+    hipLaunchKernelGGL((k_gram_partial<LA, LB>), dim3(nb), dim3(ROWS), 0, s, L, nl, R, nr, w.n, w.ld, rpb, w.gpart)
+#define SKR_GP_B(LA)                            \
+    switch (lbk) {                              \
+        case 1: SKR_GP(LA, 1); break;           \
+        case 2: SKR_GP(LA, 2); break;           \
+        default: SKR_GP(LA, 3); break;          \
+    }
+    switch (la) {
+        case 2: SKR_GP_B(2); break;
+        case 4: SKR_GP_B(4); break;
+        case 6: SKR_GP_B(6); break;
+        default: SKR_GP_B(8); break;
+    }
+#undef SKR_GP_B
+#undef SKR_GP
     hipLaunchKernelGGL(k_gram_reduce, dim3((E + 63) / 64), dim3(ROWS), 0, s, (const double*)w.gpart, nb, E, out);
 }
 void launch_cycle_gram(hipStream_t s, const Work& w, int kc, int jd_max) {
@@ -834,6 +888,7 @@ void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_
         case 0: SKR_UPD(0); break;
         case 8: SKR_UPD(8); break;
         case 16: SKR_UPD(16); break;
+        case 20: SKR_UPD(20); break;
         case 24: SKR_UPD(24); break;
         default: SKR_UPD(32); break;
     }
