@@ -517,32 +517,41 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
 // ---------------------------------------------------------------------------------------------
 // Cycle update in one pass over the basis rows: [C_new | U_new | dx | dr] = [C U V] W, then
 // x += dx, r += dr (W carries the signs), the new C and U overwrite the old, and the partials of
-// ||r||^2 are written for the next cycle. W (ncl x NO, row q = input column q) is gathered into LDS:
-// every entry is one load from the flat coefficient block at an index chosen by integer selects, so
-// no load sits inside a divergent branch. Input columns are read in batches of 16, the next batch
-// loading while the current one is applied.
+// ||r||^2 are written for the next cycle. W (ncl x NO, row q = input column q, zero-padded to
+// KP x NP) is gathered into LDS: every entry is one load from the flat coefficient block at an
+// index chosen by integer selects, so no load sits inside a divergent branch. The product runs on
+// the FP64 matrix cores (v_mfma_f64_16x16x4f64): each wave owns 64 rows (four 16-row tiles) and steps
+// over the input columns four at a time; lane l supplies A[l % 16][l / 16] = X[row + l % 16][q + l / 16]
+// (16 consecutive rows of one column per 16 lanes) and B[l / 16][l % 16] = W[q + l / 16][o + l % 16],
+// and result item t of lane l is output o + l % 16 of row 4 t + l / 16 of the tile. The next four
+// column steps load while the current four multiply.
+typedef double skr_d4u __attribute__((ext_vector_type(4)));
 template <int KB>
 __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ basis, double* __restrict__ U,
                                                        int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
                                                        double* part_n, Ctrl* ctrl) {
     constexpr int NO = 2 * KB + 2;
-    constexpr int MAXQ = 2 * KMAX + MMAX + 1;
+    constexpr int NTN = (NO + 15) / 16, NP = 16 * NTN;        // output tiles, padded outputs
+    constexpr int MAXQ = 2 * KMAX + MMAX + 1, KP = (MAXQ + 3) / 4 * 4;
     constexpr int OQC = offsetof(Coef, Qc) / sizeof(double), OQU = offsetof(Coef, Qu) / sizeof(double);
     constexpr int OYU = offsetof(Coef, yU) / sizeof(double), OYV = offsetof(Coef, yV) / sizeof(double);
     constexpr int ORC = offsetof(Coef, rC) / sizeof(double), ORV = offsetof(Coef, rV) / sizeof(double);
-    __shared__ double Wc[MAXQ * NO];
+    constexpr int RT = ROWS / NWAVE / 16;                     // 16-row tiles per wave
+    constexpr int KSB = 4;                                    // column steps per operand batch
+    __shared__ double Wc[KP * NP];
     __shared__ double sh[NWAVE * NC];
     const int jd = ctrl->j_done, brk = ctrl->breakdown, kn = ctrl->k_new;
     const int nv = jd + (brk ? 0 : 1);     // V columns of W-hat (v_{jd} is zero after a breakdown)
     const int ncl = 2 * kc + nv;           // input columns: C (kc), U (kc), V (nv)
+    const int nks = (ncl + 3) / 4;         // column steps
     const double* cf = reinterpret_cast<const double*>(coef);
-    for (int e0 = 0; e0 < ncl * NO; e0 += 8 * ROWS) {
+    for (int e0 = 0; e0 < nks * 4 * NP; e0 += 8 * ROWS) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * ROWS + threadIdx.x;
-            const int q = e / NO, o = e - q * NO;
+            const int q = e / NP, o = e - q * NP;
             const bool inC = q < kc, inU = !inC && q < 2 * kc;
             const int c = q - kc, t = q - 2 * kc;
             const bool oC = o < KB, oU = o >= KB && o < 2 * KB, oX = o == 2 * KB, oR = o == 2 * KB + 1;
@@ -562,60 +571,88 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
                 ok = (oC && o < kn) || (oU && t < jd && (o - KB) < kn) || (oX && t < jd) || oR;
                 sg = oR ? -1.0 : 1.0;
             }
-            ok = ok && e < ncl * NO;
+            ok = ok && q < ncl;
             const double ld_ = cf[ok ? idx : 0];
             v[u] = ok ? sg * ld_ : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * ROWS + threadIdx.x;
-            if (e < ncl * NO) Wc[e] = v[u];
+            if (e < nks * 4 * NP) Wc[e] = v[u];
         }
     }
     __syncthreads();
+    const int w = wave_id(), l = lane_id();
+    const int lrow = l & 15, lk = l >> 4;
     const int lb = logical_block(blockIdx.x, nblk);
-    const int i = lb * ROWS + threadIdx.x;
-    const bool valid = i < n;
-    const int ii = valid ? i : n - 1;
-    double acc[NO];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-    const double xi = x[ii], ri = r[ii];
+    const int wrow0 = lb * ROWS + w * 16 * RT;               // first row of this wave
     auto colp = [&](int q) {
         return q < kc ? basis + (size_t)q * ld
                       : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
     };
-    double vb[16];
+    skr_d4u acc[RT][NTN];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) vb[u] = colp(min(u, ncl - 1))[ii];
-    for (int q0 = 0; q0 < ncl; q0 += 16) {
-        double vn[16];
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) vn[u] = colp(min(q0 + 16 + u, ncl - 1))[ii];
+        for (int nt = 0; nt < NTN; ++nt) acc[rt][nt] = skr_d4u{0.0, 0.0, 0.0, 0.0};
+    double av[KSB][RT];
+    auto fetch = [&](int ks0) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            if (q0 + u < ncl) {
-                const double* wrow = Wc + (q0 + u) * NO;
+        for (int u = 0; u < KSB; ++u) {
+            const double* cp = colp(min(4 * (ks0 + u) + lk, ncl - 1));
 #pragma unroll
-                for (int o = 0; o < NO; ++o) acc[o] = fma(vb[u], wrow[o], acc[o]);
+            for (int rt = 0; rt < RT; ++rt) av[u][rt] = cp[min(wrow0 + 16 * rt + lrow, n - 1)];
+        }
+    };
+    fetch(0);
+    for (int ks0 = 0; ks0 < nks; ks0 += KSB) {
+        double ac[KSB][RT];
+#pragma unroll
+        for (int u = 0; u < KSB; ++u)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) ac[u][rt] = av[u][rt];
+        if (ks0 + KSB < nks) fetch(ks0 + KSB);
+#pragma unroll
+        for (int u = 0; u < KSB; ++u) {
+            if (ks0 + u < nks) {
+                const int q = 4 * (ks0 + u) + lk;
+                double bv[NTN];
+#pragma unroll
+                for (int nt = 0; nt < NTN; ++nt) bv[nt] = Wc[q * NP + 16 * nt + lrow];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int nt = 0; nt < NTN; ++nt)
+                        acc[rt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u][rt], bv[nt], acc[rt][nt], 0, 0, 0);
             }
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) vb[u] = vn[u];
     }
+    // results: item t of lane l is output o = 16 nt + (l % 16) of row wrow0 + 16 rt + 4 t + l / 16
     double rn2 = 0.0;
-    if (valid) {
-        const double rn = ri + acc[2 * KB + 1];
-        x[i] = xi + acc[2 * KB];
-        r[i] = rn;
 #pragma unroll
-        for (int o = 0; o < KB; ++o)
-            if (o < kn) {
-                basis[(size_t)o * ld + i] = acc[o];
-                U[(size_t)o * ld + i] = acc[KB + o];
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NTN; ++nt) {
+            const int o = 16 * nt + lrow;
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) {
+                const int row = wrow0 + 16 * rt + 4 * t2 + lk;
+                if (row < n) {
+                    const double val = acc[rt][nt][t2];
+                    if (o < KB) {
+                        if (o < kn) basis[(size_t)o * ld + row] = val;
+                    } else if (o < 2 * KB) {
+                        if (o - KB < kn) U[(size_t)(o - KB) * ld + row] = val;
+                    } else if (o == 2 * KB) {
+                        x[row] += val;
+                    } else if (o == 2 * KB + 1) {
+                        const double rn = r[row] + val;
+                        r[row] = rn;
+                        rn2 = fma(rn, rn, rn2);
+                    }
+                }
             }
-        rn2 = rn * rn;
-    }
+        }
     // partials of ||r||^2: the first pass A of the next cycle forms beta from them
     block_partial1(rn2, part_n, lb, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->stop = 0;
