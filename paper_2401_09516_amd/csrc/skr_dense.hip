@@ -246,7 +246,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     __shared__ double bsh[DMAX * NSHIFT];
     __shared__ double junk[DT];
     __shared__ int bcnt[DMAX * NSHIFT];
-    __shared__ int sel[KMAX];
+    __shared__ int sel[KMAX], isel[KMAX];
     __shared__ int nsel_s, sym_s, need2_s, fail_s;
     const int t = threadIdx.x;
     const int d = dw->d, kc = dw->kc;
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
             if (nh < nl) nh = nl;
             blo[i] = nl;
             bhi[i] = nh;
-            open = (nh - nl) > fmax(2.0 * eps * fmax(fabs(nl), fabs(nh)), 4.0 * eps * tnorm);
+            open = (nh - nl) > 2e-8 * tnorm;
         }
         if (!__syncthreads_or(open)) break;
     }
@@ -523,6 +523,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
         while (ns < k_target && lo <= hi) {
             const int pick = (fabs(lam[hi]) >= fabs(lam[lo])) ? hi-- : lo++;
             if (!(fabs(lam[pick]) > 0.0)) break;
+            isel[ns] = pick;
             lsel[ns++] = lam[pick];
         }
         nsel_s = ns;
@@ -532,45 +533,92 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, Coef* coef, Dens
     __syncthreads();
     const int kn = nsel_s;
 
-    // ---- eigenvectors of T (one thread per selected eigenvalue): T - lambda I = L+ D+ L+^T =
-    // U- D- U-^T, twist index r = argmin |D+_r + D-_r - (a_r - lambda)|, then z_r = 1 and
-    // z_i = -b_i z_{i+1} / D+_i (i < r), z_{i+1} = -b_i z_i / D-_{i+1} (i >= r). D+ and D- live in
-    // V (columns of 32), z overwrites D+.
+    // ---- eigenvectors of T (a lane pair per selected eigenvalue): T - lambda I = L+ D+ L+^T =
+    // U- D- U-^T, twist index r = argmin |gamma_r|, gamma_r = D+_r + D-_r - (a_r - lambda), then
+    // z_r = 1 and z_i = -b_i z_{i+1} / D+_i (i < r), z_{i+1} = -b_i z_i / D-_{i+1} (i >= r), so that
+    // (T - lambda I) z = gamma_r e_r. Lane 2o forms D+ and the upper part of z, lane 2o+1 D- and the
+    // lower part. The eigenvalue from multisection (to 2e-8 ||T||) is refined by one Rayleigh-quotient
+    // step, lambda += gamma_r / ||z||^2 (cubically convergent), kept inside its bisection interval;
+    // the second pass gives the eigenvector. D+ and D- live in V (columns of 32), z overwrites D+.
+    // Quotients use v_rcp_f64 with two Newton steps.
     double* Fp = V;
     double* Fm = V + DMAX * KMAX;
-    if (t < kn) {
-        const int o = t;
-        const double lm = lsel[o];
-        double dp = ta[0] - lm, dm = ta[d - 1] - lm;
-        if (fabs(dp) < pivmin) dp = -pivmin;
-        if (fabs(dm) < pivmin) dm = -pivmin;
-        Fp[o] = dp;
-        Fm[(d - 1) * KMAX + o] = dm;
-        for (int s2 = 1; s2 < d; ++s2) {
-            const int ib = d - 1 - s2;
-            dp = (ta[s2] - lm) - tb2[s2 - 1] / dp;
-            dm = (ta[ib] - lm) - tb2[ib] / dm;
-            if (fabs(dp) < pivmin) dp = -pivmin;
-            if (fabs(dm) < pivmin) dm = -pivmin;
-            Fp[s2 * KMAX + o] = dp;
-            Fm[ib * KMAX + o] = dm;
-        }
-        int rt = 0;
-        double gb = __builtin_inf();
-        for (int i = 0; i < d; ++i) {
-            const double g = fabs(Fp[i * KMAX + o] + Fm[i * KMAX + o] - (ta[i] - lm));
-            if (g < gb) { gb = g; rt = i; }
-        }
-        double z = 1.0;
-        for (int i = rt - 1; i >= 0; --i) {
-            z = -tb[i] * z / Fp[i * KMAX + o];
-            Fp[i * KMAX + o] = z;
-        }
-        Fp[rt * KMAX + o] = 1.0;
-        z = 1.0;
-        for (int i = rt; i + 1 < d; ++i) {
-            z = -tb[i] * z / Fm[(i + 1) * KMAX + o];
-            Fp[(i + 1) * KMAX + o] = z;
+    if (t < 64) {
+        const int o = t >> 1, side = t & 1;
+        const bool act = o < kn;
+        const int oc = min(o, KMAX - 1);
+        const int ie = act ? isel[oc] : 0;
+        const double lo_ = blo[ie], hi_ = bhi[ie];
+        double lm = act ? lsel[oc] : 0.0;
+        auto frcp = [](double v) {
+            double rc = __builtin_amdgcn_rcp(v);
+            rc = fma(rc, fma(-v, rc, 1.0), rc);
+            return fma(rc, fma(-v, rc, 1.0), rc);
+        };
+        for (int pass = 0; pass < 2; ++pass) {
+            if (act) {
+                if (side == 0) {
+                    double dp = ta[0] - lm;
+                    if (fabs(dp) < pivmin) dp = -pivmin;
+                    Fp[o] = dp;
+                    for (int s2 = 1; s2 < d; ++s2) {
+                        dp = fma(-tb2[s2 - 1], frcp(dp), ta[s2] - lm);
+                        if (fabs(dp) < pivmin) dp = -pivmin;
+                        Fp[s2 * KMAX + o] = dp;
+                    }
+                } else {
+                    double dm = ta[d - 1] - lm;
+                    if (fabs(dm) < pivmin) dm = -pivmin;
+                    Fm[(d - 1) * KMAX + o] = dm;
+                    for (int ib = d - 2; ib >= 0; --ib) {
+                        dm = fma(-tb2[ib], frcp(dm), ta[ib] - lm);
+                        if (fabs(dm) < pivmin) dm = -pivmin;
+                        Fm[ib * KMAX + o] = dm;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int rt = 0;
+            double gam = 0.0, nz = 0.0;
+            if (act) {
+                double gb = __builtin_inf();
+                for (int i = 0; i < d; ++i) {
+                    const double g = Fp[i * KMAX + o] + Fm[i * KMAX + o] - (ta[i] - lm);
+                    if (fabs(g) < gb) { gb = fabs(g); gam = g; rt = i; }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (act) {
+                double z = 1.0;
+                if (side == 0) {
+                    for (int i = rt - 1; i >= 0; --i) {
+                        z = -tb[i] * z * frcp(Fp[i * KMAX + o]);
+                        Fp[i * KMAX + o] = z;
+                        nz = fma(z, z, nz);
+                    }
+                    Fp[rt * KMAX + o] = 1.0;
+                } else {
+                    for (int i = rt; i + 1 < d; ++i) {
+                        z = -tb[i] * z * frcp(Fm[(i + 1) * KMAX + o]);
+                        Fp[(i + 1) * KMAX + o] = z;
+                        nz = fma(z, z, nz);
+                    }
+                }
+            }
+            // ||z||^2 = 1 + upper part + lower part, added in the same order on both lanes
+            const double nzo = row_partner<1>(nz);
+            const double nz2 = 1.0 + (side == 0 ? nz + nzo : nzo + nz);
+            if (act && pass == 0) {
+                const double ln = lm + gam / nz2;
+                if (ln == ln) lm = fmin(fmax(ln, lo_), hi_);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     __syncthreads();
