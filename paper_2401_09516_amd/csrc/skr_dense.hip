@@ -32,7 +32,7 @@ __device__ __forceinline__ double group8_sum(double x) {
 }
 
 // Copy a rows x cols column-major block from global (leading dimension lds) to LDS (leading
-// dimension ldd) with nthr threads, eight loads in flight per thread.
+// dimension ldd) with nthr threads, eight loads in flight per thread (all unconditional).
 __device__ __forceinline__ void stage_block(double* dst, int ldd, const double* src, int lds, int rows, int cols,
                                             int t, int nthr) {
     const int total = rows * cols;
@@ -40,8 +40,8 @@ __device__ __forceinline__ void stage_block(double* dst, int ldd, const double* 
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * nthr + t;
-            v[u] = (e < total) ? src[(e % rows) + (e / rows) * lds] : 0.0;
+            const int e = min(e0 + u * nthr + t, total - 1);   // unconditional load (clamped index)
+            v[u] = src[(e % rows) + (e / rows) * lds];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
