@@ -44,6 +44,7 @@ extern "C" {
 /* operator kinds (skr_op.kind) */
 #define SKR_OP_CSR      0   /* general sparse matrix, CSR                                        */
 #define SKR_OP_STENCIL5 1   /* matrix-free 2-D 5-point operator built from face coefficients   */
+#define SKR_OP_STENCIL7 2   /* matrix-free 3-D 7-point operator built from face coefficients   */
 
 typedef struct skr_ctx skr_ctx;
 
@@ -57,6 +58,12 @@ typedef struct skr_ctx skr_ctx;
  *            ay[(ny+1)*nx]: ay[i*nx + j] is the face between rows i-1 and i of column j.
  *            (A x)_ij = inv_h2 * ( sum of the 4 faces * x_ij - sum over interior neighbours of
  *            face * x_neighbour ), i.e. -div(a grad u) with zero Dirichlet data.
+ *  STENCIL7: the same in 3-D on an nx-by-ny-by-nz grid, unknown (x, y, z) at index
+ *            x + nx*(y + ny*z); ax[nz*ny*(nx+1)]: ax[(z*ny + y)*(nx+1) + x] is the face between x-1
+ *            and x; ay[nz*(ny+1)*nx]: ay[(z*(ny+1) + y)*nx + x] the face between y-1 and y;
+ *            az[(nz+1)*ny*nx]: az[(z*ny + y)*nx + x] the face between z-1 and z (index 0 and the
+ *            last index are the Dirichlet boundary faces). Uses nz and az; nx, ny, inv_h2, ax, ay as
+ *            for STENCIL5.
  */
 typedef struct {
     int32_t kind;
@@ -69,12 +76,17 @@ typedef struct {
     double inv_h2;
     const double* ax;
     const double* ay;
+    int32_t nz;             /* STENCIL7 only */
+    const double* az;       /* STENCIL7 only */
 } skr_op;
 
 /* Solver options. m: maximum subspace size per cycle (1..62); k: recycled vectors (0 = GMRES(m),
  * k < m, k <= 32); rtol: relative residual target; maxit: maximum Arnoldi steps per system;
- * flags: 0 or SKR_FLAG_PROFILE. */
+ * flags: 0 or a combination of SKR_FLAG_PROFILE and SKR_FLAG_FOLD. */
 #define SKR_FLAG_PROFILE 1u   /* time every 16th Arnoldi step's kernels with hipEvents (see skr_profile_get) */
+#define SKR_FLAG_FOLD    2u   /* fold the per-workgroup partials of every grid reduction into 64 rows
+                                 before they are re-summed; done anyway above 256 workgroups
+                                 (n > 65,536), where it keeps the reduction cost linear in n */
 
 typedef struct {
     int32_t m;

@@ -44,6 +44,9 @@ constexpr int PROF_MAXSAMP = (MMAX + PROF_PERIOD - 1) / PROF_PERIOD + 1;
 static double op_bytes(const DevOp& op, int64_t nvals) {
     const double n = op.n;
     if (op.kind == SKR_OP_CSR) return 12.0 * (double)nvals + 4.0 * (n + 1) + 8.0 * n;
+    if (op.kind == SKR_OP_STENCIL7)
+        return 8.0 * (double)op.nz * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) +
+               8.0 * (double)(op.nz + 1) * op.ny * op.nx + 8.0 * n;
     return 8.0 * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 8.0 * n;
 }
 static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double& a, double& b, double& c) {
@@ -99,6 +102,7 @@ static int fail(int code, const char* fmt, ...) {
 
 static void free_work(Work& w) {
     double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
+                      w.fold_a, w.fold_b, w.fold_n,
                       w.red1, w.red2, w.H, w.Bm};
     for (double* p : bufs)
         if (p) (void)hipFree(p);
@@ -140,6 +144,9 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     chk(dalloc(&w.part, (size_t)w.nblk * NC));
     chk(dalloc(&w.gpart, (size_t)w.ngblk * w.gram_max));
     chk(dalloc(&w.gram, w.gram_max));
+    chk(dalloc(&w.fold_a, (size_t)NFOLD * NC));
+    chk(dalloc(&w.fold_b, (size_t)NFOLD * NC));
+    chk(dalloc(&w.fold_n, (size_t)NFOLD));
     chk(dalloc(&w.red1, NC));
     chk(dalloc(&w.red2, NC));
     chk(dalloc(&w.H, (size_t)LDH * MMAX));
@@ -193,6 +200,18 @@ static int to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
         d.inv_h2 = o.inv_h2;
         d.ax = o.ax;
         d.ay = o.ay;
+        nvals = 0;
+    } else if (o.kind == SKR_OP_STENCIL7) {
+        if (!o.ax || !o.ay || !o.az || o.nx <= 0 || o.ny <= 0 || o.nz <= 0 ||
+            (int64_t)o.nx * o.ny * o.nz != o.n)
+            return fail(SKR_EINVAL, "7-point stencil operator needs ax, ay, az and nx * ny * nz == n");
+        d.nx = o.nx;
+        d.ny = o.ny;
+        d.nz = o.nz;
+        d.inv_h2 = o.inv_h2;
+        d.ax = o.ax;
+        d.ay = o.ay;
+        d.az = o.az;
         nvals = 0;
     } else {
         return fail(SKR_EINVAL, "unknown operator kind %d", o.kind);
@@ -364,6 +383,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
     int kin = 0;   // recycled vectors carried from the previous system (held in w.U)
     bool any_maxit = false;
     const bool profile = (opts->flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
+    w.fold = (w.nblk > FOLD_MIN || (opts->flags & SKR_FLAG_FOLD)) ? 1 : 0;
     int samp_j[PROF_MAXSAMP];
     for (int64_t q = 0; q < N; ++q) {
         const int64_t idx = order ? order[q] : q;

@@ -20,6 +20,8 @@ constexpr int KMAX = 32;         // largest k (recycled vectors)
 constexpr int LDH = MMAX + 2;    // leading dimension of the Hessenberg store (rows)
 constexpr int DMAX = 64;         // largest projected dimension d = kc + j (<= m) plus one
 constexpr int NORM_COL = NC - 1; // reduction column that carries ||A v_j||^2 in the first pass
+constexpr int NFOLD = 64;        // rows of folded partials (large grids)
+constexpr int FOLD_MIN = 256;    // grids above this many workgroups fold their partials
 
 // ---------------------------------------------------------------------------------------------
 // Operator (device view of skr_op)
@@ -30,18 +32,34 @@ struct DevOp {
     const int* rowptr;
     const int* colind;
     const double* val;
-    int nx, ny;
+    int nx, ny, nz;
     double inv_h2;
     const double* ax;
     const double* ay;
+    const double* az;
 };
 
-// One row of y = scale * (A x).
+// One row of y = scale * (A x): CSR, 2-D 5-point or 3-D 7-point harmonic-mean stencil.
 __device__ __forceinline__ double op_row(const DevOp& op, const double* __restrict__ x, int i, double scale) {
     double s = 0.0;
     if (op.kind == SKR_OP_CSR) {
         const int e0 = op.rowptr[i], e1 = op.rowptr[i + 1];
         for (int e = e0; e < e1; ++e) s = fma(op.val[e], x[op.colind[e]], s);
+    } else if (op.kind == SKR_OP_STENCIL7) {
+        const int nx = op.nx, ny = op.ny, nz = op.nz, nxy = nx * ny;
+        const int gz = i / nxy, gyx = i - gz * nxy, gy = gyx / nx, gx = gyx - gy * nx;
+        const int fx = (gz * ny + gy) * (nx + 1) + gx, fy = (gz * (ny + 1) + gy) * nx + gx, fz = gz * nxy + gyx;
+        const double aw = op.ax[fx], ae = op.ax[fx + 1];
+        const double as = op.ay[fy], an = op.ay[fy + nx];
+        const double ad = op.az[fz], au = op.az[fz + nxy];
+        s = ((aw + ae) + (as + an) + (ad + au)) * x[i];
+        if (gx > 0) s = fma(-aw, x[i - 1], s);
+        if (gx < nx - 1) s = fma(-ae, x[i + 1], s);
+        if (gy > 0) s = fma(-as, x[i - nx], s);
+        if (gy < ny - 1) s = fma(-an, x[i + nx], s);
+        if (gz > 0) s = fma(-ad, x[i - nxy], s);
+        if (gz < nz - 1) s = fma(-au, x[i + nxy], s);
+        s *= op.inv_h2;
     } else {
         const int nx = op.nx, ny = op.ny;
         const int r = i / nx, c = i - r * nx;
@@ -413,6 +431,10 @@ struct Work {
     double* part = nullptr;      // nblk * NC partials of the start-up projection
     double* gpart = nullptr;     // Gram partials: ngblk * gram_max
     double* gram = nullptr;      // reduced Gram result
+    double* fold_a = nullptr;    // NFOLD * NC folded partials of pass A (large grids)
+    double* fold_b = nullptr;    // NFOLD * NC folded partials of pass B
+    double* fold_n = nullptr;    // NFOLD folded norm partials
+    int fold = 0;                // nonzero: partials are folded before every re-sum
     double* red1 = nullptr;      // NC
     double* red2 = nullptr;      // NC
     double* H = nullptr;         // LDH x MMAX

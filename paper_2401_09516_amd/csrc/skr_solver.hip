@@ -160,7 +160,7 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
 template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
                                                  double* __restrict__ dst, double* __restrict__ basis,
-                                                 int ld, int kc, int vbase, int j, int nblk,
+                                                 int ld, int kc, int vbase, int j, int nblk, int npn,
                                                  const double* __restrict__ part_n, double* __restrict__ part_a,
                                                  const double* __restrict__ red1, const double* __restrict__ red2,
                                                  double* H, double* Bm, Ctrl* ctrl) {
@@ -189,12 +189,12 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
         for (int c = 0; c < NL; ++c) q[c] = 0.0;
     }
     double pn[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool few = nblk <= 4 * 64;
+    const bool few = npn <= 4 * 64;
     if (few && threadIdx.x < 64) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int b = threadIdx.x + 64 * u;
-            pn[u] = (b < nblk) ? part_n[b] : 0.0;
+            pn[u] = (b < npn) ? part_n[b] : 0.0;
         }
     }
     const double xi = src[ii];
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
         tot = sh[0];
         __syncthreads();
     } else {
-        tot = sum_partials1(part_n, nblk, sh);
+        tot = sum_partials1(part_n, npn, sh);
     }
     if (j == 0) {
         if (threadIdx.x == 0) {
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 // partials of Q^T w.
 template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const double* __restrict__ basis,
-                                                 int n, int ld, int kc, int vbase, int j, int nblk,
+                                                 int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
                                                  double* __restrict__ red1, const Ctrl* ctrl) {
     constexpr int NR = Width<NL>::NR;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
     for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
-    sum_partials(part_a, nblk, ncol + 1, sh, hs);
+    sum_partials(part_a, npa, ncol + 1, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
 // Pass C: h2 = Q^T w (sum of pass B's partials, stored), w -= Q h2, partials of ||w||^2.
 template <int NL>
 __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const double* __restrict__ basis,
-                                                 int n, int ld, int kc, int vbase, int j, int nblk,
+                                                 int n, int ld, int kc, int vbase, int j, int nblk, int npb,
                                                  const double* __restrict__ part_b, double* __restrict__ part_n,
                                                  double* __restrict__ red2, const Ctrl* ctrl) {
     __shared__ double sh[NWAVE * NC];
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
     for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
-    sum_partials(part_b, nblk, ncol, sh, hs);
+    sum_partials(part_b, npb, ncol, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x < ncol) red2[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
 // v_{j_done} = w_last * inv_h (zero after a breakdown), the last column of the cycle's basis.
 __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__ w0, const double* __restrict__ w1,
                                                       double* __restrict__ basis, int n, int ld, int kc, int vbase,
-                                                      int s_cycle, int nblk, const double* __restrict__ part_n,
+                                                      int s_cycle, int npn, const double* __restrict__ part_n,
                                                       const double* __restrict__ red1, const double* __restrict__ red2,
                                                       double* H, double* Bm, Ctrl* ctrl) {
     __shared__ double sh[NWAVE * NC];
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__
     __shared__ int s_jd, s_brk;
     const bool writer = blockIdx.x == 0;
     if (!ctrl->stop) {
-        const double tot = sum_partials1(part_n, nblk, sh);
+        const double tot = sum_partials1(part_n, npn, sh);
         if (threadIdx.x < 64) {
             int brk;
             double hn;
@@ -806,6 +806,62 @@ __global__ __launch_bounds__(ROWS) void k_spmv(DevOp op, const double* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
+// Partial folding for large grids. Every workgroup of a step kernel re-sums the partials of the
+// kernel before it; with many workgroups that costs O(nblk^2) reads. Above FOLD_MIN workgroups
+// (or on request) a fold kernel first sums the nblk partial rows into NFOLD rows: workgroup g adds
+// rows [g per, (g + 1) per) in a fixed order (lane = column, the four waves take contiguous quarters,
+// added in wave order), and the consumer re-sums the NFOLD rows.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(ROWS) void k_fold(const double* __restrict__ part, int nblk, int width,
+                                               double* __restrict__ out) {
+    __shared__ double sh[NWAVE * NC];
+    const int lane = lane_id(), w = wave_id();
+    const int per = (nblk + NFOLD - 1) / NFOLD;
+    const int g0 = blockIdx.x * per, g1 = min(nblk, g0 + per);
+    const int q = (per + NWAVE - 1) / NWAVE;
+    const int b0 = min(g1, g0 + w * q), b1 = min(g1, b0 + q);
+    double s = 0.0;
+    if (lane < width) {
+        for (int b = b0; b < b1; b += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = part[(size_t)min(b + u, b1 - 1) * NC + lane];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += (b + u < b1) ? v[u] : 0.0;
+        }
+    }
+    sh[w * NC + lane] = s;
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        double t = sh[threadIdx.x];
+#pragma unroll
+        for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[q2 * NC + threadIdx.x];
+        out[blockIdx.x * NC + threadIdx.x] = t;
+    }
+}
+__global__ __launch_bounds__(ROWS) void k_fold1(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    __shared__ double sh[NWAVE];
+    const int per = (nblk + NFOLD - 1) / NFOLD;
+    const int g0 = blockIdx.x * per, g1 = min(nblk, g0 + per);
+    double s = 0.0;
+    for (int b = g0 + (int)threadIdx.x; b < g1; b += ROWS) s += part[b];
+    const double ws = wave_sum(s);
+    if (lane_id() == 0) sh[wave_id()] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+#pragma unroll
+        for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[q2];
+        out[blockIdx.x] = t;
+    }
+}
+static inline const double* pn_src(const Work& w) { return w.fold ? w.fold_n : w.part_n; }
+static inline int pn_cnt(const Work& w) { return w.fold ? NFOLD : w.nblk; }
+void launch_fold_n(hipStream_t s, const Work& w) {
+    if (w.fold) hipLaunchKernelGGL(k_fold1, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_n, w.nblk, w.fold_n);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------------------------
 static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
@@ -813,6 +869,7 @@ static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
 void launch_init(hipStream_t s, const Work& w, const double* b, double* x, double rtol) {
     hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, rtol, w.part_n,
                        w.counters + 0, w.ctrl);
+    launch_fold_n(s, w);
 }
 void launch_clear_nonfinite(hipStream_t s, const Work& w) {
     hipLaunchKernelGGL(k_clear_nonfinite, dim3(1), dim3(1), 0, s, w.ctrl);
@@ -833,19 +890,21 @@ template <int NL>
 static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
                    hipEvent_t e0, hipEvent_t e1) {
     hipExtLaunchKernelGGL(k_step_a<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst, w.basis, w.ld,
-                          kc, w.k, j, w.nblk, (const double*)w.part_n, w.part_a, (const double*)w.red1,
+                          kc, w.k, j, w.nblk, pn_cnt(w), pn_src(w), w.part_a, (const double*)w.red1,
                           (const double*)w.red2, w.H, w.Bm, w.ctrl);
 }
 template <int NL>
 static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
     hipExtLaunchKernelGGL(k_step_b<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
-                          w.n, w.ld, kc, w.k, j, w.nblk, (const double*)w.part_a, w.part_b, w.red1,
+                          w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+                          (const double*)(w.fold ? w.fold_a : w.part_a), w.part_b, w.red1,
                           (const Ctrl*)w.ctrl);
 }
 template <int NL>
 static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
     hipExtLaunchKernelGGL(k_step_c<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
-                          w.n, w.ld, kc, w.k, j, w.nblk, (const double*)w.part_b, w.part_n, w.red2,
+                          w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+                          (const double*)(w.fold ? w.fold_b : w.part_b), w.part_n, w.red2,
                           (const Ctrl*)w.ctrl);
 }
 
@@ -874,16 +933,19 @@ void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, i
 #define CALL_A(NL) step_a<NL>(s, w, op, src, dst, kc, j, e[0], e[1])
     SKR_DISPATCH8(nla, CALL_A)
 #undef CALL_A
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_a, w.nblk, NC, w.fold_a);
 #define CALL_B(NL) step_b<NL>(s, w, dst, kc, j, e[2], e[3])
     SKR_DISPATCH8(nlb, CALL_B)
 #undef CALL_B
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_b, w.nblk, NC, w.fold_b);
 #define CALL_C(NL) step_c<NL>(s, w, dst, kc, j, e[4], e[5])
     SKR_DISPATCH8(nlb, CALL_C)
 #undef CALL_C
+    launch_fold_n(s, w);
 }
 void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
     hipLaunchKernelGGL(k_close_basis, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0], (const double*)w.W[1],
-                       w.basis, w.n, w.ld, kc, w.k, s_cycle, w.nblk, (const double*)w.part_n,
+                       w.basis, w.n, w.ld, kc, w.k, s_cycle, pn_cnt(w), pn_src(w),
                        (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
 }
 void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const ColList& R, int nr, double* out) {
@@ -930,10 +992,12 @@ void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_
         default: SKR_UPD(32); break;
     }
 #undef SKR_UPD
+    launch_fold_n(s, w);
 }
 void launch_true_residual(hipStream_t s, const Work& w, const DevOp& op, const double* b, const double* x) {
     hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n,
                        w.counters + 5, w.ctrl);
+    launch_fold_n(s, w);
 }
 void launch_spmm(hipStream_t s, const Work& w, const DevOp& op, int kin) {
     hipLaunchKernelGGL(k_spmm, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, op, (const double*)w.U, w.basis, w.ld, kin);
@@ -952,6 +1016,7 @@ void launch_startup_project(hipStream_t s, const Work& w, double* x) {
     hipLaunchKernelGGL(k_startup_project, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, (const double*)w.basis,
                        (const double*)w.U, w.n, w.ld, w.nblk, (const Coef*)w.coef, (const double*)w.red1,
                        w.part_n, w.counters + 7, w.ctrl);
+    launch_fold_n(s, w);
 }
 void launch_spmv(hipStream_t s, const DevOp& op, const double* x, double* y) {
     hipLaunchKernelGGL(k_spmv, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, x, y);

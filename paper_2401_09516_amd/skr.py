@@ -29,8 +29,10 @@ SKR_NONFINITE = 3
 
 SKR_OP_CSR = 0
 SKR_OP_STENCIL5 = 1
+SKR_OP_STENCIL7 = 2
 
 SKR_FLAG_PROFILE = 1
+SKR_FLAG_FOLD = 2
 
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
             "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset")
@@ -46,7 +48,8 @@ class skr_op(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("values", ctypes.c_void_p),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("inv_h2", ctypes.c_double),
-                ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p)]
+                ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p), ("nz", ctypes.c_int32),
+                ("az", ctypes.c_void_p)]
 
 
 class skr_opts(ctypes.Structure):
@@ -142,6 +145,14 @@ def stencil_op(ax, ay, nx: int, ny: int, inv_h2: float) -> Operator:
     """Matrix-free 5-point operator from face coefficients ax[ny*(nx+1)], ay[(ny+1)*nx] (float64)."""
     c = skr_op(kind=SKR_OP_STENCIL5, n=nx * ny, nx=nx, ny=ny, inv_h2=inv_h2, ax=_ptr(ax), ay=_ptr(ay))
     return Operator(c, (ax, ay))
+
+
+def stencil7_op(ax, ay, az, nx: int, ny: int, nz: int, inv_h2: float) -> Operator:
+    """Matrix-free 3-D 7-point operator from face coefficients ax[nz*ny*(nx+1)], ay[nz*(ny+1)*nx],
+    az[(nz+1)*ny*nx] (float64, layouts as in skr.h)."""
+    c = skr_op(kind=SKR_OP_STENCIL7, n=nx * ny * nz, nx=nx, ny=ny, nz=nz, inv_h2=inv_h2, ax=_ptr(ax),
+               ay=_ptr(ay), az=_ptr(az))
+    return Operator(c, (ax, ay, az))
 
 
 # ----------------------------------------------------------------------------------- entry points

@@ -45,7 +45,7 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("skr_op %zu\nskr_opts %zu\nskr_result %zu\n", sizeof(skr_op), sizeof(skr_opts), sizeof(skr_result));
   F(skr_op, kind); F(skr_op, n); F(skr_op, nnz); F(skr_op, rowptr); F(skr_op, colind); F(skr_op, values);
-  F(skr_op, nx); F(skr_op, ny); F(skr_op, inv_h2); F(skr_op, ax); F(skr_op, ay);
+  F(skr_op, nx); F(skr_op, ny); F(skr_op, inv_h2); F(skr_op, ax); F(skr_op, ay); F(skr_op, nz); F(skr_op, az);
   F(skr_opts, m); F(skr_opts, k); F(skr_opts, rtol); F(skr_opts, maxit); F(skr_opts, flags);
   F(skr_result, status); F(skr_result, cycles); F(skr_result, k_start); F(skr_result, rank_dropped);
   F(skr_result, iters); F(skr_result, spmv); F(skr_result, relres_true); F(skr_result, relres_est);

@@ -269,3 +269,49 @@ def test_solve_nonsymmetric_advdiff(env):
         assert g["relres_true"] <= 1e-9 * (1 + 1e-9)
         assert rel <= bound
         assert abs(g["iters"] - r.iters) <= (1 if i < 2 else max(3, 0.1 * r.iters))
+
+
+# ------------------------------------------------------------------------ 3-D 7-point operator
+@pytest.mark.parametrize("N", [1, 3, 8, 13])
+def test_spmv_3d_stencil(env, N):
+    torch, skr, ctx = env
+    from workloads import darcy3d_sequence
+    log(f"[spmv] 3-D 7-point N={N}")
+    s = darcy3d_sequence(N, 1, first_seed=11)[0]
+    x = np.random.default_rng(N).standard_normal(s.n)
+    ops, _, _ = upload_systems([s], "cuda:0", "stencil")
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.full_like(xd, np.nan)
+    skr.skr_spmv(ctx, ops[0], xd, yd)
+    y = yd.cpu().numpy()
+    bound = 8 * EPS * (abs(s.A) @ np.abs(x))
+    assert np.all(np.abs(y - s.A @ x) <= bound)
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_solve_3d_chain(env, kind):
+    """10^3 Darcy (3-D, 7-point), 6 systems sorted into one chain, GCRO-DR(30,10), rel-res 1e-8."""
+    torch, skr, ctx = env
+    from workloads import darcy3d_sequence
+    log(f"[solve] 3-D chain kind={kind}")
+    systems = darcy3d_sequence(10, 6)
+    order = oracle.greedy_sort(param_matrix(systems))
+    ops, bs, xs = upload_systems(systems, "cuda:0", kind)
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, 30, 10, 1e-8, 20000)
+    _compare(systems, res, xs, ref, f"3d-{kind}", order)
+
+
+def test_fold_path(env):
+    """The folded two-level partial reductions (forced at a small grid) against the oracle."""
+    torch, skr, ctx = env
+    log("[solve] config-1 chain with folded partials")
+    systems = darcy_sequence(32, 16)
+    order = oracle.greedy_sort(param_matrix(systems))
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000,
+                                     flags=skr.SKR_FLAG_FOLD)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, 30, 10, 1e-8, 20000)
+    _compare(systems, res, xs, ref, "cfg1-fold", order)

@@ -86,3 +86,53 @@ def test_advdiff_operator():
     assert not np.allclose(A, A.T)
     seq = advdiff_sequence(6, 3)
     assert all(1e-3 <= s.nu <= 1e-2 for s in seq) and seq[0].A.shape == (36, 36)
+
+
+def test_3d_structure_and_symmetry():
+    from workloads import darcy3d_sequence
+    for N in (1, 2, 5):
+        s = darcy3d_sequence(N, 1, first_seed=4)[0]
+        A = s.A
+        assert A.shape == (N ** 3, N ** 3)
+        assert A.nnz == 7 * N ** 3 - 6 * N ** 2
+        assert A.indptr.dtype == np.int32 and A.indices.dtype == np.int32
+        assert abs(A - A.T).max() == 0.0
+        d = A.diagonal()
+        off = np.asarray(abs(A).sum(axis=1)).ravel() - d
+        assert np.all(d >= off * (1 - 1e-15)) and np.all(d > 0)
+        assert s.ax.shape == (N, N, N + 1) and s.ay.shape == (N, N + 1, N) and s.az.shape == (N + 1, N, N)
+
+
+def test_3d_faces_reproduce_csr():
+    from workloads import darcy3d_sequence
+    s = darcy3d_sequence(6, 1, first_seed=2)[0]
+    N = s.N
+    x = np.random.default_rng(1).standard_normal((N, N, N))        # [z, y, x]
+    xp = np.zeros((N + 2, N + 2, N + 2))
+    xp[1:-1, 1:-1, 1:-1] = x
+    c = xp[1:-1, 1:-1, 1:-1]
+    y = (s.ax[:, :, :-1] * (c - xp[1:-1, 1:-1, :-2]) + s.ax[:, :, 1:] * (c - xp[1:-1, 1:-1, 2:])
+         + s.ay[:, :-1, :] * (c - xp[1:-1, :-2, 1:-1]) + s.ay[:, 1:, :] * (c - xp[1:-1, 2:, 1:-1])
+         + s.az[:-1, :, :] * (c - xp[:-2, 1:-1, 1:-1]) + s.az[1:, :, :] * (c - xp[2:, 1:-1, 1:-1])) * s.inv_h2
+    np.testing.assert_allclose(y.ravel(), s.A @ x.ravel(), rtol=1e-12, atol=1e-9 * s.inv_h2)
+
+
+def test_3d_constant_coefficient_closed_form():
+    # a == 1: the 7-point Dirichlet Laplacian, whose eigenvalues are
+    # (4/h^2) (sin^2(p pi h/2) + sin^2(q pi h/2) + sin^2(r pi h/2)), p, q, r = 1..N
+    from workloads.darcy3d import darcy3d_from_nodes
+    N = 5
+    h = 1.0 / (N + 1)
+    A = darcy3d_from_nodes(np.ones((N + 2, N + 2, N + 2))).A.toarray()
+    lam = np.sort(np.linalg.eigvalsh(A))
+    s1 = np.sin(np.arange(1, N + 1) * np.pi * h / 2) ** 2
+    ref = np.sort((4 / h ** 2) * (s1[:, None, None] + s1[None, :, None] + s1[None, None, :]).ravel())
+    np.testing.assert_allclose(lam, ref, rtol=1e-12)
+
+
+def test_grf3d_is_seeded_and_unit_variance():
+    from workloads import grf_field3d
+    assert np.array_equal(grf_field3d(10, 3), grf_field3d(10, 3))
+    assert not np.array_equal(grf_field3d(10, 3), grf_field3d(10, 4))
+    v = np.mean([grf_field3d(12, s).var() + grf_field3d(12, s).mean() ** 2 for s in range(60)])
+    assert 0.8 < v < 1.2

@@ -5,6 +5,8 @@ sort or solver arithmetic lives here.
 """
 from .darcy import (DarcySystem, darcy_from_nodes, darcy_sequence, darcy_system, faces_from_nodes,
                     grf_field, param_matrix, permeability)
+from .darcy3d import Darcy3DSystem, darcy3d_sequence, darcy3d_system, grf_field3d
 
 __all__ = ["DarcySystem", "darcy_from_nodes", "darcy_sequence", "darcy_system", "faces_from_nodes",
-           "grf_field", "param_matrix", "permeability"]
+           "grf_field", "param_matrix", "permeability", "Darcy3DSystem", "darcy3d_sequence", "darcy3d_system",
+           "grf_field3d"]

@@ -10,11 +10,11 @@ import numpy as np
 def upload_systems(systems, device="cuda:0", kind="csr"):
     """Return (ops, b_list, x_list) for ``systems`` (list of DarcySystem) on ``device``.
 
-    kind = "csr" (CSR matrices) or "stencil" (matrix-free 5-point face coefficients). The x tensors
-    are zero-initialised outputs.
+    kind = "csr" (CSR matrices) or "stencil" (matrix-free face coefficients: 5-point for 2-D systems,
+    7-point for 3-D ones). The x tensors are zero-initialised outputs.
     """
     import torch
-    from paper_2401_09516_amd.skr import csr_op, stencil_op
+    from paper_2401_09516_amd.skr import csr_op, stencil7_op, stencil_op
 
     ops, bs, xs = [], [], []
     for s in systems:
@@ -27,7 +27,11 @@ def upload_systems(systems, device="cuda:0", kind="csr"):
         elif kind == "stencil":
             ax = torch.from_numpy(np.ascontiguousarray(s.ax, dtype=np.float64).ravel()).to(device)
             ay = torch.from_numpy(np.ascontiguousarray(s.ay, dtype=np.float64).ravel()).to(device)
-            ops.append(stencil_op(ax, ay, s.N_g, s.N_g, s.inv_h2))
+            if hasattr(s, "az"):
+                az = torch.from_numpy(np.ascontiguousarray(s.az, dtype=np.float64).ravel()).to(device)
+                ops.append(stencil7_op(ax, ay, az, s.N, s.N, s.N, s.inv_h2))
+            else:
+                ops.append(stencil_op(ax, ay, s.N_g, s.N_g, s.inv_h2))
         else:
             raise ValueError(kind)
         bs.append(torch.from_numpy(np.ascontiguousarray(s.b, dtype=np.float64)).to(device))
