@@ -11,6 +11,10 @@ relative residual 1e-8, inputs resident in HBM before the timed region.
 Printed: one JSON line with systems/s (converged systems only), the roofline of the dominant
 Arnoldi-step kernel (sampled hipEvent timings inside the timed region), GMRES(60) on the same GPU
 for a prefix of the sorted chain, SpMV bandwidth, and the CPU oracle timed on a bounded sample.
+
+--dim 3 is a secondary mode: 3-D Darcy on a 128^3 grid (n = 2,097,152; 7-point operator, CSR or
+matrix-free), 8 systems by default. Its working set (basis about 1.4 GB) is far beyond the 256 MB
+Infinity Cache, so its kernel rates are HBM rates. It reports no oracle sample.
 """
 import argparse
 import json
@@ -54,8 +58,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--systems", type=int, default=400)
-    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--systems", type=int, default=None, help="default 400 in 2-D, 8 in 3-D")
+    ap.add_argument("--dim", type=int, choices=[2, 3], default=2,
+                    help="2: the 2-D Darcy workload; 3: 3-D Darcy on a grid^3 mesh (7-point), a secondary mode")
+    ap.add_argument("--grid", type=int, default=None, help="grid side (default 256 in 2-D, 128 in 3-D)")
     ap.add_argument("--m", type=int, default=60)
     ap.add_argument("--k", type=int, default=20)
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -73,7 +79,14 @@ def parse():
                          "--copy-mib MiB (the reference kernel that scales hardware byte counters); for "
                          "rocprofv3 --pmc runs")
     ap.add_argument("--copy-mib", type=int, default=512)
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.grid is None:
+        a.grid = 256 if a.dim == 2 else 128
+    if a.systems is None:
+        a.systems = 400 if a.dim == 2 else 8
+    if a.dim == 3:
+        a.spmv_grid = 0          # the 3-D matrix at the config grid is already the HBM-sized case
+    return a
 
 
 def log(*a):
@@ -91,7 +104,7 @@ def main():
     import torch
 
     from paper_2401_09516_amd import skr
-    from workloads import darcy_sequence, darcy_system, param_matrix
+    from workloads import darcy3d_system, darcy_sequence, darcy_system, param_matrix
     from workloads.device import upload_systems
 
     if not torch.cuda.is_available():
@@ -100,12 +113,19 @@ def main():
     skr.load_library()
     dev = "cuda:0"
     t = time.perf_counter()
-    systems = darcy_sequence(a.grid, a.systems)
+    if a.dim == 2:
+        systems = darcy_sequence(a.grid, a.systems)
+    else:
+        systems = []
+        for i in range(a.systems):
+            systems.append(darcy3d_system(a.grid, i, with_csr=(a.matrix == "csr")))
+            log(f"generated 3-D system {i}")
     P = param_matrix(systems)
     log(f"generated {a.systems} systems of n={systems[0].n} in {time.perf_counter() - t:.1f}s")
     Pd = torch.from_numpy(P).to(dev)
     ops, bs, xs = upload_systems(systems, dev, a.matrix)
-    nnz = int(systems[0].A.nnz)
+    G = a.grid
+    nnz = 5 * G * G - 4 * G if a.dim == 2 else 7 * G ** 3 - 6 * G * G     # nonzeros of the assembled operator
     stream = torch.cuda.current_stream()
     ctx = skr.skr_ctx_create(0, stream.cuda_stream)
     N, p = P.shape
@@ -231,34 +251,55 @@ def main():
         skr_prefix_iters = float(np.mean([res[i]["iters"] for i in pre]))
         gmres["skr_iters_mean_same_systems"] = skr_prefix_iters
 
-    # SpMV bandwidth: the config matrix (fits the 256 MB Infinity Cache) and a > 256 MB matrix
+    # SpMV bandwidth. 2-D: the config matrix (fits the 256 MB Infinity Cache) and a > 256 MB matrix.
+    # 3-D: the 7-point operator at the config grid, matrix-free and CSR.
+    def spmv_bytes(kind, dim, G_, nnz_):
+        n_ = G_ ** dim
+        if kind == "csr":
+            return 12.0 * nnz_ + 4.0 * (n_ + 1) + 16.0 * n_
+        return 8.0 * dim * G_ ** (dim - 1) * (G_ + 1) + 16.0 * n_
+
+    def time_spmv(op, n_, reps):
+        xd = torch.rand(n_, dtype=torch.float64, device=dev)
+        yd = torch.empty_like(xd)
+        return skr.skr_spmv_repeat(ctx, op, xd, yd, reps)
+
     spmv = {}
-    xd = torch.rand(systems[0].n, dtype=torch.float64, device=dev)
-    yd = torch.empty_like(xd)
-    ms = skr.skr_spmv_repeat(ctx, ops[0], xd, yd, 200)
-    byt = 12.0 * nnz + 4.0 * (systems[0].n + 1) + 16.0 * systems[0].n
-    spmv[f"csr_{a.grid}"] = dict(us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1),
-                                 bytes=byt, note="working set inside the 256 MB Infinity Cache: effective GB/s")
+    n0 = systems[0].n
+    ms = time_spmv(ops[0], n0, 200 if a.dim == 2 else 50)
+    byt = spmv_bytes(a.matrix, a.dim, G, nnz)
+    spmv[f"{a.matrix}{'' if a.dim == 2 else '7'}_{G}"] = dict(
+        us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1), bytes=byt,
+        note="repeated launches on one operator: a working set under 256 MB stays in the Infinity Cache, "
+             "so this is an effective rate")
+    if a.dim == 3:
+        other = "stencil" if a.matrix == "csr" else "csr"
+        from workloads.darcy3d import darcy3d_from_nodes
+        s0 = darcy3d_from_nodes(systems[0].a, with_csr=(other == "csr"))
+        oops, _, _ = upload_systems([s0], dev, other)
+        ms = time_spmv(oops[0], n0, 50)
+        byt = spmv_bytes(other, 3, G, nnz)
+        spmv[f"{other}7_{G}"] = dict(us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1), bytes=byt)
+        del oops, s0
     if a.spmv_grid:
         big = darcy_system(a.spmv_grid, 999)
-        bops, bbs, bxs = upload_systems([big], dev, "csr")
-        bx = torch.rand(big.n, dtype=torch.float64, device=dev)
-        by = torch.empty_like(bx)
-        ms = skr.skr_spmv_repeat(ctx, bops[0], bx, by, 20)
-        byt = 12.0 * big.A.nnz + 4.0 * (big.n + 1) + 16.0 * big.n
+        bn, bnnz = big.n, int(big.A.nnz)
+        bops, _, _ = upload_systems([big], dev, "csr")
+        ms = time_spmv(bops[0], bn, 20)
+        byt = spmv_bytes("csr", 2, a.spmv_grid, bnnz)
         spmv[f"csr_{a.spmv_grid}"] = dict(us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1),
                                           bytes=byt, frac_hbm=round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3))
         bops2, _, _ = upload_systems([big], dev, "stencil")
-        ms = skr.skr_spmv_repeat(ctx, bops2[0], bx, by, 20)
-        byt = 8.0 * (big.N_g * (big.N_g + 1) * 2) + 16.0 * big.n
+        ms = time_spmv(bops2[0], bn, 20)
+        byt = spmv_bytes("stencil", 2, a.spmv_grid, bnnz)
         spmv[f"stencil_{a.spmv_grid}"] = dict(us=round(1e3 * ms, 2), gbs=round(byt / (ms * 1e-3) / 1e9, 1),
                                               bytes=byt, frac_hbm=round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3))
-        del bops, bbs, bxs, bops2
+        del bops, bops2
     for c_ in ctxs:
         skr.skr_ctx_destroy(c_)
 
     cpu = None
-    if not a.no_cpu and a.cpu_systems > 0:
+    if not a.no_cpu and a.cpu_systems > 0 and a.dim == 2:
         import oracle
         try:
             from threadpoolctl import threadpool_info
@@ -287,9 +328,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"darcy2d-{a.grid}x{a.grid}-{a.systems}sys-sorted-gcrodr({a.m},{a.k})-{a.matrix}"
+        "config": {"workload": (f"darcy2d-{G}x{G}" if a.dim == 2 else f"darcy3d-{G}x{G}x{G}")
+                               + f"-{a.systems}sys-sorted-gcrodr({a.m},{a.k})-{a.matrix}"
                                + (f"-{C}chains" if C > 1 else ""),
-                   "grid": a.grid, "n": systems[0].n, "nnz": nnz, "systems": a.systems, "m": a.m, "k": a.k,
+                   "dim": a.dim, "grid": a.grid, "n": systems[0].n, "nnz": nnz, "systems": a.systems, "m": a.m, "k": a.k,
                    "rtol": a.rtol, "matrix": a.matrix, "chains": C,
                    "parallelism": "single chain" if C == 1 else f"{C} contiguous chains of the sorted order, "
                                                                  "one stream each"},
