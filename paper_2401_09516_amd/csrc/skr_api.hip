@@ -31,8 +31,9 @@ void launch_startup_apply(hipStream_t, const Work&, int, int);
 void launch_startup_project(hipStream_t, const Work&, double*);
 void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
 void launch_spmv_repeat(hipStream_t, const DevOp&, const double*, double*, int);
-void launch_sort(hipStream_t, const double*, long, long, long, double*, long long*, double*);
+void launch_sort(hipStream_t, const double*, long, long, long, double*, double*, long long*, double*);
 long sort_nmax();
+long sort_part_doubles(long, long);
 }  // namespace skr
 
 using namespace skr;
@@ -66,6 +67,8 @@ struct skr_ctx {
     // sort scratch
     double* sortD = nullptr;
     size_t sortD_cap = 0;
+    double* sortP = nullptr;       // slice partials of the distance pass
+    size_t sortP_cap = 0;
     long long* order_d = nullptr;
     double* dist_d = nullptr;
     size_t sortN_cap = 0;
@@ -254,6 +257,7 @@ int skr_ctx_destroy(skr_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     free_work(ctx->w);
     if (ctx->sortD) (void)hipFree(ctx->sortD);
+    if (ctx->sortP) (void)hipFree(ctx->sortP);
     if (ctx->order_d) (void)hipFree(ctx->order_d);
     if (ctx->dist_d) (void)hipFree(ctx->dist_d);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
@@ -339,7 +343,17 @@ int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64
             return fail(SKR_ENOMEM, "sort output buffers");
         ctx->sortN_cap = (size_t)N;
     }
-    launch_sort(ctx->stream, params_dev, (long)N, (long)p, (long)start, ctx->sortD, ctx->order_d, ctx->dist_d);
+    const size_t needp = (size_t)sort_part_doubles((long)N, (long)p);
+    if (ctx->sortP_cap < needp) {
+        if (ctx->sortP) (void)hipFree(ctx->sortP);
+        ctx->sortP = nullptr;
+        ctx->sortP_cap = 0;
+        if (hipMalloc((void**)&ctx->sortP, needp * sizeof(double)) != hipSuccess)
+            return fail(SKR_ENOMEM, "sort slice partials (%zu bytes)", needp * sizeof(double));
+        ctx->sortP_cap = needp;
+    }
+    launch_sort(ctx->stream, params_dev, (long)N, (long)p, (long)start, ctx->sortD, ctx->sortP, ctx->order_d,
+                ctx->dist_d);
     HIPLAUNCHCHK();
     HIPCHK(hipMemcpyAsync(order_host, ctx->order_d, N * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
     if (step_d2_host)

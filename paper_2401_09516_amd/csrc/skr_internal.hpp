@@ -39,40 +39,73 @@ struct DevOp {
     const double* az;
 };
 
-// One row of y = scale * (A x): CSR, 2-D 5-point or 3-D 7-point harmonic-mean stencil.
-__device__ __forceinline__ double op_row(const DevOp& op, const double* __restrict__ x, int i, double scale) {
+// One row of y = scale * (A x): CSR, 2-D 5-point or 3-D 7-point harmonic-mean stencil. KIND is the
+// operator kind when the caller knows it at compile time (each kind then gets its own register
+// allocation), or -1 to branch on op.kind.
+template <int KIND>
+__device__ __forceinline__ double op_row_k(const DevOp& op, const double* __restrict__ x, int i, double scale) {
+    const int kind = KIND >= 0 ? KIND : op.kind;
     double s = 0.0;
-    if (op.kind == SKR_OP_CSR) {
+    if (kind == SKR_OP_CSR) {
+        // Entries in groups of 8: every index, value and gather load of a group is in flight before
+        // the first product, at clamped indices; the products are added in entry order.
         const int e0 = op.rowptr[i], e1 = op.rowptr[i + 1];
-        for (int e = e0; e < e1; ++e) s = fma(op.val[e], x[op.colind[e]], s);
-    } else if (op.kind == SKR_OP_STENCIL7) {
+        for (int e = e0; e < e1; e += 8) {
+            int c[8];
+            double v[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = min(e + u, e1 - 1);
+                c[u] = op.colind[q];
+                v[u] = op.val[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < e1) s = fma(v[u], xv[u], s);
+        }
+    } else if (kind == SKR_OP_STENCIL7) {
         const int nx = op.nx, ny = op.ny, nz = op.nz, nxy = nx * ny;
         const int gz = i / nxy, gyx = i - gz * nxy, gy = gyx / nx, gx = gyx - gy * nx;
         const int fx = (gz * ny + gy) * (nx + 1) + gx, fy = (gz * (ny + 1) + gy) * nx + gx, fz = gz * nxy + gyx;
         const double aw = op.ax[fx], ae = op.ax[fx + 1];
         const double as = op.ay[fy], an = op.ay[fy + nx];
         const double ad = op.az[fz], au = op.az[fz + nxy];
-        s = ((aw + ae) + (as + an) + (ad + au)) * x[i];
-        if (gx > 0) s = fma(-aw, x[i - 1], s);
-        if (gx < nx - 1) s = fma(-ae, x[i + 1], s);
-        if (gy > 0) s = fma(-as, x[i - nx], s);
-        if (gy < ny - 1) s = fma(-an, x[i + nx], s);
-        if (gz > 0) s = fma(-ad, x[i - nxy], s);
-        if (gz < nz - 1) s = fma(-au, x[i + nxy], s);
+        // neighbour loads at clamped indices (a missing neighbour reads x[i]); its term is selected away
+        const bool hw = gx > 0, he = gx < nx - 1, hs = gy > 0, hn = gy < ny - 1, hd = gz > 0, hu = gz < nz - 1;
+        const double xc = x[i];
+        const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
+        const double xs = x[hs ? i - nx : i], xn = x[hn ? i + nx : i];
+        const double xd = x[hd ? i - nxy : i], xu = x[hu ? i + nxy : i];
+        s = ((aw + ae) + (as + an) + (ad + au)) * xc;
+        s = hw ? fma(-aw, xw, s) : s;
+        s = he ? fma(-ae, xe, s) : s;
+        s = hs ? fma(-as, xs, s) : s;
+        s = hn ? fma(-an, xn, s) : s;
+        s = hd ? fma(-ad, xd, s) : s;
+        s = hu ? fma(-au, xu, s) : s;
         s *= op.inv_h2;
     } else {
         const int nx = op.nx, ny = op.ny;
         const int r = i / nx, c = i - r * nx;
         const double aw = op.ax[r * (nx + 1) + c], ae = op.ax[r * (nx + 1) + c + 1];
         const double an = op.ay[r * nx + c], as = op.ay[(r + 1) * nx + c];
-        s = (aw + ae + an + as) * x[i];
-        if (c > 0) s = fma(-aw, x[i - 1], s);
-        if (c < nx - 1) s = fma(-ae, x[i + 1], s);
-        if (r > 0) s = fma(-an, x[i - nx], s);
-        if (r < ny - 1) s = fma(-as, x[i + nx], s);
+        const bool hw = c > 0, he = c < nx - 1, hn = r > 0, hs = r < ny - 1;
+        const double xc = x[i];
+        const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
+        const double xn = x[hn ? i - nx : i], xs = x[hs ? i + nx : i];
+        s = (aw + ae + an + as) * xc;
+        s = hw ? fma(-aw, xw, s) : s;
+        s = he ? fma(-ae, xe, s) : s;
+        s = hn ? fma(-an, xn, s) : s;
+        s = hs ? fma(-as, xs, s) : s;
         s *= op.inv_h2;
     }
     return s * scale;
+}
+__device__ __forceinline__ double op_row(const DevOp& op, const double* __restrict__ x, int i, double scale) {
+    return op_row_k<-1>(op, x, i, scale);
 }
 
 // ---------------------------------------------------------------------------------------------

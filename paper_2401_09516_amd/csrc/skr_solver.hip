@@ -157,7 +157,7 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
 // the estimate meets the tolerance or the step broke down; then v_j = w * inv_h (stored as a basis
 // column), w = A v_j, and partials of Q^T w (Q = [C, V_0..V_j], ncol = kc + j + 1 columns) and of
 // ||w||^2 (reduction column ncol).
-template <int NL>
+template <int NL, int KIND>
 __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
                                                  double* __restrict__ dst, double* __restrict__ basis,
                                                  int ld, int kc, int vbase, int j, int nblk, int npn,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
         }
     }
     const double xi = src[ii];
-    const double wraw = op_row(op, src, ii, 1.0);
+    const double wraw = op_row_k<KIND>(op, src, ii, 1.0);
     if (stopped) return;
     double tot;
     if (few) {
@@ -886,12 +886,22 @@ static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
 
 // With e0/e1 non-null the launch goes through hipExtLaunchKernelGGL, whose events take the start
 // and end timestamps of the kernel's own dispatch (no marker packets around it).
+template <int NL, int KIND>
+static void step_a_k(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
+                     hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_step_a<NL, KIND>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst, w.basis,
+                          w.ld, kc, w.k, j, w.nblk, pn_cnt(w), pn_src(w), w.part_a, (const double*)w.red1,
+                          (const double*)w.red2, w.H, w.Bm, w.ctrl);
+}
 template <int NL>
 static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
                    hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_step_a<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst, w.basis, w.ld,
-                          kc, w.k, j, w.nblk, pn_cnt(w), pn_src(w), w.part_a, (const double*)w.red1,
-                          (const double*)w.red2, w.H, w.Bm, w.ctrl);
+    if (op.kind == SKR_OP_CSR)
+        step_a_k<NL, SKR_OP_CSR>(s, w, op, src, dst, kc, j, e0, e1);
+    else if (op.kind == SKR_OP_STENCIL7)
+        step_a_k<NL, SKR_OP_STENCIL7>(s, w, op, src, dst, kc, j, e0, e1);
+    else
+        step_a_k<NL, SKR_OP_STENCIL5>(s, w, op, src, dst, kc, j, e0, e1);
 }
 template <int NL>
 static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {

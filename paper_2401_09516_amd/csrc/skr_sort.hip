@@ -7,9 +7,12 @@
 //    accumulated error by about p * 128 * 2^-106 relative (~1e-25 at p = 66564), far below half
 //    an ulp of the result: the value equals the correctly rounded exact sum except when that sum
 //    lies within that distance of a rounding boundary, so the summation order does not matter.
-//    One workgroup computes a 16 x 16 tile of pairs, staging 128-element chunks of both row
-//    blocks in LDS; only tiles on or above the diagonal are launched and each value is written to
-//    both (i, j) and (j, i).
+//    One workgroup computes a 16 x 16 tile of pairs over one slice of the parameter index, staging
+//    128-element chunks of both row blocks in LDS; only tiles on or above the diagonal are launched.
+//    When there are few tiles (few systems, long parameter vectors) the index range is split into
+//    slices on their own workgroups; each leaves its renormalised pair, and a second kernel adds
+//    the pairs of a tile in slice order with error-free sums (the bound above grows by one 2^-106
+//    term per slice) and writes each value to both (i, j) and (j, i).
 // 2. One workgroup walks the greedy path: N - 1 steps, each an arg-min over one row of d2 of the
 //    unvisited systems, ties to the lowest index, NaN/Inf never preferred (a row with no finite
 //    candidate takes the lowest unvisited index).
@@ -20,8 +23,30 @@ namespace skr {
 constexpr int TS = 16;     // tile side (pairs)
 constexpr int PCH = 128;   // parameter chunk staged in LDS
 
-__global__ __launch_bounds__(TS * TS) void k_sq_dist(const double* __restrict__ P, long N, long p,
-                                                     double* __restrict__ D) {
+// Slices of the parameter index per tile: enough workgroups to fill the chip, slices of at least
+// SLICE_MIN elements.
+constexpr long SLICE_MIN = 2048;
+constexpr long TARGET_WG = 2048;
+long sort_slices(long N, long p) {
+    const long nt = (N + TS - 1) / TS;
+    const long tiles = nt * (nt + 1) / 2;
+    const long by_p = (p + SLICE_MIN - 1) / SLICE_MIN;
+    const long by_wg = (TARGET_WG + tiles - 1) / tiles;
+    long q = by_p < by_wg ? by_p : by_wg;
+    return q < 1 ? 1 : q;
+}
+// Doubles of slice partials needed for (N, p): zero when one slice per tile suffices.
+long sort_part_doubles(long N, long p) {
+    const long q = sort_slices(N, p);
+    if (q == 1) return 0;
+    const long nt = (N + TS - 1) / TS;
+    return nt * (nt + 1) / 2 * q * TS * TS * 2;
+}
+
+// blockIdx.x = tile, blockIdx.y = slice. part == nullptr: one slice, the value goes to D directly;
+// otherwise the renormalised pair (s, lo) goes to part[((tile * nslice + slice) * 256 + thread) * 2].
+__global__ __launch_bounds__(TS * TS) void k_sq_dist(const double* __restrict__ P, long N, long p, long slen,
+                                                     double* __restrict__ D, double* __restrict__ part) {
 #pragma clang fp contract(off)
     // tile index -> (bi, bj) with bi <= bj, row-major over the upper triangle
     const long nt = (N + TS - 1) / TS;
@@ -33,8 +58,9 @@ __global__ __launch_bounds__(TS * TS) void k_sq_dist(const double* __restrict__ 
     const int ti = threadIdx.x / TS, tj = threadIdx.x % TS;
     const long i = bi * TS + ti, j = bj * TS + tj;
     double s = 0.0, lo = 0.0;
-    for (long e0 = 0; e0 < p; e0 += PCH) {
-        const int len = (int)((p - e0) < PCH ? (p - e0) : PCH);
+    const long p0 = (long)blockIdx.y * slen, p1 = (p0 + slen < p) ? p0 + slen : p;
+    for (long e0 = p0; e0 < p1; e0 += PCH) {
+        const int len = (int)((p1 - e0) < PCH ? (p1 - e0) : PCH);
         __syncthreads();
         for (int e = threadIdx.x; e < TS * PCH; e += TS * TS) {
             const int r = e / PCH, c = e % PCH;
@@ -57,6 +83,40 @@ __global__ __launch_bounds__(TS * TS) void k_sq_dist(const double* __restrict__ 
             lo = lo + (err + he);
         }
         // renormalise (s, lo) once per chunk so that |lo| stays below half an ulp of s
+        const double t2 = s + lo;
+        lo = lo - (t2 - s);
+        s = t2;
+    }
+    if (part) {
+        const size_t o = (((size_t)blockIdx.x * gridDim.y + blockIdx.y) * (TS * TS) + threadIdx.x) * 2;
+        part[o] = s;
+        part[o + 1] = lo;
+    } else if (i < N && j < N) {
+        const double v = s + lo;
+        D[i * N + j] = v;
+        D[j * N + i] = v;
+    }
+}
+
+// One thread per (tile, pair): adds the slices' pairs in slice order, rounds once, writes both halves.
+__global__ __launch_bounds__(TS * TS) void k_sq_combine(const double* __restrict__ part, long N, int nslice,
+                                                        double* __restrict__ D) {
+#pragma clang fp contract(off)
+    const long nt = (N + TS - 1) / TS;
+    long tid = blockIdx.x, bi = 0;
+    while (tid >= nt - bi) { tid -= nt - bi; ++bi; }
+    const long bj = bi + tid;
+    const int ti = threadIdx.x / TS, tj = threadIdx.x % TS;
+    const long i = bi * TS + ti, j = bj * TS + tj;
+    double s = 0.0, lo = 0.0;
+    for (int q = 0; q < nslice; ++q) {
+        const size_t o = (((size_t)blockIdx.x * nslice + q) * (TS * TS) + threadIdx.x) * 2;
+        const double hi = part[o], l2 = part[o + 1];
+        const double t = s + hi;
+        const double bb = t - s;
+        const double err = (s - (t - bb)) + (hi - bb);
+        s = t;
+        lo = lo + (err + l2);
         const double t2 = s + lo;
         lo = lo - (t2 - s);
         s = t2;
@@ -125,11 +185,19 @@ __global__ __launch_bounds__(GW) void k_greedy(const double* __restrict__ D, lon
 
 long sort_nmax() { return SORT_NMAX; }
 
-void launch_sort(hipStream_t s, const double* P, long N, long p, long start, double* D, long long* order,
-                 double* dist) {
+void launch_sort(hipStream_t s, const double* P, long N, long p, long start, double* D, double* part,
+                 long long* order, double* dist) {
     const long nt = (N + TS - 1) / TS;
     const long tiles = nt * (nt + 1) / 2;
-    if (tiles > 0 && p > 0) hipLaunchKernelGGL(k_sq_dist, dim3((unsigned)tiles), dim3(TS * TS), 0, s, P, N, p, D);
+    const long nslice = sort_slices(N, p);
+    const long slen = (p + nslice - 1) / nslice;
+    if (tiles > 0 && p > 0) {
+        hipLaunchKernelGGL(k_sq_dist, dim3((unsigned)tiles, (unsigned)nslice), dim3(TS * TS), 0, s, P, N, p, slen, D,
+                           nslice > 1 ? part : nullptr);
+        if (nslice > 1)
+            hipLaunchKernelGGL(k_sq_combine, dim3((unsigned)tiles), dim3(TS * TS), 0, s, (const double*)part, N,
+                               (int)nslice, D);
+    }
     hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GW), 0, s, (const double*)D, N, start, order, dist);
 }
 

@@ -64,7 +64,9 @@ def test_sort_config1(env):
 
 
 @pytest.mark.parametrize("N,p,start,dups", [(1, 5, 0, False), (2, 3, 1, False), (37, 300, 0, True),
-                                             (37, 300, 11, False), (50, 129, 3, True)])
+                                             (37, 300, 11, False), (50, 129, 3, True),
+                                             # few systems, long vectors: the parameter index is sliced
+                                             (3, 5000, 0, False), (20, 9001, 2, True), (5, 70001, 1, False)])
 def test_sort_random_ragged(env, N, p, start, dups):
     torch, skr, ctx = env
     log(f"[sort] random N={N} p={p} start={start} dups={dups}")
