@@ -27,6 +27,20 @@ Readings adopted where the paper is silent or loose (each is mirrored by the GPU
   the k harmonic Ritz vectors of the standard form (Alg. 2, else branch) when that cycle ran more
   than k steps; otherwise no recycle space is formed.
 * A system whose right-hand side is zero returns x = 0 and passes the incoming recycle space on.
+
+Mixed-precision mode (``basis_fp32=True``; the FP32-inner / FP64-refinement variant of the method,
+an extension that the paper does not describe):
+* Every column kept in the subspace stores is rounded to FP32 when it is stored: the Arnoldi
+  vectors v_j and the recycle pair C_k, U_k (after the start-up QR and after each cycle). All
+  arithmetic, x, r, the operator, Hbar, G, the least-squares and eigen problems stay FP64; the
+  operator is applied to the stored (rounded) vector.
+* Iterative refinement at cycle granularity: every cycle starts from the true residual
+  r = b - A x computed in FP64 (not at the very first cycle from x = 0, where r = b already),
+  projected onto range(C) as at a system start (x += U C^T r, r -= C C^T r), so each cycle
+  computes an FP32-stored correction to an FP64 iterate. The projection keeps r orthogonal to C,
+  which the cycle's least-squares problem on [C, V] relies on; a true residual is only
+  orthogonal to the FP32-stored C up to rounding, and without the projection that component
+  grows from cycle to cycle.
 """
 from __future__ import annotations
 
@@ -42,6 +56,15 @@ NONFINITE = 3
 
 RANK_DROP_TOL = 1e-7
 BREAKDOWN_TOL = 1e-14
+
+
+def fp32_store(v: np.ndarray) -> np.ndarray:
+    """Round to the nearest FP32 value (ties to even), held in FP64."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _keep(v: np.ndarray) -> np.ndarray:
+    return v
 
 
 @dataclass
@@ -136,11 +159,12 @@ def harmonic_ritz_generalized(G: np.ndarray, WtV: np.ndarray, k: int):
 # ----------------------------------------------------------------------------------------------
 # Arnoldi with (I - C C^T) A and CGS2 (Eq. 3 when C is empty, Eq. 6 otherwise)
 # ----------------------------------------------------------------------------------------------
-def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool = False):
+def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool = False, store=_keep):
     """Up to s Arnoldi steps from v1 = r/||r||.
 
     Returns (V, Hbar, B, est, breakdown): V is n x (j+1), Hbar (j+1) x j, B kc x j for the j steps
-    taken, est the least-squares residual of Hbar against ||r|| e1.
+    taken, est the least-squares residual of Hbar against ||r|| e1. ``store`` is applied to every
+    Arnoldi vector as it is stored (identity, or FP32 rounding in the mixed-precision mode).
     """
     n = r.size
     kc = 0 if C is None else C.shape[1]
@@ -148,7 +172,7 @@ def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool
     basis = np.zeros((n, kc + s + 1), order="F")       # [C, v1, v2, ...]
     if kc:
         basis[:, :kc] = C
-    basis[:, kc] = r / beta
+    basis[:, kc] = store(r / beta)
     Hbar = np.zeros((s + 1, s))
     B = np.zeros((kc, s))
     est = beta
@@ -172,7 +196,7 @@ def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool
             Hbar[j + 1, j] = 0.0
         else:
             Hbar[j + 1, j] = hn
-            basis[:, kc + j + 1] = w / hn
+            basis[:, kc + j + 1] = store(w / hn)
         est = ls_residual(Hbar[:j + 2, :j + 1], beta)
         if breakdown:
             break
@@ -185,8 +209,9 @@ def arnoldi_cycle(A, r: np.ndarray, C, s: int, tol_abs: float, full_cycles: bool
 # ----------------------------------------------------------------------------------------------
 # Start-up with a recycled space (App. B.1; Alg. 2, if branch)
 # ----------------------------------------------------------------------------------------------
-def startup(A, Y: np.ndarray, r0: np.ndarray):
-    """[Q,R] = qr(A Y); C = Q; U = Y R^-1; x1 = U C^T r0; r1 = r0 - C C^T r0 (with column drops)."""
+def startup(A, Y: np.ndarray, r0: np.ndarray, store=_keep):
+    """[Q,R] = qr(A Y); C = Q; U = Y R^-1; x1 = U C^T r0; r1 = r0 - C C^T r0 (with column drops).
+    C and U pass through ``store`` before they are used."""
     Z = A @ Y
     keep = list(range(Y.shape[1]))
     while keep:
@@ -199,8 +224,8 @@ def startup(A, Y: np.ndarray, r0: np.ndarray):
     dropped = Y.shape[1] - len(keep)
     if not keep:
         return np.zeros_like(r0), r0.copy(), None, None, dropped
-    C = Q
-    U = sla.solve_triangular(R, Y[:, keep].T, trans="T", lower=False).T    # Y R^{-1}
+    C = store(Q)
+    U = store(sla.solve_triangular(R, Y[:, keep].T, trans="T", lower=False).T)    # Y R^{-1}
     c = C.T @ r0
     x1 = U @ c
     r1 = r0 - C @ c
@@ -211,8 +236,10 @@ def startup(A, Y: np.ndarray, r0: np.ndarray):
 # One system
 # ----------------------------------------------------------------------------------------------
 def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 10,
-           rtol: float = 1e-8, maxit: int = 10000, full_cycles: bool = False) -> SolveResult:
-    """Solve A x = b from x0 = 0, recycling span(Y) (App. B.2, Alg. 2). Returns the next Y in Y_next."""
+           rtol: float = 1e-8, maxit: int = 10000, full_cycles: bool = False,
+           basis_fp32: bool = False) -> SolveResult:
+    """Solve A x = b from x0 = 0, recycling span(Y) (App. B.2, Alg. 2). Returns the next Y in Y_next.
+    ``basis_fp32`` selects the mixed-precision mode described in the module notes."""
     if k < 0 or m <= k or rtol <= 0:
         raise ValueError("need 0 <= k < m and rtol > 0")
     b = np.asarray(b, dtype=np.float64)
@@ -224,14 +251,17 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
     if bnorm == 0.0:
         return SolveResult(x, CONVERGED, 0, 0, 0, 0.0, 0.0, Y_next=Y)
     tol_abs = rtol * bnorm
+    store = fp32_store if basis_fp32 else _keep
     r = b.copy()
+    r_is_true = True                 # r equals b - A x computed directly (x = 0 here)
     C = U = None
     spmv = iters = cycles = 0
     k_start = dropped = 0
     if k > 0 and Y is not None and Y.shape[1] > 0:
-        x, r, C, U, dropped = startup(A, Y, r)
+        x, r, C, U, dropped = startup(A, Y, r, store)
         spmv += Y.shape[1]
         k_start = 0 if C is None else C.shape[1]
+        r_is_true = C is None
     hist = [float(np.linalg.norm(r))]
     est = hist[0]
     status = None
@@ -245,13 +275,24 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
             status = CONVERGED
         else:
             r = rt
+            r_is_true = True
     while status is None:
         if iters >= maxit:
             status = MAXIT
             break
+        if basis_fp32 and not r_is_true:
+            # refinement step: the cycle corrects the FP64 iterate from its true residual, first
+            # projected onto range(C) as at a system start (App. B.1): x += U C^T r, r -= C C^T r
+            r = b - A @ x
+            spmv += 1
+            if C is not None:
+                c = C.T @ r
+                x = x + U @ c
+                r = r - C @ c
+        r_is_true = False
         s = m if C is None else m - C.shape[1]
         s = min(s, maxit - iters)
-        V, Hbar, B, est, breakdown = arnoldi_cycle(A, r, C, s, tol_abs, full_cycles)
+        V, Hbar, B, est, breakdown = arnoldi_cycle(A, r, C, s, tol_abs, full_cycles, store)
         j = Hbar.shape[1]
         iters += j
         spmv += j
@@ -269,8 +310,8 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
                 if P.shape[1] > 0:
                     Yt = V[:, :j] @ P
                     Q, R = qr_pos(Hbar @ P)
-                    C = V @ Q
-                    U = sla.solve_triangular(R, Yt.T, trans="T", lower=False).T
+                    C = store(V @ Q)
+                    U = store(sla.solve_triangular(R, Yt.T, trans="T", lower=False).T)
         else:
             # GCRO-DR cycle (Alg. 2, while body)
             kc = C.shape[1]
@@ -290,8 +331,8 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
             if P.shape[1] > 0:
                 Yt = Vhat @ P
                 Q, R = qr_pos(G @ P)
-                C = What @ Q
-                U = sla.solve_triangular(R, Yt.T, trans="T", lower=False).T
+                C = store(What @ Q)
+                U = store(sla.solve_triangular(R, Yt.T, trans="T", lower=False).T)
         hist.append(float(np.linalg.norm(r)))
         if est <= tol_abs or breakdown:
             rt = b - A @ x
@@ -301,6 +342,7 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
                 status = BREAKDOWN if breakdown else CONVERGED
                 break
             r = rt
+            r_is_true = True
     if status == MAXIT:
         rt_norm = float(np.linalg.norm(b - A @ x))
         spmv += 1
@@ -315,7 +357,8 @@ def gmres(A, b, m: int = 30, rtol: float = 1e-8, maxit: int = 10000) -> SolveRes
 
 
 def solve_sequence(As, bs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
-                   maxit: int = 10000, full_cycles: bool = False, limit: int | None = None):
+                   maxit: int = 10000, full_cycles: bool = False, limit: int | None = None,
+                   basis_fp32: bool = False):
     """Solve the systems in ``order`` (identity when None), carrying Y = U_k from each to the next.
 
     Returns a list of SolveResult indexed by original system index (None for systems not solved
@@ -328,7 +371,7 @@ def solve_sequence(As, bs, order=None, m: int = 30, k: int = 10, rtol: float = 1
     results = [None] * N
     Y = None
     for idx in order:
-        res = gcrodr(As[idx], bs[idx], Y, m, k, rtol, maxit, full_cycles)
+        res = gcrodr(As[idx], bs[idx], Y, m, k, rtol, maxit, full_cycles, basis_fp32)
         results[idx] = res
         Y = res.Y_next
     return results
