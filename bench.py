@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=40000)
     ap.add_argument("--matrix", choices=["csr", "stencil"], default="csr")
+    ap.add_argument("--mixed", action="store_true",
+                    help="FP32-stored Arnoldi vectors and recycle space, FP64 arithmetic and residuals, "
+                         "one refinement step per cycle (SKR_FLAG_MIXED)")
     ap.add_argument("--chains", type=int, default=1,
                     help="split the sorted order into this many contiguous chains, solved concurrently on "
                          "their own contexts and streams (the sorted-partition parallel scheme, App. E)")
@@ -129,11 +132,12 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = skr.skr_ctx_create(0, stream.cuda_stream)
     N, p = P.shape
+    mode = skr.SKR_FLAG_MIXED if a.mixed else 0
 
     if a.pmc_probe:
         order, _ = skr.skr_sort(ctx, Pd, N, p, 0, want_dist=False)
         rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
-                                         flags=skr.SKR_FLAG_PROFILE)
+                                         flags=skr.SKR_FLAG_PROFILE | mode)
         torch.cuda.synchronize()
         sa = skr.skr_profile_get(ctx)["kernels"]["step_a"]
         nb = a.copy_mib << 20
@@ -156,7 +160,7 @@ def main():
     def solve_chains(order, flags):
         if C == 1:
             return skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
-                                          flags=flags)
+                                          flags=flags | mode)
         import threading
         slices = [[int(i) for i in sl] for sl in np.array_split(np.asarray(order), C)]
         out = [None] * C
@@ -166,7 +170,7 @@ def main():
                 sl = slices[c]
                 out[c] = skr.skr_solve_sequence(ctxs[c], [ops[i] for i in sl], [bs[i] for i in sl],
                                                 [xs[i] for i in sl], None, m=a.m, k=a.k, rtol=a.rtol,
-                                                maxit=a.maxit, flags=flags)
+                                                maxit=a.maxit, flags=flags | mode)
             except BaseException as e:   # re-raised in the calling thread
                 out[c] = e
         th = [threading.Thread(target=run, args=(c,)) for c in range(C)]
@@ -241,7 +245,8 @@ def main():
         gxs = [torch.zeros_like(bs[i]) for i in pre]
         torch.cuda.synchronize()
         tg = time.perf_counter()
-        rcg, resg = skr.skr_solve_sequence(ctx, gops, gbs, gxs, None, m=a.m, k=0, rtol=a.rtol, maxit=a.maxit)
+        rcg, resg = skr.skr_solve_sequence(ctx, gops, gbs, gxs, None, m=a.m, k=0, rtol=a.rtol, maxit=a.maxit,
+                                           flags=mode)
         torch.cuda.synchronize()
         tg = time.perf_counter() - tg
         gconv = sum(r["status"] == skr.SKR_CONVERGED for r in resg)
@@ -309,7 +314,7 @@ def main():
         pre = [int(i) for i in order[:a.cpu_systems]]
         tc = time.perf_counter()
         ref = oracle.solve_sequence([systems[i].A for i in pre], [systems[i].b for i in pre], None,
-                                    a.m, a.k, a.rtol, a.maxit)
+                                    a.m, a.k, a.rtol, a.maxit, basis_fp32=a.mixed)
         tc = time.perf_counter() - tc
         cpu = dict(value=round(len(pre) / tc, 4), unit="systems/s", cores=int(cores), kind="oracle",
                    sample=f"first {len(pre)} systems of the sorted chain (the first starts without a recycle "
@@ -330,9 +335,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"darcy2d-{G}x{G}" if a.dim == 2 else f"darcy3d-{G}x{G}x{G}")
                                + f"-{a.systems}sys-sorted-gcrodr({a.m},{a.k})-{a.matrix}"
+                               + ("-fp32basis" if a.mixed else "")
                                + (f"-{C}chains" if C > 1 else ""),
                    "dim": a.dim, "grid": a.grid, "n": systems[0].n, "nnz": nnz, "systems": a.systems, "m": a.m, "k": a.k,
                    "rtol": a.rtol, "matrix": a.matrix, "chains": C,
+                   "basis_storage": "fp32 (FP64 arithmetic and refinement)" if a.mixed else "fp64",
                    "parallelism": "single chain" if C == 1 else f"{C} contiguous chains of the sorted order, "
                                                                  "one stream each"},
         "roofline": roofline,

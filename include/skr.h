@@ -82,11 +82,20 @@ typedef struct {
 
 /* Solver options. m: maximum subspace size per cycle (1..62); k: recycled vectors (0 = GMRES(m),
  * k < m, k <= 32); rtol: relative residual target; maxit: maximum Arnoldi steps per system;
- * flags: 0 or a combination of SKR_FLAG_PROFILE and SKR_FLAG_FOLD. */
+ * flags: 0 or a combination of SKR_FLAG_PROFILE, SKR_FLAG_FOLD and SKR_FLAG_MIXED. */
 #define SKR_FLAG_PROFILE 1u   /* time every 16th Arnoldi step's kernels with hipEvents (see skr_profile_get) */
 #define SKR_FLAG_FOLD    2u   /* fold the per-workgroup partials of every grid reduction into 64 rows
                                  before they are re-summed; done anyway above 256 workgroups
                                  (n > 65,536), where it keeps the reduction cost linear in n */
+#define SKR_FLAG_MIXED   4u   /* mixed precision: the Arnoldi vectors and the recycle pair C_k, U_k
+                                 are stored in FP32 (round to nearest even), halving the bytes the
+                                 Arnoldi steps stream; every product, sum, x, r, the operator and the
+                                 small dense problems stay FP64. Each cycle after the first starts
+                                 from the true residual r = b - A x (FP64), projected onto range(C)
+                                 (x += U C^T r, r -= C C^T r): iterative refinement with one cycle
+                                 as the inner correction. relres_true is the FP64 residual of the
+                                 FP64 solution, so rtol keeps its meaning. An extension of the
+                                 paper's method (Alg. 2 is stated in exact arithmetic). */
 
 typedef struct {
     int32_t m;

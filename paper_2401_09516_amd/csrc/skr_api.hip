@@ -28,7 +28,7 @@ void launch_spmm(hipStream_t, const Work&, const DevOp&, int);
 void launch_startup_gram(hipStream_t, const Work&, int);
 void launch_chol(hipStream_t, const Work&, int, int);
 void launch_startup_apply(hipStream_t, const Work&, int, int);
-void launch_startup_project(hipStream_t, const Work&, double*);
+void launch_startup_project(hipStream_t, const Work&, double*, int, int);
 void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
 void launch_spmv_repeat(hipStream_t, const DevOp&, const double*, double*, int);
 void launch_sort(hipStream_t, const double*, long, long, long, double*, double*, long long*, double*);
@@ -50,11 +50,12 @@ static double op_bytes(const DevOp& op, int64_t nvals) {
                8.0 * (double)(op.nz + 1) * op.ny * op.nx + 8.0 * n;
     return 8.0 * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 8.0 * n;
 }
-static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double& a, double& b, double& c) {
+// es: bytes per stored basis element (8, or 4 with an FP32 basis); w and the operand stay FP64.
+static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double es, double& a, double& b, double& c) {
     const double n = op.n;
-    a = op_bytes(op, nvals) + 8.0 * n /* w */ + 8.0 * n /* v_j */ + 8.0 * n * (ncol - 1);
-    b = 8.0 * n * ncol + 16.0 * n;
-    c = 8.0 * n * ncol + 16.0 * n;
+    a = op_bytes(op, nvals) + 8.0 * n /* w */ + es * n /* v_j */ + es * n * (ncol - 1);
+    b = es * n * ncol + 16.0 * n;
+    c = es * n * ncol + 16.0 * n;
 }
 
 struct skr_ctx;
@@ -398,6 +399,8 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
     bool any_maxit = false;
     const bool profile = (opts->flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
     w.fold = (w.nblk > FOLD_MIN || (opts->flags & SKR_FLAG_FOLD)) ? 1 : 0;
+    w.mixed = (opts->flags & SKR_FLAG_MIXED) ? 1 : 0;
+    const double es = w.mixed ? 4.0 : 8.0;
     int samp_j[PROF_MAXSAMP];
     for (int64_t q = 0; q < N; ++q) {
         const int64_t idx = order ? order[q] : q;
@@ -414,8 +417,10 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
         if (op.kind == SKR_OP_CSR) {
             launch_check_finite(s, w, op.val, (long)nvals);
         } else {
-            launch_check_finite(s, w, op.ax, (long)op.ny * (op.nx + 1));
-            launch_check_finite(s, w, op.ay, (long)(op.ny + 1) * op.nx);
+            const long nzl = op.kind == SKR_OP_STENCIL7 ? (long)op.nz : 1L;
+            launch_check_finite(s, w, op.ax, nzl * op.ny * (op.nx + 1));
+            launch_check_finite(s, w, op.ay, nzl * (op.ny + 1) * op.nx);
+            if (op.kind == SKR_OP_STENCIL7) launch_check_finite(s, w, op.az, (nzl + 1) * op.ny * op.nx);
         }
         HIPLAUNCHCHK();
         if ((rc = read_ctrl(ctx))) return rc;
@@ -452,7 +457,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
                 launch_startup_gram(s, w, ke);
                 launch_chol(s, w, ke, 0);
                 launch_startup_apply(s, w, 0, 1);
-                launch_startup_project(s, w, x);
+                launch_startup_project(s, w, x, ke, 0);
                 HIPLAUNCHCHK();
             }
             if ((rc = read_ctrl(ctx))) return rc;
@@ -461,16 +466,27 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
         }
         int status = -1;
         double est = hc.beta;
+        // r equals b - A x computed directly (at x = 0, or right after a true-residual product)
+        bool r_is_true = kc == 0;
         if (hc.beta <= tol_abs) {
             launch_true_residual(s, w, op, b, x);
             HIPLAUNCHCHK();
             if ((rc = read_ctrl(ctx))) return rc;
             spmv += 1;
             if (std::sqrt(hc.res2) <= tol_abs) status = SKR_CONVERGED;
+            r_is_true = true;
         }
         // ---- Arnoldi cycles (Alg. 2)
         while (status < 0) {
             if (iters >= maxit) { status = SKR_MAXIT; break; }
+            if (w.mixed && !r_is_true) {
+                // refinement step: true FP64 residual, projected onto range(C) as at a system start
+                launch_true_residual(s, w, op, b, x);
+                spmv += 1;
+                if (kc > 0) launch_startup_project(s, w, x, kc, 1);
+                HIPLAUNCHCHK();
+            }
+            r_is_true = false;
             int scyc = (kc == 0) ? m : m - kc;
             scyc = (int)std::min<int64_t>(scyc, maxit - iters);
             int nsamp = 0;
@@ -500,14 +516,14 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
                     for (int e = 0; e < 3; ++e)
                         HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[6 * q + 2 * e], ctx->ev[6 * q + 2 * e + 1]));
                     double ba, bb, bc;
-                    step_bytes(op, nvals, kc + samp_j[q] + 1, ba, bb, bc);
+                    step_bytes(op, nvals, kc + samp_j[q] + 1, es, ba, bb, bc);
                     pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;
                     pr.step_b.launches++; pr.step_b.ms += t[1]; pr.step_b.bytes += bb;
                     pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc;
                 }
                 for (int j = 0; j < jd; ++j) {
                     double ba, bb, bc;
-                    step_bytes(op, nvals, kc + j + 1, ba, bb, bc);
+                    step_bytes(op, nvals, kc + j + 1, es, ba, bb, bc);
                     pr.step_bytes += ba + bb + bc;
                 }
                 pr.steps += jd;
@@ -534,6 +550,7 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
                     status = brk ? SKR_BREAKDOWN : SKR_CONVERGED;
                     break;
                 }
+                r_is_true = true;
             }
         }
         if (status == SKR_MAXIT) {

@@ -39,12 +39,21 @@ struct DevOp {
     const double* az;
 };
 
+// Round to the nearest FP32 value (ties to even), held in FP64.
+__device__ __forceinline__ double rnd32(double v) { return (double)(float)v; }
+
 // One row of y = scale * (A x): CSR, 2-D 5-point or 3-D 7-point harmonic-mean stencil. KIND is the
 // operator kind when the caller knows it at compile time (each kind then gets its own register
-// allocation), or -1 to branch on op.kind.
-template <int KIND>
-__device__ __forceinline__ double op_row_k(const DevOp& op, const double* __restrict__ x, int i, double scale) {
+// allocation), or -1 to branch on op.kind. XT is the element type of x. With RND the row is that of
+// A v with v = rnd32(scale * x) (the FP32-stored vector the product is defined on), and no scaling
+// follows.
+template <int KIND, typename XT = double, bool RND = false>
+__device__ __forceinline__ double op_row_k(const DevOp& op, const XT* __restrict__ x, int i, double scale) {
     const int kind = KIND >= 0 ? KIND : op.kind;
+    auto X = [&](int idx) -> double {
+        const double v = (double)x[idx];
+        return RND ? rnd32(v * scale) : v;
+    };
     double s = 0.0;
     if (kind == SKR_OP_CSR) {
         // Entries in groups of 8: every index, value and gather load of a group is in flight before
@@ -60,7 +69,7 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const double* __rest
                 v[u] = op.val[q];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
+            for (int u = 0; u < 8; ++u) xv[u] = X(c[u]);
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (e + u < e1) s = fma(v[u], xv[u], s);
@@ -74,10 +83,10 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const double* __rest
         const double ad = op.az[fz], au = op.az[fz + nxy];
         // neighbour loads at clamped indices (a missing neighbour reads x[i]); its term is selected away
         const bool hw = gx > 0, he = gx < nx - 1, hs = gy > 0, hn = gy < ny - 1, hd = gz > 0, hu = gz < nz - 1;
-        const double xc = x[i];
-        const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
-        const double xs = x[hs ? i - nx : i], xn = x[hn ? i + nx : i];
-        const double xd = x[hd ? i - nxy : i], xu = x[hu ? i + nxy : i];
+        const double xc = X(i);
+        const double xw = X(hw ? i - 1 : i), xe = X(he ? i + 1 : i);
+        const double xs = X(hs ? i - nx : i), xn = X(hn ? i + nx : i);
+        const double xd = X(hd ? i - nxy : i), xu = X(hu ? i + nxy : i);
         s = ((aw + ae) + (as + an) + (ad + au)) * xc;
         s = hw ? fma(-aw, xw, s) : s;
         s = he ? fma(-ae, xe, s) : s;
@@ -92,9 +101,9 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const double* __rest
         const double aw = op.ax[r * (nx + 1) + c], ae = op.ax[r * (nx + 1) + c + 1];
         const double an = op.ay[r * nx + c], as = op.ay[(r + 1) * nx + c];
         const bool hw = c > 0, he = c < nx - 1, hn = r > 0, hs = r < ny - 1;
-        const double xc = x[i];
-        const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
-        const double xn = x[hn ? i - nx : i], xs = x[hs ? i + nx : i];
+        const double xc = X(i);
+        const double xw = X(hw ? i - 1 : i), xe = X(he ? i + 1 : i);
+        const double xn = X(hn ? i - nx : i), xs = X(hs ? i + nx : i);
         s = (aw + ae + an + as) * xc;
         s = hw ? fma(-aw, xw, s) : s;
         s = he ? fma(-ae, xe, s) : s;
@@ -102,10 +111,10 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const double* __rest
         s = hs ? fma(-as, xs, s) : s;
         s *= op.inv_h2;
     }
-    return s * scale;
+    return RND ? s : s * scale;
 }
 __device__ __forceinline__ double op_row(const DevOp& op, const double* __restrict__ x, int i, double scale) {
-    return op_row_k<-1>(op, x, i, scale);
+    return op_row_k<-1, double, false>(op, x, i, scale);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -454,8 +463,11 @@ __device__ __forceinline__ int logical_block(int b, int nblk) {
 // ---------------------------------------------------------------------------------------------
 struct Work {
     int n = 0, ld = 0, nblk = 0, m = 0, k = 0;
-    double* basis = nullptr;     // [C (k cols) | V (m+1 cols)], column-major, leading dim ld
-    double* U = nullptr;         // k cols
+    // [C (k cols) | V (m+1 cols)] and U (k cols), column-major, leading dim ld; the elements are
+    // doubles, or floats when mixed (the buffers are sized for doubles either way)
+    double* basis = nullptr;
+    double* U = nullptr;
+    int mixed = 0;
     double* W[2] = {nullptr, nullptr};
     double* r = nullptr;
     double* part_a = nullptr;    // nblk * NC partials written by step pass A (read by pass B)

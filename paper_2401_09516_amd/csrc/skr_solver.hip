@@ -23,12 +23,11 @@ __device__ __forceinline__ const double* qcol(const double* basis, int ld, int k
 }
 
 // ---------------------------------------------------------------------------------------------
-// Solve set-up: x = 0, r = b, ||b||, finiteness of b.
+// Solve set-up: x = 0, r = b, partials of ||b||^2 (closed by k_norm_finish).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(ROWS) void k_init(const double* __restrict__ b, double* __restrict__ x,
-                                               double* __restrict__ r, int n, int nblk, double rtol,
-                                               double* part1, unsigned* counter, Ctrl* ctrl) {
-    __shared__ double sh[NWAVE * NC];
+                                               double* __restrict__ r, int n, int nblk, double* part_n) {
+    __shared__ double sh[NWAVE];
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     double v = 0.0;
@@ -38,25 +37,40 @@ __global__ __launch_bounds__(ROWS) void k_init(const double* __restrict__ b, dou
         r[i] = bi;
         v = bi * bi;
     }
-    double tot;
-    if (grid_sum1(v, part1, counter, nblk, lb, sh, &tot)) {
-        if (threadIdx.x == 0) {
-            const double bn = sqrt(tot);
-            ctrl->stop = 0;
-            ctrl->j_done = 0;
-            ctrl->breakdown = 0;
-            ctrl->kc = 0;
-            ctrl->k_new = 0;
-            ctrl->eig_fail = 0;
-            ctrl->nonfinite = (isfinite(bn) ? 0 : 1) | ctrl->nonfinite;
-            ctrl->bnorm = bn;
-            ctrl->tol_abs = rtol * bn;
-            ctrl->beta = bn;
-            ctrl->inv_h = bn > 0.0 ? 1.0 / bn : 0.0;
-            ctrl->est = bn;
-            ctrl->res2 = tot;
-            ctrl->g[0] = bn;
-        }
+    block_partial1(v, part_n, lb, sh);
+}
+
+// Close of a squared-norm reduction whose per-workgroup partials (folded or not) the previous
+// kernel left: one workgroup sums them in the fixed order every Arnoldi pass A uses for the same
+// partials, so the host and the next cycle see bitwise the same value, and sets the control-block
+// fields that follow from it. No fences or atomics: the kernel boundary orders it after the writer.
+enum { FIN_INIT = 0, FIN_TRUE_RES = 1, FIN_PROJECT = 2 };
+__global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__ pn, int npn, int mode, double rtol,
+                                                      int ke, Ctrl* ctrl) {
+    __shared__ double sh[NWAVE * NC];
+    const double tot = sum_partials1(pn, npn, sh);
+    if (threadIdx.x != 0) return;
+    const double bt = sqrt(tot);
+    ctrl->beta = bt;
+    ctrl->inv_h = bt > 0.0 ? 1.0 / bt : 0.0;
+    ctrl->g[0] = bt;
+    ctrl->stop = 0;
+    if (mode == FIN_INIT) {
+        ctrl->j_done = 0;
+        ctrl->breakdown = 0;
+        ctrl->kc = 0;
+        ctrl->k_new = 0;
+        ctrl->eig_fail = 0;
+        ctrl->nonfinite = (isfinite(bt) ? 0 : 1) | ctrl->nonfinite;
+        ctrl->bnorm = bt;
+        ctrl->tol_abs = rtol * bt;
+        ctrl->est = bt;
+        ctrl->res2 = tot;
+    } else if (mode == FIN_TRUE_RES) {
+        ctrl->res2 = tot;
+    } else {
+        ctrl->est = bt;
+        ctrl->kc = ke;
     }
 }
 
@@ -157,9 +171,9 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
 // the estimate meets the tolerance or the step broke down; then v_j = w * inv_h (stored as a basis
 // column), w = A v_j, and partials of Q^T w (Q = [C, V_0..V_j], ncol = kc + j + 1 columns) and of
 // ||w||^2 (reduction column ncol).
-template <int NL, int KIND>
+template <int NL, int KIND, typename BT>
 __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
-                                                 double* __restrict__ dst, double* __restrict__ basis,
+                                                 double* __restrict__ dst, BT* __restrict__ basis,
                                                  int ld, int kc, int vbase, int j, int nblk, int npn,
                                                  const double* __restrict__ part_n, double* __restrict__ part_a,
                                                  const double* __restrict__ red1, const double* __restrict__ red2,
@@ -178,12 +192,14 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     const int nst = ncol - 1;                 // stored columns (v_j itself is formed here)
     // Every global load of the kernel is issued before the first decision that waits on one: the
     // stop flag, the basis rows, the product with the unscaled previous vector (A is linear, so the
-    // scale is applied afterwards) and the partials of ||w||^2.
+    // scale is applied afterwards) and the partials of ||w||^2. With an FP32 basis the product is
+    // taken on the stored (rounded) vector, which needs the scale: it follows the closing instead.
+    constexpr bool MIX = sizeof(BT) == 4;
     const int stopped = ctrl->stop;
     double q[NL];
     if (nst > 0) {
 #pragma unroll
-        for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < nst ? c : nst - 1, kc, vbase, ld) + ii];
+        for (int c = 0; c < NL; ++c) q[c] = (double)basis[qoff(c < nst ? c : nst - 1, kc, vbase, ld) + ii];
     } else {
 #pragma unroll
         for (int c = 0; c < NL; ++c) q[c] = 0.0;
@@ -198,7 +214,8 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
         }
     }
     const double xi = src[ii];
-    const double wraw = op_row_k<KIND>(op, src, ii, 1.0);
+    double wraw = 0.0;
+    if constexpr (!MIX) wraw = op_row_k<KIND>(op, src, ii, 1.0);
     if (stopped) return;
     double tot;
     if (few) {
@@ -245,10 +262,16 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     __syncthreads();
     if (s_stop) return;
     const double scale = s_scale;
-    const double vj = xi * scale;
-    double w = wraw * scale;
+    double vj, w;
+    if constexpr (MIX) {
+        vj = rnd32(xi * scale);
+        w = op_row_k<KIND, double, true>(op, src, ii, scale);
+    } else {
+        vj = xi * scale;
+        w = wraw * scale;
+    }
     if (valid) {
-        basis[(size_t)(vbase + j) * ld + i] = vj;
+        basis[(size_t)(vbase + j) * ld + i] = (BT)vj;
         dst[i] = w;
     } else {
         w = 0.0;
@@ -265,8 +288,8 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 
 // Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
 // partials of Q^T w.
-template <int NL>
-__global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const double* __restrict__ basis,
+template <int NL, typename BT>
+__global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
                                                  double* __restrict__ red1, const Ctrl* ctrl) {
@@ -280,7 +303,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
     const int ii = valid ? i : n - 1;
     double q[NL];
 #pragma unroll
-    for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
+    for (int c = 0; c < NL; ++c) q[c] = (double)basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
     sum_partials(part_a, npa, ncol + 1, sh, hs);
@@ -298,8 +321,8 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
 }
 
 // Pass C: h2 = Q^T w (sum of pass B's partials, stored), w -= Q h2, partials of ||w||^2.
-template <int NL>
-__global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const double* __restrict__ basis,
+template <int NL, typename BT>
+__global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npb,
                                                  const double* __restrict__ part_b, double* __restrict__ part_n,
                                                  double* __restrict__ red2, const Ctrl* ctrl) {
@@ -312,7 +335,7 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
     const int ii = valid ? i : n - 1;
     double q[NL];
 #pragma unroll
-    for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
+    for (int c = 0; c < NL; ++c) q[c] = (double)basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
     sum_partials(part_b, npb, ncol, sh, hs);
@@ -327,8 +350,9 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
 
 // Cycle end: closes the last step when no pass A did (the cycle ran all s_cycle steps), then stores
 // v_{j_done} = w_last * inv_h (zero after a breakdown), the last column of the cycle's basis.
+template <typename BT>
 __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__ w0, const double* __restrict__ w1,
-                                                      double* __restrict__ basis, int n, int ld, int kc, int vbase,
+                                                      BT* __restrict__ basis, int n, int ld, int kc, int vbase,
                                                       int s_cycle, int npn, const double* __restrict__ part_n,
                                                       const double* __restrict__ red1, const double* __restrict__ red2,
                                                       double* H, double* Bm, Ctrl* ctrl) {
@@ -362,26 +386,29 @@ __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i >= n) return;
     const double* wl = ((s_jd - 1) & 1) ? w1 : w0;
-    basis[(size_t)(vbase + s_jd) * ld + i] = s_brk ? 0.0 : wl[i] * s_scale;
+    basis[(size_t)(vbase + s_jd) * ld + i] = (BT)(s_brk ? 0.0 : wl[i] * s_scale);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Tall-skinny Gram products out = L^T R over all rows (L, R: lists of columns), used for
 // [C V]^T U, C^T r, U^T U at a cycle end and for the start-up CholQR.
 // ---------------------------------------------------------------------------------------------
+// Up to four column segments; segment s has cnt[s] columns at seg[s] (stride ld), all of the
+// element type the kernel takes for the list.
 struct ColList {
-    const double* seg[4];
+    const void* seg[4];
     int cnt[4];
 };
 constexpr int GCHUNK = 32;               // rows staged per LDS chunk
 constexpr int GL_MAX = 2 * KMAX + MMAX + 2;   // max columns on the left
 constexpr int GR_MAX = KMAX + 1;              // max columns on the right
 
-__device__ __forceinline__ const double* col_of(const ColList& L, int a, int ld) {
+template <typename T>
+__device__ __forceinline__ const T* col_of(const ColList& L, int a, int ld) {
     int base = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        if (a < base + L.cnt[s]) return L.seg[s] + (size_t)(a - base) * ld;
+        if (a < base + L.cnt[s]) return (const T*)L.seg[s] + (size_t)(a - base) * ld;
         base += L.cnt[s];
     }
     return nullptr;
@@ -396,7 +423,7 @@ __device__ __forceinline__ const double* col_of(const ColList& L, int a, int ld)
 // are multiplied; rows past the block end are zeroed in A. The four waves' tiles are added in LDS
 // in a fixed order at the end.
 typedef double skr_d4 __attribute__((ext_vector_type(4)));
-template <int TA, int TB>
+template <int TA, int TB, typename LT, typename RT>
 __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColList R, int nr, int n, int ld,
                                                        int rows_per_block, double* __restrict__ gpart) {
     constexpr int NT = TA * TB, KS = NT > 12 ? 2 : 4;   // row steps (of 4 rows) per operand batch
@@ -407,12 +434,12 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
     const int r1 = min(n, r0 + rows_per_block);
     const int per = (rows_per_block / NWAVE + 3) / 4 * 4;
     const int w0 = r0 + w * per, w1 = min(r1, w0 + per);
-    const double* lp[TA];
-    const double* rp[TB];
+    const LT* lp[TA];
+    const RT* rp[TB];
 #pragma unroll
-    for (int ta = 0; ta < TA; ++ta) lp[ta] = col_of(L, min(16 * ta + csub, nl - 1), ld);
+    for (int ta = 0; ta < TA; ++ta) lp[ta] = col_of<LT>(L, min(16 * ta + csub, nl - 1), ld);
 #pragma unroll
-    for (int tb = 0; tb < TB; ++tb) rp[tb] = col_of(R, min(16 * tb + csub, nr - 1), ld);
+    for (int tb = 0; tb < TB; ++tb) rp[tb] = col_of<RT>(R, min(16 * tb + csub, nr - 1), ld);
     skr_d4 acc[TA][TB];
 #pragma unroll
     for (int ta = 0; ta < TA; ++ta)
@@ -425,9 +452,9 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
             const int row = row0 + 4 * u + rsub;
             const int rc = min(row, r1 - 1);
 #pragma unroll
-            for (int ta = 0; ta < TA; ++ta) av[u][ta] = lp[ta][rc];
+            for (int ta = 0; ta < TA; ++ta) av[u][ta] = (double)lp[ta][rc];
 #pragma unroll
-            for (int tb = 0; tb < TB; ++tb) bv[u][tb] = rp[tb][rc];
+            for (int tb = 0; tb < TB; ++tb) bv[u][tb] = (double)rp[tb][rc];
         }
     };
     if (w0 < w1) fetch(w0);
@@ -477,10 +504,11 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
     }
 }
 
-// out[e] = sum_b gpart[b][e]: one workgroup per 64 outputs; wave w sums a contiguous quarter of
-// the partials (loads issued 16 at a time), then the quarters are added in order.
-__global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__ gpart, int nb, int E,
-                                                      double* __restrict__ out) {
+// out[(e / nr) * ostride + e % nr] = sum_b gpart[b][e]: one workgroup per 64 outputs; wave w sums a
+// contiguous quarter of the partials (loads issued 16 at a time), then the quarters are added in
+// order.
+__global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__ gpart, int nb, int E, int nr,
+                                                      int ostride, double* __restrict__ out) {
     __shared__ double sh[NWAVE * 64];
     const int lane = lane_id(), w = wave_id();
     const int e = blockIdx.x * 64 + lane;
@@ -504,7 +532,7 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
         double t = sh[lane];
 #pragma unroll
         for (int q = 1; q < NWAVE; ++q) t += sh[q * 64 + lane];
-        out[e] = t;
+        out[(e / nr) * ostride + e % nr] = t;
     }
 }
 
@@ -526,9 +554,9 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
 // and result item t of lane l is output o + l % 16 of row 4 t + l / 16 of the tile. The next four
 // column steps load while the current four multiply.
 typedef double skr_d4u __attribute__((ext_vector_type(4)));
-template <int KB>
+template <int KB, typename BT>
 __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ basis, double* __restrict__ U,
+                                                       BT* __restrict__ basis, BT* __restrict__ U,
                                                        int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
                                                        double* part_n, Ctrl* ctrl) {
     constexpr int NO = 2 * KB + 2;
@@ -599,9 +627,9 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
     auto fetch = [&](int ks0) {
 #pragma unroll
         for (int u = 0; u < KSB; ++u) {
-            const double* cp = colp(min(4 * (ks0 + u) + lk, ncl - 1));
+            const BT* cp = colp(min(4 * (ks0 + u) + lk, ncl - 1));
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) av[u][rt] = cp[min(wrow0 + 16 * rt + lrow, n - 1)];
+            for (int rt = 0; rt < RT; ++rt) av[u][rt] = (double)cp[min(wrow0 + 16 * rt + lrow, n - 1)];
         }
     };
     fetch(0);
@@ -640,9 +668,9 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
                 if (row < n) {
                     const double val = acc[rt][nt][t2];
                     if (o < KB) {
-                        if (o < kn) basis[(size_t)o * ld + row] = val;
+                        if (o < kn) basis[(size_t)o * ld + row] = (BT)val;
                     } else if (o < 2 * KB) {
-                        if (o - KB < kn) U[(size_t)(o - KB) * ld + row] = val;
+                        if (o - KB < kn) U[(size_t)(o - KB) * ld + row] = (BT)val;
                     } else if (o == 2 * KB) {
                         x[row] += val;
                     } else if (o == 2 * KB + 1) {
@@ -659,12 +687,12 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
 }
 
 // ---------------------------------------------------------------------------------------------
-// True residual r = b - A x (overwrites r) and ||r||^2.
+// True residual r = b - A x (overwrites r) and the partials of ||r||^2 (closed by k_norm_finish).
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* __restrict__ b,
                                                         const double* __restrict__ x, double* __restrict__ r,
-                                                        int nblk, double* part1, unsigned* counter, Ctrl* ctrl) {
-    __shared__ double sh[NWAVE * NC];
+                                                        int nblk, double* part_n) {
+    __shared__ double sh[NWAVE];
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     double v = 0.0;
@@ -673,31 +701,27 @@ __global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* 
         r[i] = ri;
         v = ri * ri;
     }
-    double tot;
-    if (grid_sum1(v, part1, counter, nblk, lb, sh, &tot) && threadIdx.x == 0) {
-        const double bt = sqrt(tot);
-        ctrl->res2 = tot;
-        ctrl->beta = bt;
-        ctrl->inv_h = bt > 0.0 ? 1.0 / bt : 0.0;
-        ctrl->g[0] = bt;
-        ctrl->stop = 0;
-    }
+    block_partial1(v, part_n, lb, sh);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Start-up with a carried recycle space (App. B.1): Z = A Y, CholQR2 of Z with column drops,
-// C = Q, U = Y R^{-1}, x1 = U C^T r0, r1 = r0 - C C^T r0.
+// C = Q, U = Y R^{-1}, x1 = U C^T r0, r1 = r0 - C C^T r0. The same projection starts every
+// refinement step of the mixed-precision mode (x += U C^T r, r -= C C^T r).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const double* __restrict__ Y, double* __restrict__ Z,
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const BT* __restrict__ Y, BT* __restrict__ Z,
                                                int ld, int kin) {
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i >= op.n) return;
-    for (int c = 0; c < kin; ++c) Z[(size_t)c * ld + i] = op_row(op, Y + (size_t)c * ld, i, 1.0);
+    for (int c = 0; c < kin; ++c)
+        Z[(size_t)c * ld + i] = (BT)op_row_k<-1, BT, false>(op, Y + (size_t)c * ld, i, 1.0);
 }
 
 // Row-wise triangular solves z <- z R^{-1} (R upper, k x k, ld KMAX) on Z (kept columns gathered
 // through keep[]) and on U, compacting both to the first k_eff columns.
-__global__ __launch_bounds__(ROWS) void k_startup_apply(double* __restrict__ Z, double* __restrict__ U, int n,
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_startup_apply(BT* __restrict__ Z, BT* __restrict__ U, int n,
                                                         int ld, const Coef* coef, int use_keep, int second) {
     __shared__ double Rs[KMAX * KMAX];
     __shared__ int ks[KMAX];
@@ -711,8 +735,8 @@ __global__ __launch_bounds__(ROWS) void k_startup_apply(double* __restrict__ Z, 
     double z[KMAX], u[KMAX];
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
-        z[c] = c < ke ? Z[(size_t)ks[c] * ld + i] : 0.0;
-        u[c] = c < ke ? U[(size_t)ks[c] * ld + i] : 0.0;
+        z[c] = c < ke ? (double)Z[(size_t)ks[c] * ld + i] : 0.0;
+        u[c] = c < ke ? (double)U[(size_t)ks[c] * ld + i] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
@@ -731,70 +755,49 @@ __global__ __launch_bounds__(ROWS) void k_startup_apply(double* __restrict__ Z, 
 #pragma unroll
     for (int c = 0; c < KMAX; ++c)
         if (c < ke) {
-            Z[(size_t)c * ld + i] = z[c];
-            U[(size_t)c * ld + i] = u[c];
+            Z[(size_t)c * ld + i] = (BT)z[c];
+            U[(size_t)c * ld + i] = (BT)u[c];
         }
 }
 
-// cvec = C^T r0 (partials + last-workgroup reduction into red_out[0..k_eff)).
-__global__ __launch_bounds__(ROWS) void k_ctr(const double* __restrict__ C, const double* __restrict__ r, int n,
-                                              int ld, int nblk, const Coef* coef, double* part, unsigned* counter,
-                                              double* red_out) {
-    __shared__ double sh[NWAVE * NC];
-    const int ke = coef->k_eff;
-    const int lb = logical_block(blockIdx.x, nblk);
-    const int i = lb * ROWS + threadIdx.x;
-    const bool valid = i < n;
-    const double ri = valid ? r[i] : 0.0;
-    double acc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = (valid && c < ke) ? C[(size_t)c * ld + i] * ri : 0.0;
-    const double s = wave_reduce_scatter64(acc);
-    sh[wave_id() * NC + lane_id()] = s;
-    __syncthreads();
-    if (threadIdx.x < NC) {
-        double t = sh[threadIdx.x];
-#pragma unroll
-        for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + threadIdx.x];
-        part[lb * NC + threadIdx.x] = t;
-    }
-    if (last_block_arrive(counter, (unsigned)nblk)) final_reduce64(part, nblk, sh, red_out);
-}
-
-// x1 = U c, r1 = r0 - C c, ||r1|| -> control block (next cycle starts from r1).
+// x = x0 + U c, r -= C c with c = C^T r (ke entries, from a Gram product), and the partials of
+// ||r||^2 (closed by k_norm_finish). x0 = 0 at a system start, the current iterate at a refinement
+// step. The columns are taken eight at a time, every load of a group in flight together at clamped
+// column indices (a coefficient of zero past ke), products added in column order.
+template <typename BT>
 __global__ __launch_bounds__(ROWS) void k_startup_project(double* __restrict__ x, double* __restrict__ r,
-                                                          const double* __restrict__ C, const double* __restrict__ U,
-                                                          int n, int ld, int nblk, const Coef* coef,
-                                                          const double* __restrict__ cvec, double* part1,
-                                                          unsigned* counter, Ctrl* ctrl) {
-    __shared__ double sh[NWAVE * NC];
+                                                          const BT* __restrict__ C, const BT* __restrict__ U,
+                                                          int n, int ld, int nblk, int ke, int add_x,
+                                                          const double* __restrict__ cvec, double* part_n) {
+    __shared__ double sh[NWAVE];
     __shared__ double cs[KMAX];
-    const int ke = coef->k_eff;
-    if (threadIdx.x < KMAX) cs[threadIdx.x] = threadIdx.x < ke ? cvec[threadIdx.x] : 0.0;
+    if (threadIdx.x < KMAX) cs[threadIdx.x] = (int)threadIdx.x < ke ? cvec[threadIdx.x] : 0.0;
     __syncthreads();
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
     double v = 0.0;
     if (i < n) {
-        double xi = 0.0, ri = r[i];
-        for (int c = 0; c < ke; ++c) {
-            xi = fma(U[(size_t)c * ld + i], cs[c], xi);
-            ri = fma(-C[(size_t)c * ld + i], cs[c], ri);
+        double xi = add_x ? x[i] : 0.0, ri = r[i];
+        for (int c0 = 0; c0 < ke; c0 += 8) {
+            double uc[8], cc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const size_t off = (size_t)min(c0 + u, ke - 1) * ld + i;
+                uc[u] = (double)U[off];
+                cc[u] = (double)C[off];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double cu = (c0 + u < KMAX) ? cs[min(c0 + u, KMAX - 1)] : 0.0;
+                xi = fma(uc[u], cu, xi);
+                ri = fma(-cc[u], cu, ri);
+            }
         }
         x[i] = xi;
         r[i] = ri;
         v = ri * ri;
     }
-    double tot;
-    if (grid_sum1(v, part1, counter, nblk, lb, sh, &tot) && threadIdx.x == 0) {
-        const double bt = sqrt(tot);
-        ctrl->beta = bt;
-        ctrl->inv_h = bt > 0.0 ? 1.0 / bt : 0.0;
-        ctrl->g[0] = bt;
-        ctrl->est = bt;
-        ctrl->stop = 0;
-        ctrl->kc = ke;
-    }
+    block_partial1(v, part_n, lb, sh);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -866,10 +869,13 @@ void launch_fold_n(hipStream_t s, const Work& w) {
 // ---------------------------------------------------------------------------------------------
 static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
 
+static void launch_norm_finish(hipStream_t s, const Work& w, int mode, double rtol, int ke) {
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(ROWS), 0, s, pn_src(w), pn_cnt(w), mode, rtol, ke, w.ctrl);
+}
 void launch_init(hipStream_t s, const Work& w, const double* b, double* x, double rtol) {
-    hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, rtol, w.part_n,
-                       w.counters + 0, w.ctrl);
+    hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, w.part_n);
     launch_fold_n(s, w);
+    launch_norm_finish(s, w, FIN_INIT, rtol, 0);
 }
 void launch_clear_nonfinite(hipStream_t s, const Work& w) {
     hipLaunchKernelGGL(k_clear_nonfinite, dim3(1), dim3(1), 0, s, w.ctrl);
@@ -883,37 +889,41 @@ void launch_zero(hipStream_t s, double* x, int n) {
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(n)), dim3(ROWS), 0, s, x, n);
 }
 static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
+template <typename BT>
+static inline BT* bas(const Work& w) { return reinterpret_cast<BT*>(w.basis); }
+template <typename BT>
+static inline BT* ucols(const Work& w) { return reinterpret_cast<BT*>(w.U); }
 
 // With e0/e1 non-null the launch goes through hipExtLaunchKernelGGL, whose events take the start
 // and end timestamps of the kernel's own dispatch (no marker packets around it).
-template <int NL, int KIND>
+template <int NL, int KIND, typename BT>
 static void step_a_k(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
                      hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_step_a<NL, KIND>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst, w.basis,
-                          w.ld, kc, w.k, j, w.nblk, pn_cnt(w), pn_src(w), w.part_a, (const double*)w.red1,
-                          (const double*)w.red2, w.H, w.Bm, w.ctrl);
+    hipExtLaunchKernelGGL((k_step_a<NL, KIND, BT>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, src, dst,
+                          bas<BT>(w), w.ld, kc, w.k, j, w.nblk, pn_cnt(w), pn_src(w), w.part_a,
+                          (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
 }
-template <int NL>
+template <int NL, typename BT>
 static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* src, double* dst, int kc, int j,
                    hipEvent_t e0, hipEvent_t e1) {
     if (op.kind == SKR_OP_CSR)
-        step_a_k<NL, SKR_OP_CSR>(s, w, op, src, dst, kc, j, e0, e1);
+        step_a_k<NL, SKR_OP_CSR, BT>(s, w, op, src, dst, kc, j, e0, e1);
     else if (op.kind == SKR_OP_STENCIL7)
-        step_a_k<NL, SKR_OP_STENCIL7>(s, w, op, src, dst, kc, j, e0, e1);
+        step_a_k<NL, SKR_OP_STENCIL7, BT>(s, w, op, src, dst, kc, j, e0, e1);
     else
-        step_a_k<NL, SKR_OP_STENCIL5>(s, w, op, src, dst, kc, j, e0, e1);
+        step_a_k<NL, SKR_OP_STENCIL5, BT>(s, w, op, src, dst, kc, j, e0, e1);
 }
-template <int NL>
+template <int NL, typename BT>
 static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_step_b<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
-                          w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+    hipExtLaunchKernelGGL((k_step_b<NL, BT>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                          (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
                           (const double*)(w.fold ? w.fold_a : w.part_a), w.part_b, w.red1,
                           (const Ctrl*)w.ctrl);
 }
-template <int NL>
+template <int NL, typename BT>
 static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_step_c<NL>, dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst, (const double*)w.basis,
-                          w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+    hipExtLaunchKernelGGL((k_step_c<NL, BT>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                          (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
                           (const double*)(w.fold ? w.fold_b : w.part_b), w.part_n, w.red2,
                           (const Ctrl*)w.ctrl);
 }
@@ -932,7 +942,8 @@ static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hip
 
 // One Arnoldi step (three kernels). With ev != nullptr, ev[2q], ev[2q+1] take the start and end of
 // kernel q (A, B, C).
-void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle, hipEvent_t* ev) {
+template <typename BT>
+static void launch_step_t(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, hipEvent_t* ev) {
     const double* src = (j == 0) ? w.r : w.W[(j - 1) & 1];
     double* dst = w.W[j & 1];
     const int ncol = kc + j + 1;
@@ -940,32 +951,48 @@ void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, i
     hipEvent_t e[6] = {};
     if (ev)
         for (int q = 0; q < 6; ++q) e[q] = ev[q];
-#define CALL_A(NL) step_a<NL>(s, w, op, src, dst, kc, j, e[0], e[1])
+#define CALL_A(NL) step_a<NL, BT>(s, w, op, src, dst, kc, j, e[0], e[1])
     SKR_DISPATCH8(nla, CALL_A)
 #undef CALL_A
     if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_a, w.nblk, NC, w.fold_a);
-#define CALL_B(NL) step_b<NL>(s, w, dst, kc, j, e[2], e[3])
+#define CALL_B(NL) step_b<NL, BT>(s, w, dst, kc, j, e[2], e[3])
     SKR_DISPATCH8(nlb, CALL_B)
 #undef CALL_B
     if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_b, w.nblk, NC, w.fold_b);
-#define CALL_C(NL) step_c<NL>(s, w, dst, kc, j, e[4], e[5])
+#define CALL_C(NL) step_c<NL, BT>(s, w, dst, kc, j, e[4], e[5])
     SKR_DISPATCH8(nlb, CALL_C)
 #undef CALL_C
     launch_fold_n(s, w);
 }
-void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
-    hipLaunchKernelGGL(k_close_basis, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0], (const double*)w.W[1],
-                       w.basis, w.n, w.ld, kc, w.k, s_cycle, pn_cnt(w), pn_src(w),
-                       (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
+void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle, hipEvent_t* ev) {
+    (void)s_cycle;
+    if (w.mixed)
+        launch_step_t<float>(s, w, op, kc, j, ev);
+    else
+        launch_step_t<double>(s, w, op, kc, j, ev);
 }
-void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const ColList& R, int nr, double* out) {
+void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
+    if (w.mixed)
+        hipLaunchKernelGGL(k_close_basis<float>, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0],
+                           (const double*)w.W[1], bas<float>(w), w.n, w.ld, kc, w.k, s_cycle, pn_cnt(w), pn_src(w),
+                           (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
+    else
+        hipLaunchKernelGGL(k_close_basis<double>, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0],
+                           (const double*)w.W[1], bas<double>(w), w.n, w.ld, kc, w.k, s_cycle, pn_cnt(w), pn_src(w),
+                           (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
+}
+// out[a * ostride + b] = L_a^T R_b (a < nl, b < nr); LT, RT: element types of the two lists.
+template <typename LT, typename RT>
+static void launch_gram_t(hipStream_t s, const Work& w, const ColList& L, int nl, const ColList& R, int nr,
+                          double* out, int ostride) {
     const int E = nl * nr;
     const int rpb = ((w.n + w.ngblk - 1) / w.ngblk + GCHUNK - 1) / GCHUNK * GCHUNK;
     const int nb = (w.n + rpb - 1) / rpb;
     const int la = nl <= 32 ? 2 : (nl <= 64 ? 4 : (nl <= 96 ? 6 : 8));
     const int lbk = nr <= 16 ? 1 : (nr <= 32 ? 2 : 3);
-#define SKR_GP(LA, LB)                                                                                   \
-    hipLaunchKernelGGL((k_gram_partial<LA, LB>), dim3(nb), dim3(ROWS), 0, s, L, nl, R, nr, w.n, w.ld, rpb, w.gpart)
+#define SKR_GP(LA, LB)                                                                                      \
+    hipLaunchKernelGGL((k_gram_partial<LA, LB, LT, RT>), dim3(nb), dim3(ROWS), 0, s, L, nl, R, nr, w.n, w.ld, \
+                       rpb, w.gpart)
 #define SKR_GP_B(LA)                            \
     switch (lbk) {                              \
         case 1: SKR_GP(LA, 1); break;           \
@@ -980,53 +1007,104 @@ void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const C
     }
 #undef SKR_GP_B
 #undef SKR_GP
-    hipLaunchKernelGGL(k_gram_reduce, dim3((E + 63) / 64), dim3(ROWS), 0, s, (const double*)w.gpart, nb, E, out);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((E + 63) / 64), dim3(ROWS), 0, s, (const double*)w.gpart, nb, E, nr,
+                       ostride, out);
+}
+// Both lists in the basis storage type.
+void launch_gram(hipStream_t s, const Work& w, const ColList& L, int nl, const ColList& R, int nr, double* out) {
+    if (w.mixed)
+        launch_gram_t<float, float>(s, w, L, nl, R, nr, out, nr);
+    else
+        launch_gram_t<double, double>(s, w, L, nl, R, nr, out, nr);
+}
+// Left list in the basis storage type, one FP64 right column (r): out[a * ostride] = L_a^T r.
+static void launch_gram_r(hipStream_t s, const Work& w, const ColList& L, int nl, double* out, int ostride) {
+    ColList R = {{w.r, nullptr, nullptr, nullptr}, {1, 0, 0, 0}};
+    if (w.mixed)
+        launch_gram_t<float, double>(s, w, L, nl, R, 1, out, ostride);
+    else
+        launch_gram_t<double, double>(s, w, L, nl, R, 1, out, ostride);
+}
+// Column offsets inside the basis buffer, in elements of the storage type.
+static inline const void* bcol(const Work& w, int c) {
+    return w.mixed ? (const void*)(bas<float>(w) + (size_t)c * w.ld) : (const void*)(bas<double>(w) + (size_t)c * w.ld);
 }
 void launch_cycle_gram(hipStream_t s, const Work& w, int kc, int jd_max) {
     // L = [C (kc), V_0..V_jd (jd+1), U (kc)], R = [U (kc), r]; jd is bounded on the host by the
-    // cycle length, the columns past j_done only add products that nobody reads.
-    ColList L = {{w.basis, w.basis + (size_t)w.k * w.ld, w.U, nullptr}, {kc, jd_max + 1, kc, 0}};
-    ColList R = {{w.U, w.r, nullptr, nullptr}, {kc, 1, 0, 0}};
-    launch_gram(s, w, L, 2 * kc + jd_max + 1, R, kc + 1, w.gram);
+    // cycle length, the columns past j_done only add products that nobody reads. In FP64 storage
+    // this is one product; with an FP32 basis the FP64 column r is a product of its own.
+    ColList L = {{bcol(w, 0), bcol(w, w.k), w.U, nullptr}, {kc, jd_max + 1, kc, 0}};
+    const int nl = 2 * kc + jd_max + 1;
+    if (!w.mixed) {
+        ColList R = {{w.U, w.r, nullptr, nullptr}, {kc, 1, 0, 0}};
+        launch_gram(s, w, L, nl, R, kc + 1, w.gram);
+    } else {
+        ColList R = {{w.U, nullptr, nullptr, nullptr}, {kc, 0, 0, 0}};
+        launch_gram_t<float, float>(s, w, L, nl, R, kc, w.gram, kc + 1);
+        launch_gram_r(s, w, L, nl, w.gram + kc, kc + 1);
+    }
 }
 void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_bucket) {
-#define SKR_UPD(KB)                                                                                        \
-    hipLaunchKernelGGL(k_cycle_update<KB>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, w.basis, w.U, w.n, w.ld, w.k, \
-                       kc, w.nblk, (const Coef*)w.coef, w.part_n, w.ctrl)
-    switch (k_bucket) {
-        case 0: SKR_UPD(0); break;
-        case 8: SKR_UPD(8); break;
-        case 16: SKR_UPD(16); break;
-        case 20: SKR_UPD(20); break;
-        case 24: SKR_UPD(24); break;
-        default: SKR_UPD(32); break;
+#define SKR_UPD(KB, BT)                                                                                      \
+    hipLaunchKernelGGL((k_cycle_update<KB, BT>), dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, bas<BT>(w), ucols<BT>(w), \
+                       w.n, w.ld, w.k, kc, w.nblk, (const Coef*)w.coef, w.part_n, w.ctrl)
+#define SKR_UPD_K(BT)                           \
+    switch (k_bucket) {                         \
+        case 0: SKR_UPD(0, BT); break;          \
+        case 8: SKR_UPD(8, BT); break;          \
+        case 16: SKR_UPD(16, BT); break;        \
+        case 20: SKR_UPD(20, BT); break;        \
+        case 24: SKR_UPD(24, BT); break;        \
+        default: SKR_UPD(32, BT); break;        \
     }
+    if (w.mixed) {
+        SKR_UPD_K(float)
+    } else {
+        SKR_UPD_K(double)
+    }
+#undef SKR_UPD_K
 #undef SKR_UPD
     launch_fold_n(s, w);
 }
 void launch_true_residual(hipStream_t s, const Work& w, const DevOp& op, const double* b, const double* x) {
-    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n,
-                       w.counters + 5, w.ctrl);
+    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n);
     launch_fold_n(s, w);
+    launch_norm_finish(s, w, FIN_TRUE_RES, 0.0, 0);
 }
 void launch_spmm(hipStream_t s, const Work& w, const DevOp& op, int kin) {
-    hipLaunchKernelGGL(k_spmm, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, op, (const double*)w.U, w.basis, w.ld, kin);
+    if (w.mixed)
+        hipLaunchKernelGGL(k_spmm<float>, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, op, (const float*)ucols<float>(w),
+                           bas<float>(w), w.ld, kin);
+    else
+        hipLaunchKernelGGL(k_spmm<double>, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, op,
+                           (const double*)ucols<double>(w), bas<double>(w), w.ld, kin);
 }
 void launch_startup_gram(hipStream_t s, const Work& w, int kcols) {
-    ColList L = {{w.basis, nullptr, nullptr, nullptr}, {kcols, 0, 0, 0}};
+    ColList L = {{bcol(w, 0), nullptr, nullptr, nullptr}, {kcols, 0, 0, 0}};
     launch_gram(s, w, L, kcols, L, kcols, w.gram);
 }
 void launch_startup_apply(hipStream_t s, const Work& w, int use_keep, int second) {
-    hipLaunchKernelGGL(k_startup_apply, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, w.basis, w.U, w.n, w.ld,
-                       (const Coef*)w.coef, use_keep, second);
+    if (w.mixed)
+        hipLaunchKernelGGL(k_startup_apply<float>, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, bas<float>(w),
+                           ucols<float>(w), w.n, w.ld, (const Coef*)w.coef, use_keep, second);
+    else
+        hipLaunchKernelGGL(k_startup_apply<double>, dim3(blocks_for(w.n)), dim3(ROWS), 0, s, bas<double>(w),
+                           ucols<double>(w), w.n, w.ld, (const Coef*)w.coef, use_keep, second);
 }
-void launch_startup_project(hipStream_t s, const Work& w, double* x) {
-    hipLaunchKernelGGL(k_ctr, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.basis, (const double*)w.r, w.n,
-                       w.ld, w.nblk, (const Coef*)w.coef, w.part, w.counters + 6, w.red1);
-    hipLaunchKernelGGL(k_startup_project, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, (const double*)w.basis,
-                       (const double*)w.U, w.n, w.ld, w.nblk, (const Coef*)w.coef, (const double*)w.red1,
-                       w.part_n, w.counters + 7, w.ctrl);
+// c = C^T r (ke columns, on the matrix cores), then x = x0 + U c, r -= C c and ||r||.
+void launch_startup_project(hipStream_t s, const Work& w, double* x, int ke, int add_x) {
+    ColList L = {{bcol(w, 0), nullptr, nullptr, nullptr}, {ke, 0, 0, 0}};
+    launch_gram_r(s, w, L, ke, w.red1, 1);
+    if (w.mixed)
+        hipLaunchKernelGGL(k_startup_project<float>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r,
+                           (const float*)bas<float>(w), (const float*)ucols<float>(w), w.n, w.ld, w.nblk, ke, add_x,
+                           (const double*)w.red1, w.part_n);
+    else
+        hipLaunchKernelGGL(k_startup_project<double>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r,
+                           (const double*)bas<double>(w), (const double*)ucols<double>(w), w.n, w.ld, w.nblk, ke,
+                           add_x, (const double*)w.red1, w.part_n);
     launch_fold_n(s, w);
+    launch_norm_finish(s, w, FIN_PROJECT, 0.0, ke);
 }
 void launch_spmv(hipStream_t s, const DevOp& op, const double* x, double* y) {
     hipLaunchKernelGGL(k_spmv, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, x, y);

@@ -33,6 +33,7 @@ SKR_OP_STENCIL7 = 2
 
 SKR_FLAG_PROFILE = 1
 SKR_FLAG_FOLD = 2
+SKR_FLAG_MIXED = 4
 
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
             "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset")
