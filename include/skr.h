@@ -34,6 +34,7 @@ extern "C" {
 #define SKR_EHIP              (-3)   /* HIP runtime failure                                    */
 #define SKR_ENONFINITE        (-4)   /* NaN or Inf in an input where none is allowed           */
 #define SKR_WARN_NOTCONVERGED   1    /* at least one system stopped at maxit                   */
+#define SKR_PENDING             2    /* skr_poll: the ticket's system is not solved yet        */
 
 /* per-system status (skr_result.status) */
 #define SKR_CONVERGED   0   /* ||b - A x|| <= rtol ||b||                                        */
@@ -194,6 +195,73 @@ int skr_profile_get(skr_ctx* ctx, skr_profile* out);
 
 /* Clear the accumulated statistics. */
 int skr_profile_reset(skr_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: systems arrive one at a time (continuous batching).
+ *
+ * The sorted-sequence idea (Sec. 4.1, Alg. 1: each system is solved after its nearest neighbour;
+ * App. E: contiguous slices of the sorted order are independent chains) applied online. A submitted
+ * system joins the chain whose most recently admitted system is nearest to it in d2 (the exact
+ * squared distance of the parameter vectors, as in skr_sort; ties to the lower chain id), among the
+ * chains of the same shape (n, p, m, k and SKR_FLAG_MIXED). It starts a new chain when no chain of
+ * its shape exists, or when d2 > split_d2_rel * ||params||^2 and a chain can be added without
+ * retiring one. Each chain
+ * owns a HIP stream, a workspace and its recycle space, which stays resident in device memory
+ * between systems; its systems are solved in admission order, each starting from the recycle space
+ * the previous one left (Alg. 2), so a result depends only on the chain's history, never on timing
+ * or on the other chains. Host worker threads drive up to `workers` chains at once.
+ *
+ * Admission is by workspace bytes: a new chain is created only while the chains' workspaces fit in
+ * arena_bytes (0: no limit) and fewer than max_chains exist. For a shape that has no chain, idle
+ * chains (nothing queued or running) are retired, least recently used first, to make room; if
+ * none is idle the system waits (deferred admission) and is assigned when room frees, as are the
+ * systems submitted after it. Only retirement and deferral depend on timing. A system whose
+ * workspace alone exceeds arena_bytes is refused with SKR_ENOMEM.
+ * --------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_chains;     /* chains held at once (>= 1)                                       */
+    int32_t workers;        /* host threads driving chains concurrently (>= 1)                  */
+    uint64_t arena_bytes;   /* device bytes all chain workspaces may take together, 0 = no limit */
+    double split_d2_rel;    /* start a new chain above this relative d2 (INFINITY: never)        */
+} skr_serve_opts;
+
+typedef struct {
+    int64_t submitted, completed;
+    int32_t chains_live, chains_created, chains_retired, deferred;
+    uint64_t bytes_in_use;  /* device bytes of the live chains' workspaces */
+} skr_serve_stats;
+
+/* Start serving on the context's device (the context's stream is used for the distance products
+ * at submission). SKR_EINVAL if already started or the options are out of range. */
+int skr_serve_start(skr_ctx* ctx, const skr_serve_opts* opts);
+
+/* Submit A x = b with parameter vector params_dev[p] (device, FP64; copied before return, the
+ * caller may reuse it). op, b_dev and x_dev are caller-owned device memory that must stay valid
+ * until the ticket is reported done; x_dev receives the solution. opts as for skr_solve_sequence
+ * (all systems of a chain share m, k and the SKR_FLAG_MIXED setting). *ticket receives an id > 0.
+ * Errors: SKR_EINVAL (not serving, bad arguments), SKR_ENOMEM (workspace larger than the arena),
+ * SKR_EHIP. Thread-safe. */
+int skr_submit(skr_ctx* ctx, const skr_op* op, const double* params_dev, int64_t p, const double* b_dev,
+               double* x_dev, const skr_opts* opts, uint64_t* ticket);
+
+/* SKR_PENDING while the system is queued or running; when it is done, writes the result (host)
+ * and returns SKR_OK, or the error code of a failed solve (skr_last_error() has the message).
+ * A ticket is collected by the first call that reports it done; later calls return SKR_EINVAL. */
+int skr_poll(skr_ctx* ctx, uint64_t ticket, skr_result* out);
+
+/* skr_poll that blocks until the ticket is done. */
+int skr_wait(skr_ctx* ctx, uint64_t ticket, skr_result* out);
+
+/* The chain a ticket was assigned to and its position in that chain (0 = the chain's first
+ * system), or -1 / -1 while its admission is deferred. Valid until the ticket is collected. */
+int skr_ticket_chain(skr_ctx* ctx, uint64_t ticket, int32_t* chain, int64_t* position);
+
+/* Counters of the serving runtime (host pointer). */
+int skr_serve_stats_get(skr_ctx* ctx, skr_serve_stats* out);
+
+/* Finish every submitted system, then free the chains and stop the workers. Uncollected results
+ * are dropped. Called by skr_ctx_destroy if serving is still on. */
+int skr_serve_stop(skr_ctx* ctx);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "skr_internal.hpp"
+#include "skr_host.hpp"
 
 namespace skr {
 struct ColList;
@@ -38,8 +38,20 @@ long sort_part_doubles(long, long);
 
 using namespace skr;
 
-constexpr int PROF_PERIOD = 16;   // one Arnoldi step in PROF_PERIOD is timed
-constexpr int PROF_MAXSAMP = (MMAX + PROF_PERIOD - 1) / PROF_PERIOD + 1;
+static thread_local std::string g_err;
+
+namespace skr {
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+const std::string& last_error() { return g_err; }
+}  // namespace skr
 
 // Algorithmic bytes of the three step kernels at step j with ncol = kc + j + 1 basis columns.
 static double op_bytes(const DevOp& op, int64_t nvals) {
@@ -57,52 +69,6 @@ static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double es, doub
     b = es * n * ncol + 16.0 * n;
     c = es * n * ncol + 16.0 * n;
 }
-
-struct skr_ctx;
-struct skr_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    Work w;
-    CtrlHost* hctrl = nullptr;     // pinned
-    int* hkeff = nullptr;          // pinned
-    // sort scratch
-    double* sortD = nullptr;
-    size_t sortD_cap = 0;
-    double* sortP = nullptr;       // slice partials of the distance pass
-    size_t sortP_cap = 0;
-    long long* order_d = nullptr;
-    double* dist_d = nullptr;
-    size_t sortN_cap = 0;
-    // profiling
-    hipEvent_t ev[PROF_MAXSAMP * 6] = {};
-    bool ev_ok = false;
-    int64_t step_counter = 0;
-    skr_profile prof = {};
-};
-
-static thread_local std::string g_err;
-
-static int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-#define HIPCHK(call)                                                                            \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail(SKR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-#define HIPLAUNCHCHK()                                                                          \
-    do {                                                                                        \
-        hipError_t e_ = hipGetLastError();                                                      \
-        if (e_ != hipSuccess) return fail(SKR_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
 
 static void free_work(Work& w) {
     double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
@@ -178,13 +144,24 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     return SKR_OK;
 }
 
+size_t skr::work_bytes(int n, int m, int k) {
+    const size_t ld = (size_t)((n + 63) / 64 * 64);
+    const size_t nblk = (size_t)((n + ROWS - 1) / ROWS);
+    const size_t ngblk = (size_t)std::min(256, std::max(1, (n + 255) / 256));
+    const size_t gmax = (size_t)gram_cols_max(m, k);
+    size_t d = (size_t)(k + m + 1) * ld + (size_t)std::max(k, 1) * ld + 3 * ld;   // basis, U, W[2], r
+    d += 3 * nblk * NC + nblk + ngblk * gmax + gmax + 2 * (size_t)NFOLD * NC + NFOLD + 2 * NC;
+    d += (size_t)LDH * MMAX + (size_t)KMAX * MMAX;
+    return d * sizeof(double) + sizeof(Ctrl) + sizeof(Coef) + sizeof(DenseWork) + 8 * sizeof(unsigned);
+}
+
 static int read_ctrl(skr_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->hctrl, ctx->w.ctrl, sizeof(CtrlHost), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return SKR_OK;
 }
 
-static int to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
+int skr::to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
     d = DevOp();
     d.kind = o.kind;
     d.n = o.n;
@@ -223,22 +200,209 @@ static int to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
     return SKR_OK;
 }
 
-extern "C" {
+// Solves one system A x = b on the context's stream (Alg. 2), starting from the recycle space the
+// context holds (kin columns of U, left by the system solved before on this context) and leaving
+// the next one there (kin updated). The workspace must be sized for (n, m, k), with the fold and
+// storage modes set (prepare_solve). Returns SKR_OK with the outcome in res, or an error code.
+int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double* x, const skr_opts& opts, int& kin,
+                 skr_result& res) {
+    Work& w = ctx->w;
+    hipStream_t s = ctx->stream;
+    CtrlHost& hc = *ctx->hctrl;
+    const int n = w.n, m = opts.m, k = opts.k;
+    const double rtol = opts.rtol;
+    const int64_t maxit = opts.maxit;
+    const bool profile = (opts.flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
+    const double es = w.mixed ? 4.0 : 8.0;
+    int samp_j[PROF_MAXSAMP];
+    int rc;
+    DevOp op;
+    int64_t nvals;
+    to_devop(opin, op, nvals);
+    std::memset(&res, 0, sizeof res);
 
-const char* skr_version(void) { return "skr-gfx950 0.1"; }
+    launch_clear_nonfinite(s, w);
+    launch_init(s, w, b, x, rtol);
+    if (op.kind == SKR_OP_CSR) {
+        launch_check_finite(s, w, op.val, (long)nvals);
+    } else {
+        const long nzl = op.kind == SKR_OP_STENCIL7 ? (long)op.nz : 1L;
+        launch_check_finite(s, w, op.ax, nzl * op.ny * (op.nx + 1));
+        launch_check_finite(s, w, op.ay, nzl * (op.ny + 1) * op.nx);
+        if (op.kind == SKR_OP_STENCIL7) launch_check_finite(s, w, op.az, (nzl + 1) * op.ny * op.nx);
+    }
+    HIPLAUNCHCHK();
+    if ((rc = read_ctrl(ctx))) return rc;
+    if (hc.nonfinite || !std::isfinite(hc.bnorm)) {
+        launch_zero(s, x, n);
+        res.status = SKR_NONFINITE;
+        res.relres_true = NAN;
+        res.relres_est = NAN;
+        return SKR_OK;   // the carried recycle space is passed on untouched
+    }
+    if (hc.bnorm == 0.0) {
+        res.status = SKR_CONVERGED;
+        return SKR_OK;
+    }
+    const double bnorm = hc.bnorm, tol_abs = hc.tol_abs;
+    int64_t iters = 0, spmv = 0;
+    int cycles = 0;
+    int kc = 0;
+    // ---- start-up with the carried recycle space (App. B.1)
+    if (k > 0 && kin > 0) {
+        launch_spmm(s, w, op, kin);
+        launch_startup_gram(s, w, kin);
+        launch_chol(s, w, kin, 1);
+        launch_startup_apply(s, w, 1, 0);
+        HIPLAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(ctx->hkeff, &w.coef->k_eff, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const int ke = *ctx->hkeff;
+        spmv += kin;
+        res.rank_dropped = kin - ke;
+        if (ke > 0) {
+            launch_startup_gram(s, w, ke);
+            launch_chol(s, w, ke, 0);
+            launch_startup_apply(s, w, 0, 1);
+            launch_startup_project(s, w, x, ke, 0);
+            HIPLAUNCHCHK();
+        }
+        if ((rc = read_ctrl(ctx))) return rc;
+        kc = hc.kc;
+        res.k_start = kc;
+    }
+    int status = -1;
+    double est = hc.beta;
+    // r equals b - A x computed directly (at x = 0, or right after a true-residual product)
+    bool r_is_true = kc == 0;
+    if (hc.beta <= tol_abs) {
+        launch_true_residual(s, w, op, b, x);
+        HIPLAUNCHCHK();
+        if ((rc = read_ctrl(ctx))) return rc;
+        spmv += 1;
+        if (std::sqrt(hc.res2) <= tol_abs) status = SKR_CONVERGED;
+        r_is_true = true;
+    }
+    // ---- Arnoldi cycles (Alg. 2)
+    while (status < 0) {
+        if (iters >= maxit) { status = SKR_MAXIT; break; }
+        if (w.mixed && !r_is_true) {
+            // refinement step: true FP64 residual, projected onto range(C) as at a system start
+            launch_true_residual(s, w, op, b, x);
+            spmv += 1;
+            if (kc > 0) launch_startup_project(s, w, x, kc, 1);
+            HIPLAUNCHCHK();
+        }
+        r_is_true = false;
+        int scyc = (kc == 0) ? m : m - kc;
+        scyc = (int)std::min<int64_t>(scyc, maxit - iters);
+        int nsamp = 0;
+        for (int j = 0; j < scyc; ++j) {
+            hipEvent_t* ev = nullptr;
+            if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
+                ev = ctx->ev + 6 * nsamp;
+                samp_j[nsamp++] = j;
+            }
+            launch_step(s, w, op, kc, j, scyc, ev);
+        }
+        launch_close_basis(s, w, kc, scyc);
+        if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
+        launch_cycle_dense(s, w, kc, scyc, k);
+        // the new recycle size is at most k (0 when no recycle space is formed this cycle)
+        const bool forms = k > 0 && (kc > 0 || scyc > k);
+        launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : 32) : 0);
+        HIPLAUNCHCHK();
+        if ((rc = read_ctrl(ctx))) return rc;
+        const int jd = hc.j_done;
+        if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
+        if (profile) {
+            skr_profile& pr = ctx->prof;
+            for (int q = 0; q < nsamp; ++q) {
+                if (samp_j[q] >= jd) continue;   // steps after the stop are skipped launches
+                float t[3];
+                for (int e = 0; e < 3; ++e)
+                    HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[6 * q + 2 * e], ctx->ev[6 * q + 2 * e + 1]));
+                double ba, bb, bc;
+                step_bytes(op, nvals, kc + samp_j[q] + 1, es, ba, bb, bc);
+                pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;
+                pr.step_b.launches++; pr.step_b.ms += t[1]; pr.step_b.bytes += bb;
+                pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc;
+            }
+            for (int j = 0; j < jd; ++j) {
+                double ba, bb, bc;
+                step_bytes(op, nvals, kc + j + 1, es, ba, bb, bc);
+                pr.step_bytes += ba + bb + bc;
+            }
+            pr.steps += jd;
+            pr.cycles += 1;
+        }
+        iters += jd;
+        spmv += jd;
+        cycles += 1;
+        est = hc.est;
+        kc = hc.k_new;
+        if (!std::isfinite(est)) {
+            launch_zero(s, x, n);
+            status = SKR_NONFINITE;
+            kc = 0;
+            break;
+        }
+        if (est <= tol_abs || hc.breakdown) {
+            const int brk = hc.breakdown;
+            launch_true_residual(s, w, op, b, x);
+            HIPLAUNCHCHK();
+            if ((rc = read_ctrl(ctx))) return rc;
+            spmv += 1;
+            if (std::sqrt(hc.res2) <= tol_abs) {
+                status = brk ? SKR_BREAKDOWN : SKR_CONVERGED;
+                break;
+            }
+            r_is_true = true;
+        }
+    }
+    if (status == SKR_MAXIT) {
+        launch_true_residual(s, w, op, b, x);
+        HIPLAUNCHCHK();
+        if ((rc = read_ctrl(ctx))) return rc;
+        spmv += 1;
+    }
+    res.status = status;
+    res.cycles = cycles;
+    res.iters = iters;
+    res.spmv = spmv;
+    res.relres_true = status == SKR_NONFINITE ? NAN : std::sqrt(hc.res2) / bnorm;
+    res.relres_est = est / bnorm;
+    kin = (k > 0) ? kc : 0;
+    return SKR_OK;
+}
 
-const char* skr_last_error(void) { return g_err.c_str(); }
+// Checks m, k, rtol and maxit (Alg. 2 inputs).
+int skr::check_opts(const skr_opts* opts) {
+    if (!opts) return fail(SKR_EINVAL, "NULL options");
+    const int m = opts->m, k = opts->k;
+    if (m < 1 || m > MMAX) return fail(SKR_EINVAL, "m must be in [1, %d] (got %d)", MMAX, m);
+    if (k < 0 || k > KMAX || k >= m) return fail(SKR_EINVAL, "k must satisfy 0 <= k < m and k <= %d (got %d)", KMAX, k);
+    if (!(opts->rtol > 0.0)) return fail(SKR_EINVAL, "rtol must be > 0");
+    if (opts->maxit < 0) return fail(SKR_EINVAL, "maxit must be >= 0");
+    return SKR_OK;
+}
 
-int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
-    if (!out) return fail(SKR_EINVAL, "out is NULL");
-    *out = nullptr;
-    int ndev = 0;
-    HIPCHK(hipGetDeviceCount(&ndev));
-    if (device < 0 || device >= ndev) return fail(SKR_EINVAL, "device %d out of range (%d devices)", device, ndev);
+// Sizes the context's workspace for (n, m, k) and sets the per-solve modes.
+int skr::prepare_solve(skr_ctx* ctx, int n, const skr_opts& opts) {
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = ensure_work(ctx, n, opts.m, opts.k);
+    if (rc) return rc;
+    Work& w = ctx->w;
+    w.fold = (w.nblk > FOLD_MIN || (opts.flags & SKR_FLAG_FOLD)) ? 1 : 0;
+    w.mixed = (opts.flags & SKR_FLAG_MIXED) ? 1 : 0;
+    return SKR_OK;
+}
+
+int skr::ctx_make(int device, hipStream_t stream, skr_ctx** out) {
     HIPCHK(hipSetDevice(device));
     skr_ctx* c = new skr_ctx();
     c->device = device;
-    c->stream = (hipStream_t)hip_stream;
+    c->stream = stream;
     if (hipHostMalloc((void**)&c->hctrl, sizeof(CtrlHost), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->hkeff, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -252,8 +416,25 @@ int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
     return SKR_OK;
 }
 
+extern "C" {
+
+const char* skr_version(void) { return "skr-gfx950 0.1"; }
+
+const char* skr_last_error(void) { return g_err.c_str(); }
+
+int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
+    if (!out) return fail(SKR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SKR_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    return ctx_make(device, (hipStream_t)hip_stream, out);
+}
+
+
 int skr_ctx_destroy(skr_ctx* ctx) {
     if (!ctx) return SKR_OK;
+    serve_free(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     free_work(ctx->w);
@@ -369,13 +550,8 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
     if (N < 0) return fail(SKR_EINVAL, "N must be >= 0");
     if (N == 0) return SKR_OK;
     if (!ops || !b_dev || !x_dev || !results_host) return fail(SKR_EINVAL, "NULL array argument");
-    const int m = opts->m, k = opts->k;
-    const double rtol = opts->rtol;
-    const int64_t maxit = opts->maxit;
-    if (m < 1 || m > MMAX) return fail(SKR_EINVAL, "m must be in [1, %d] (got %d)", MMAX, m);
-    if (k < 0 || k > KMAX || k >= m) return fail(SKR_EINVAL, "k must satisfy 0 <= k < m and k <= %d (got %d)", KMAX, k);
-    if (!(rtol > 0.0)) return fail(SKR_EINVAL, "rtol must be > 0");
-    if (maxit < 0) return fail(SKR_EINVAL, "maxit must be >= 0");
+    int rc = check_opts(opts);
+    if (rc) return rc;
     const int n = ops[0].n;
     std::vector<char> seen((size_t)N, 0);
     for (int64_t q = 0; q < N; ++q) {
@@ -386,188 +562,18 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
         if (!b_dev[idx] || !x_dev[idx]) return fail(SKR_EINVAL, "NULL b or x pointer for system %lld", (long long)idx);
         DevOp d;
         int64_t nv;
-        int rc = to_devop(ops[idx], d, nv);
+        rc = to_devop(ops[idx], d, nv);
         if (rc) return rc;
     }
-    HIPCHK(hipSetDevice(ctx->device));
-    int rc = ensure_work(ctx, n, m, k);
-    if (rc) return rc;
-    Work& w = ctx->w;
-    hipStream_t s = ctx->stream;
-    CtrlHost& hc = *ctx->hctrl;
+    if ((rc = prepare_solve(ctx, n, *opts))) return rc;
     int kin = 0;   // recycled vectors carried from the previous system (held in w.U)
     bool any_maxit = false;
-    const bool profile = (opts->flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
-    w.fold = (w.nblk > FOLD_MIN || (opts->flags & SKR_FLAG_FOLD)) ? 1 : 0;
-    w.mixed = (opts->flags & SKR_FLAG_MIXED) ? 1 : 0;
-    const double es = w.mixed ? 4.0 : 8.0;
-    int samp_j[PROF_MAXSAMP];
     for (int64_t q = 0; q < N; ++q) {
         const int64_t idx = order ? order[q] : q;
-        DevOp op;
-        int64_t nvals;
-        to_devop(ops[idx], op, nvals);
-        const double* b = b_dev[idx];
-        double* x = x_dev[idx];
         skr_result res;
-        std::memset(&res, 0, sizeof res);
-
-        launch_clear_nonfinite(s, w);
-        launch_init(s, w, b, x, rtol);
-        if (op.kind == SKR_OP_CSR) {
-            launch_check_finite(s, w, op.val, (long)nvals);
-        } else {
-            const long nzl = op.kind == SKR_OP_STENCIL7 ? (long)op.nz : 1L;
-            launch_check_finite(s, w, op.ax, nzl * op.ny * (op.nx + 1));
-            launch_check_finite(s, w, op.ay, nzl * (op.ny + 1) * op.nx);
-            if (op.kind == SKR_OP_STENCIL7) launch_check_finite(s, w, op.az, (nzl + 1) * op.ny * op.nx);
-        }
-        HIPLAUNCHCHK();
-        if ((rc = read_ctrl(ctx))) return rc;
-        if (hc.nonfinite || !std::isfinite(hc.bnorm)) {
-            launch_zero(s, x, n);
-            res.status = SKR_NONFINITE;
-            res.relres_true = NAN;
-            res.relres_est = NAN;
-            results_host[idx] = res;
-            continue;   // the carried recycle space is passed on untouched
-        }
-        if (hc.bnorm == 0.0) {
-            res.status = SKR_CONVERGED;
-            results_host[idx] = res;
-            continue;
-        }
-        const double bnorm = hc.bnorm, tol_abs = hc.tol_abs;
-        int64_t iters = 0, spmv = 0;
-        int cycles = 0;
-        int kc = 0;
-        // ---- start-up with the carried recycle space (App. B.1)
-        if (k > 0 && kin > 0) {
-            launch_spmm(s, w, op, kin);
-            launch_startup_gram(s, w, kin);
-            launch_chol(s, w, kin, 1);
-            launch_startup_apply(s, w, 1, 0);
-            HIPLAUNCHCHK();
-            HIPCHK(hipMemcpyAsync(ctx->hkeff, &w.coef->k_eff, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const int ke = *ctx->hkeff;
-            spmv += kin;
-            res.rank_dropped = kin - ke;
-            if (ke > 0) {
-                launch_startup_gram(s, w, ke);
-                launch_chol(s, w, ke, 0);
-                launch_startup_apply(s, w, 0, 1);
-                launch_startup_project(s, w, x, ke, 0);
-                HIPLAUNCHCHK();
-            }
-            if ((rc = read_ctrl(ctx))) return rc;
-            kc = hc.kc;
-            res.k_start = kc;
-        }
-        int status = -1;
-        double est = hc.beta;
-        // r equals b - A x computed directly (at x = 0, or right after a true-residual product)
-        bool r_is_true = kc == 0;
-        if (hc.beta <= tol_abs) {
-            launch_true_residual(s, w, op, b, x);
-            HIPLAUNCHCHK();
-            if ((rc = read_ctrl(ctx))) return rc;
-            spmv += 1;
-            if (std::sqrt(hc.res2) <= tol_abs) status = SKR_CONVERGED;
-            r_is_true = true;
-        }
-        // ---- Arnoldi cycles (Alg. 2)
-        while (status < 0) {
-            if (iters >= maxit) { status = SKR_MAXIT; break; }
-            if (w.mixed && !r_is_true) {
-                // refinement step: true FP64 residual, projected onto range(C) as at a system start
-                launch_true_residual(s, w, op, b, x);
-                spmv += 1;
-                if (kc > 0) launch_startup_project(s, w, x, kc, 1);
-                HIPLAUNCHCHK();
-            }
-            r_is_true = false;
-            int scyc = (kc == 0) ? m : m - kc;
-            scyc = (int)std::min<int64_t>(scyc, maxit - iters);
-            int nsamp = 0;
-            for (int j = 0; j < scyc; ++j) {
-                hipEvent_t* ev = nullptr;
-                if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
-                    ev = ctx->ev + 6 * nsamp;
-                    samp_j[nsamp++] = j;
-                }
-                launch_step(s, w, op, kc, j, scyc, ev);
-            }
-            launch_close_basis(s, w, kc, scyc);
-            if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
-            launch_cycle_dense(s, w, kc, scyc, k);
-            // the new recycle size is at most k (0 when no recycle space is formed this cycle)
-            const bool forms = k > 0 && (kc > 0 || scyc > k);
-            launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : 32) : 0);
-            HIPLAUNCHCHK();
-            if ((rc = read_ctrl(ctx))) return rc;
-            const int jd = hc.j_done;
-            if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
-            if (profile) {
-                skr_profile& pr = ctx->prof;
-                for (int q = 0; q < nsamp; ++q) {
-                    if (samp_j[q] >= jd) continue;   // steps after the stop are skipped launches
-                    float t[3];
-                    for (int e = 0; e < 3; ++e)
-                        HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[6 * q + 2 * e], ctx->ev[6 * q + 2 * e + 1]));
-                    double ba, bb, bc;
-                    step_bytes(op, nvals, kc + samp_j[q] + 1, es, ba, bb, bc);
-                    pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;
-                    pr.step_b.launches++; pr.step_b.ms += t[1]; pr.step_b.bytes += bb;
-                    pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc;
-                }
-                for (int j = 0; j < jd; ++j) {
-                    double ba, bb, bc;
-                    step_bytes(op, nvals, kc + j + 1, es, ba, bb, bc);
-                    pr.step_bytes += ba + bb + bc;
-                }
-                pr.steps += jd;
-                pr.cycles += 1;
-            }
-            iters += jd;
-            spmv += jd;
-            cycles += 1;
-            est = hc.est;
-            kc = hc.k_new;
-            if (!std::isfinite(est)) {
-                launch_zero(s, x, n);
-                status = SKR_NONFINITE;
-                kc = 0;
-                break;
-            }
-            if (est <= tol_abs || hc.breakdown) {
-                const int brk = hc.breakdown;
-                launch_true_residual(s, w, op, b, x);
-                HIPLAUNCHCHK();
-                if ((rc = read_ctrl(ctx))) return rc;
-                spmv += 1;
-                if (std::sqrt(hc.res2) <= tol_abs) {
-                    status = brk ? SKR_BREAKDOWN : SKR_CONVERGED;
-                    break;
-                }
-                r_is_true = true;
-            }
-        }
-        if (status == SKR_MAXIT) {
-            launch_true_residual(s, w, op, b, x);
-            HIPLAUNCHCHK();
-            if ((rc = read_ctrl(ctx))) return rc;
-            spmv += 1;
-            any_maxit = true;
-        }
-        res.status = status;
-        res.cycles = cycles;
-        res.iters = iters;
-        res.spmv = spmv;
-        res.relres_true = status == SKR_NONFINITE ? NAN : std::sqrt(hc.res2) / bnorm;
-        res.relres_est = est / bnorm;
+        if ((rc = solve_system(ctx, ops[idx], b_dev[idx], x_dev[idx], *opts, kin, res))) return rc;
         results_host[idx] = res;
-        kin = (k > 0) ? kc : 0;
+        any_maxit = any_maxit || res.status == SKR_MAXIT;
     }
     return any_maxit ? SKR_WARN_NOTCONVERGED : SKR_OK;
 }

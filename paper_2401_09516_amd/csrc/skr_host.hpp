@@ -1,0 +1,66 @@
+// Host-side internals of libskr shared by the C ABI (skr_api.hip) and the serving runtime
+// (skr_serve.hip): the context, error reporting and the per-system solve.
+#pragma once
+#include <string>
+
+#include "skr_internal.hpp"
+
+namespace skr {
+struct Server;
+constexpr int PROF_PERIOD = 16;   // one Arnoldi step in PROF_PERIOD is timed
+constexpr int PROF_MAXSAMP = (MMAX + PROF_PERIOD - 1) / PROF_PERIOD + 1;
+}  // namespace skr
+
+struct skr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    skr::Work w;
+    skr::CtrlHost* hctrl = nullptr;     // pinned
+    int* hkeff = nullptr;          // pinned
+    // sort scratch
+    double* sortD = nullptr;
+    size_t sortD_cap = 0;
+    double* sortP = nullptr;       // slice partials of the distance pass
+    size_t sortP_cap = 0;
+    long long* order_d = nullptr;
+    double* dist_d = nullptr;
+    size_t sortN_cap = 0;
+    // profiling
+    hipEvent_t ev[skr::PROF_MAXSAMP * 6] = {};
+    bool ev_ok = false;
+    int64_t step_counter = 0;
+    skr_profile prof = {};
+    // serving (skr_serve_start .. skr_serve_stop)
+    skr::Server* server = nullptr;
+};
+
+namespace skr {
+// Records the message of an error for skr_last_error() in the calling thread; returns code.
+int fail(int code, const char* fmt, ...);
+// The calling thread's last error message.
+const std::string& last_error();
+// Per-system solve and its set-up (skr_api.hip).
+int check_opts(const skr_opts* opts);
+int prepare_solve(skr_ctx* ctx, int n, const skr_opts& opts);
+int solve_system(skr_ctx* ctx, const skr_op& op, const double* b, double* x, const skr_opts& opts, int& kin,
+                 skr_result& res);
+int to_devop(const skr_op& o, DevOp& d, int64_t& nvals);
+// Internal context with its own stream (serving chains); freed with skr_ctx_destroy.
+int ctx_make(int device, hipStream_t stream, skr_ctx** out);
+// Device bytes of the workspace ensure_work allocates for (n, m, k).
+size_t work_bytes(int n, int m, int k);
+// Serving state of a context (skr_serve.hip).
+void serve_free(skr_ctx* ctx);
+}  // namespace skr
+
+#define HIPCHK(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return skr::fail(SKR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIPLAUNCHCHK()                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = hipGetLastError();                                                      \
+        if (e_ != hipSuccess) return skr::fail(SKR_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)

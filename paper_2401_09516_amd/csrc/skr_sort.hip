@@ -201,4 +201,83 @@ void launch_sort(hipStream_t s, const double* P, long N, long p, long start, dou
     hipLaunchKernelGGL(k_greedy, dim3(1), dim3(GW), 0, s, (const double*)D, N, start, order, dist);
 }
 
+// ---------------------------------------------------------------------------------------------
+// d2(a, b) of two parameter vectors for the serving runtime's nearest-chain choice, with the same
+// arithmetic as the all-pairs pass: exact squares accumulated in double-double, rounded once.
+// Slice q of the index (slen elements) goes to one workgroup: each thread sums a strided subset,
+// the 256 pairs are added in a fixed tree order with error-free sums, and the slice's pair is
+// stored; a one-thread kernel adds the slices in order and writes the rounded value.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void dd_add(double& s, double& lo, double hi, double l2) {
+    const double t = s + hi;
+    const double bb = t - s;
+    const double err = (s - (t - bb)) + (hi - bb);
+    s = t;
+    lo = lo + (err + l2);
+    const double t2 = s + lo;
+    lo = lo - (t2 - s);
+    s = t2;
+}
+
+__global__ __launch_bounds__(256) void k_dd_slice(const double* __restrict__ a, const double* __restrict__ b, long p,
+                                                  long slen, double* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ double ss[256], sl[256];
+    const long p0 = (long)blockIdx.x * slen, p1 = (p0 + slen < p) ? p0 + slen : p;
+    double s = 0.0, lo = 0.0;
+    int cnt = 0;
+    for (long e = p0 + threadIdx.x; e < p1; e += 256) {
+        const double d = a[e] - b[e];
+        const double hi = d * d;
+        const double he = __builtin_fma(d, d, -hi);
+        const double t = s + hi;
+        const double bb = t - s;
+        const double err = (s - (t - bb)) + (hi - bb);
+        s = t;
+        lo = lo + (err + he);
+        if (++cnt == 128) {      // renormalise as the all-pairs pass does per chunk
+            const double t2 = s + lo;
+            lo = lo - (t2 - s);
+            s = t2;
+            cnt = 0;
+        }
+    }
+    const double t2 = s + lo;
+    lo = lo - (t2 - s);
+    s = t2;
+    ss[threadIdx.x] = s;
+    sl[threadIdx.x] = lo;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double s1 = ss[threadIdx.x], l1 = sl[threadIdx.x];
+            dd_add(s1, l1, ss[threadIdx.x + w], sl[threadIdx.x + w]);
+            ss[threadIdx.x] = s1;
+            sl[threadIdx.x] = l1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss[0];
+        part[2 * blockIdx.x + 1] = sl[0];
+    }
+}
+
+__global__ void k_dd_combine(const double* __restrict__ part, int nslice, double* __restrict__ out) {
+#pragma clang fp contract(off)
+    double s = 0.0, lo = 0.0;
+    for (int q = 0; q < nslice; ++q) dd_add(s, lo, part[2 * q], part[2 * q + 1]);
+    *out = s + lo;
+}
+
+constexpr long DD_SLICE = 8192;
+long dd_slices(long p) { return (p + DD_SLICE - 1) / DD_SLICE; }
+
+// out[0] = d2(a, b); part holds 2 * dd_slices(p) doubles.
+void launch_dd_dist(hipStream_t s, const double* a, const double* b, long p, double* part, double* out) {
+    const long ns = dd_slices(p);
+    hipLaunchKernelGGL(k_dd_slice, dim3((unsigned)ns), dim3(256), 0, s, a, b, p, DD_SLICE, part);
+    hipLaunchKernelGGL(k_dd_combine, dim3(1), dim3(1), 0, s, (const double*)part, (int)ns, out);
+}
+
 }  // namespace skr

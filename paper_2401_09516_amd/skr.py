@@ -21,6 +21,7 @@ SKR_ENOMEM = -2
 SKR_EHIP = -3
 SKR_ENONFINITE = -4
 SKR_WARN_NOTCONVERGED = 1
+SKR_PENDING = 2
 
 SKR_CONVERGED = 0
 SKR_MAXIT = 1
@@ -36,7 +37,9 @@ SKR_FLAG_FOLD = 2
 SKR_FLAG_MIXED = 4
 
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
-            "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset")
+            "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
+            "skr_serve_start", "skr_submit", "skr_poll", "skr_wait", "skr_ticket_chain", "skr_serve_stats_get",
+            "skr_serve_stop")
 
 
 class SkrError(RuntimeError):
@@ -71,6 +74,17 @@ class skr_kernel_stat(ctypes.Structure):
 class skr_profile(ctypes.Structure):
     _fields_ = [("step_a", skr_kernel_stat), ("step_b", skr_kernel_stat), ("step_c", skr_kernel_stat),
                 ("steps", ctypes.c_int64), ("cycles", ctypes.c_int64), ("step_bytes", ctypes.c_double)]
+
+
+class skr_serve_opts(ctypes.Structure):
+    _fields_ = [("max_chains", ctypes.c_int32), ("workers", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64),
+                ("split_d2_rel", ctypes.c_double)]
+
+
+class skr_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("chains_live", ctypes.c_int32),
+                ("chains_created", ctypes.c_int32), ("chains_retired", ctypes.c_int32),
+                ("deferred", ctypes.c_int32), ("bytes_in_use", ctypes.c_uint64)]
 
 
 _lib = None
@@ -108,6 +122,21 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.skr_profile_get.restype = i32
     lib.skr_profile_reset.argtypes = [vp]
     lib.skr_profile_reset.restype = i32
+    lib.skr_serve_start.argtypes = [vp, ctypes.POINTER(skr_serve_opts)]
+    lib.skr_serve_start.restype = i32
+    lib.skr_submit.argtypes = [vp, ctypes.POINTER(skr_op), vp, i64, vp, vp, ctypes.POINTER(skr_opts),
+                               ctypes.POINTER(ctypes.c_uint64)]
+    lib.skr_submit.restype = i32
+    lib.skr_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(skr_result)]
+    lib.skr_poll.restype = i32
+    lib.skr_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(skr_result)]
+    lib.skr_wait.restype = i32
+    lib.skr_ticket_chain.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.skr_ticket_chain.restype = i32
+    lib.skr_serve_stats_get.argtypes = [vp, ctypes.POINTER(skr_serve_stats)]
+    lib.skr_serve_stats_get.restype = i32
+    lib.skr_serve_stop.argtypes = [vp]
+    lib.skr_serve_stop.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -202,10 +231,12 @@ def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 
     opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
     res = (skr_result * max(N, 1))()
     rc = _check(load_library().skr_solve_sequence(ctx, arr, bp, xp, N, optr, ctypes.byref(opts), res))
-    out = [dict(status=r.status, cycles=r.cycles, k_start=r.k_start, rank_dropped=r.rank_dropped,
+    return rc, [_result_dict(r) for r in list(res)[:N]]
+
+
+def _result_dict(r: skr_result) -> dict:
+    return dict(status=r.status, cycles=r.cycles, k_start=r.k_start, rank_dropped=r.rank_dropped,
                 iters=r.iters, spmv=r.spmv, relres_true=r.relres_true, relres_est=r.relres_est)
-           for r in list(res)[:N]]
-    return rc, out
 
 
 def skr_spmv(ctx: int, op: Operator, x, y) -> None:
@@ -231,3 +262,52 @@ def skr_profile_get(ctx: int) -> dict:
 
 def skr_profile_reset(ctx: int) -> None:
     _check(load_library().skr_profile_reset(ctx))
+
+
+# ----------------------------------------------------------------------------------- serving
+def skr_serve_start(ctx: int, max_chains: int = 8, workers: int = 4, arena_bytes: int = 0,
+                    split_d2_rel: float = float("inf")) -> None:
+    """Start the serving runtime on ``ctx`` (skr.h: nearest-chain admission, one stream per chain)."""
+    o = skr_serve_opts(max_chains=max_chains, workers=workers, arena_bytes=arena_bytes, split_d2_rel=split_d2_rel)
+    _check(load_library().skr_serve_start(ctx, ctypes.byref(o)))
+
+
+def skr_submit(ctx: int, op: Operator, params, p: int, b, x, m: int = 30, k: int = 10, rtol: float = 1e-8,
+               maxit: int = 10000, flags: int = 0) -> int:
+    """Submit one system; returns its ticket. ``op``, ``b`` and ``x`` must stay alive until it is done."""
+    t = ctypes.c_uint64()
+    opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
+    _check(load_library().skr_submit(ctx, ctypes.byref(op.c), _ptr(params), p, _ptr(b), _ptr(x),
+                                     ctypes.byref(opts), ctypes.byref(t)))
+    return t.value
+
+
+def skr_poll(ctx: int, ticket: int):
+    """The result dict when the ticket is done (it is then collected), None while pending."""
+    r = skr_result()
+    rc = _check(load_library().skr_poll(ctx, ticket, ctypes.byref(r)))
+    return None if rc == SKR_PENDING else _result_dict(r)
+
+
+def skr_wait(ctx: int, ticket: int) -> dict:
+    """Block until the ticket is done; returns (and collects) its result dict."""
+    r = skr_result()
+    _check(load_library().skr_wait(ctx, ticket, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def skr_ticket_chain(ctx: int, ticket: int):
+    """(chain id, position in the chain) of a ticket not yet collected; (-1, -1) while deferred."""
+    c, pos = ctypes.c_int32(), ctypes.c_int64()
+    _check(load_library().skr_ticket_chain(ctx, ticket, ctypes.byref(c), ctypes.byref(pos)))
+    return c.value, pos.value
+
+
+def skr_serve_stats_get(ctx: int) -> dict:
+    st = skr_serve_stats()
+    _check(load_library().skr_serve_stats_get(ctx, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in skr_serve_stats._fields_}
+
+
+def skr_serve_stop(ctx: int) -> None:
+    _check(load_library().skr_serve_stop(ctx))

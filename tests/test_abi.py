@@ -53,6 +53,12 @@ int main(void) {
   F(skr_kernel_stat, launches); F(skr_kernel_stat, ms); F(skr_kernel_stat, bytes);
   F(skr_profile, step_a); F(skr_profile, step_b); F(skr_profile, step_c); F(skr_profile, steps);
   F(skr_profile, cycles); F(skr_profile, step_bytes);
+  printf("skr_serve_opts %zu\nskr_serve_stats %zu\n", sizeof(skr_serve_opts), sizeof(skr_serve_stats));
+  F(skr_serve_opts, max_chains); F(skr_serve_opts, workers); F(skr_serve_opts, arena_bytes);
+  F(skr_serve_opts, split_d2_rel);
+  F(skr_serve_stats, submitted); F(skr_serve_stats, completed); F(skr_serve_stats, chains_live);
+  F(skr_serve_stats, chains_created); F(skr_serve_stats, chains_retired); F(skr_serve_stats, deferred);
+  F(skr_serve_stats, bytes_in_use);
   return 0;
 }
 ''')
@@ -61,7 +67,8 @@ int main(void) {
     out = dict(ln.rsplit(" ", 1) for ln in subprocess.run([str(exe)], capture_output=True, text=True,
                                                           check=True).stdout.splitlines())
     for cname, ct in (("skr_op", skr.skr_op), ("skr_opts", skr.skr_opts), ("skr_result", skr.skr_result),
-                      ("skr_kernel_stat", skr.skr_kernel_stat), ("skr_profile", skr.skr_profile)):
+                      ("skr_kernel_stat", skr.skr_kernel_stat), ("skr_profile", skr.skr_profile),
+                      ("skr_serve_opts", skr.skr_serve_opts), ("skr_serve_stats", skr.skr_serve_stats)):
         assert int(out[cname]) == ctypes.sizeof(ct), cname
         for f, _ in ct._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
