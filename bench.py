@@ -82,6 +82,14 @@ def parse():
                          "--copy-mib MiB (the reference kernel that scales hardware byte counters); for "
                          "rocprofv3 --pmc runs")
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: Darcy systems of several grid sizes arrive one at a time (Poisson) and "
+                         "are admitted by skr_submit into nearest chains; prints throughput and latency")
+    ap.add_argument("--serve-sizes", default="64,128,256,512,1024")
+    ap.add_argument("--serve-systems", type=int, default=30, help="systems submitted per run (sizes round-robin)")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the measured capacity")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-chains", type=int, default=8)
     a = ap.parse_args()
     if a.grid is None:
         a.grid = 256 if a.dim == 2 else 128
@@ -96,8 +104,118 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def serve_bench(a):
+    """Continuous batching: capacity from a saturation run (every system submitted at once), then
+    a Poisson arrival run at --serve-load times that capacity. Latency = completion - submission."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2401_09516_amd import skr
+    from workloads import darcy_sequence
+    from workloads.device import upload_systems
+
+    skr.load_library()
+    sizes = [int(v) for v in a.serve_sizes.split(",")]
+    per = -(-a.serve_systems // len(sizes))
+    pool = []
+    for N in sizes:
+        t = time.perf_counter()
+        for s_ in darcy_sequence(N, per, first_seed=1000 * N):
+            pool.append(s_)
+        log(f"generated {per} systems of {N}x{N} in {time.perf_counter() - t:.1f}s")
+    rng = np.random.default_rng(2401)
+    order = [int(i) for i in rng.permutation(len(pool))[:a.serve_systems]]
+    ops, bs, xs = upload_systems(pool, "cuda:0", a.matrix)
+    params = [torch.from_numpy(np.ascontiguousarray(s_.a.ravel())).cuda() for s_ in pool]
+    mode = skr.SKR_FLAG_MIXED if a.mixed else 0
+
+    def run(gaps):
+        ctx = skr.skr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+        skr.skr_serve_start(ctx, max_chains=a.serve_chains, workers=a.serve_workers)
+        sub, done, res, tickets = {}, {}, {}, {}
+        lock = threading.Lock()
+        finished = threading.Event()
+
+        def poller():
+            while True:
+                with lock:
+                    pending = [(i, t) for i, t in tickets.items() if i not in done]
+                    all_sent = len(tickets) == len(order)
+                for i, t in pending:
+                    r = skr.skr_poll(ctx, t)
+                    if r is not None:
+                        with lock:
+                            done[i] = time.perf_counter()
+                            res[i] = r
+                if all_sent and not pending:
+                    finished.set()
+                    return
+                time.sleep(0.0005)
+        th = threading.Thread(target=poller)
+        t0 = time.perf_counter()
+        th.start()
+        nxt = t0
+        for q, i in enumerate(order):
+            nxt += gaps[q]
+            while time.perf_counter() < nxt:
+                time.sleep(min(0.001, max(0.0, nxt - time.perf_counter())))
+            ts = time.perf_counter()
+            t = skr.skr_submit(ctx, ops[i], params[i], params[i].numel(), bs[i], xs[i], m=a.m, k=a.k, rtol=a.rtol,
+                               maxit=a.maxit, flags=mode)
+            with lock:
+                sub[i], tickets[i] = ts, t
+        finished.wait()
+        th.join()
+        wall = max(done.values()) - t0
+        stats = skr.skr_serve_stats_get(ctx)
+        skr.skr_serve_stop(ctx)
+        skr.skr_ctx_destroy(ctx)
+        lat = {i: done[i] - sub[i] for i in order}
+        return wall, lat, res, stats
+
+    log("saturation run (capacity)")
+    wall_sat, _, res_sat, st_sat = run([0.0] * len(order))
+    capacity = len(order) / wall_sat
+    lam = a.serve_load * capacity
+    gaps = list(np.random.default_rng(2402).exponential(1.0 / lam, len(order)))
+    log(f"capacity {capacity:.2f} systems/s; Poisson run at {lam:.2f} systems/s")
+    wall, lat, res, st = run(gaps)
+    conv = sum(r["status"] in (skr.SKR_CONVERGED, skr.SKR_BREAKDOWN) for r in res.values())
+    L = np.array([lat[i] for i in order]) * 1e3
+    by_size = {}
+    for N in sizes:
+        idx = [i for i in order if pool[i].N_g == N]
+        if idx:
+            v = np.array([lat[i] for i in idx]) * 1e3
+            by_size[str(N)] = dict(systems=len(idx), p50_ms=round(float(np.percentile(v, 50)), 1),
+                                   p99_ms=round(float(np.percentile(v, 99)), 1),
+                                   iters_mean=float(np.mean([res[i]["iters"] for i in idx])))
+    out = {
+        "metric": "serving: systems/s and latency, Poisson arrivals of Darcy systems of mixed grid sizes",
+        "value": round(conv / wall, 3), "unit": "systems/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"darcy2d-serving-{'-'.join(map(str, sizes))}-{len(order)}sys-gcrodr({a.m},{a.k})"
+                               + ("-fp32basis" if a.mixed else ""),
+                   "sizes": sizes, "systems": len(order), "m": a.m, "k": a.k, "rtol": a.rtol,
+                   "workers": a.serve_workers, "max_chains": a.serve_chains, "load": a.serve_load},
+        "capacity_systems_per_s": round(capacity, 3), "arrival_rate": round(lam, 3),
+        "latency_ms": {"p50": round(float(np.percentile(L, 50)), 1), "p99": round(float(np.percentile(L, 99)), 1),
+                       "max": round(float(L.max()), 1)},
+        "latency_by_size": by_size, "converged": conv,
+        "max_relres": max(r["relres_true"] for r in res.values()),
+        "chains": {"created": st["chains_created"], "retired": st["chains_retired"]},
+        "saturation_wall_s": round(wall_sat, 2), "poisson_wall_s": round(wall, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.serve and a.gpus == 1:
+        serve_bench(a)
+        return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build measures one GPU. Sorted chains "
               "would shard across GPUs without communication (contiguous slices of the sorted order).",
