@@ -90,6 +90,10 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the measured capacity")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-chains", type=int, default=8)
+    ap.add_argument("--advdiff", action="store_true",
+                    help="time-stepping mode: unsteady advection-diffusion, --chains chains of --steps-per-chain "
+                         "backward-Euler steps on a --grid^2 mesh, each chain solved as a chain of the serving runtime")
+    ap.add_argument("--steps-per-chain", type=int, default=32)
     a = ap.parse_args()
     if a.grid is None:
         a.grid = 256 if a.dim == 2 else 128
@@ -211,10 +215,108 @@ def serve_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def advdiff_bench(a):
+    """Backward-Euler chains A x^{t+1} = x^t / dt: one host thread per chain submits each step when
+    the previous one is done; the serving runtime keeps each chain's recycle space resident and runs
+    up to --serve-workers chains at once on their own streams."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2401_09516_amd import skr
+    from workloads.advdiff import advdiff_chains
+    from workloads.device import upload_systems
+
+    skr.load_library()
+    N, C, T = a.grid, a.chains, a.steps_per_chain
+    t = time.perf_counter()
+    chains = advdiff_chains(N, C, first_seed=0)
+    log(f"generated {C} chains of {N}x{N} in {time.perf_counter() - t:.1f}s")
+    ops, _, _ = upload_systems(chains, "cuda:0")
+    params = [torch.from_numpy(c.params).cuda() for c in chains]
+    x0 = [torch.from_numpy(c.x0).cuda() for c in chains]
+    torch.cuda.synchronize()          # the chain threads read these on their own streams
+    mode = skr.SKR_FLAG_MIXED if a.mixed else 0
+
+    def run(nch, nsteps, k):
+        ctx = skr.skr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+        skr.skr_serve_start(ctx, max_chains=max(nch, 1), workers=a.serve_workers, split_d2_rel=1e-12)
+        res = [[None] * nsteps for _ in range(nch)]
+        errs = []
+
+        def chain_loop(c):
+            try:
+                st = torch.cuda.Stream()
+                with torch.cuda.stream(st):
+                    xa = torch.empty_like(x0[c])
+                    xb = torch.empty_like(x0[c])
+                    b = torch.empty_like(x0[c])
+                    prev = x0[c]
+                    for q in range(nsteps):
+                        torch.div(prev, chains[c].dt, out=b)
+                        st.synchronize()
+                        x = xa if q % 2 == 0 else xb
+                        tk = skr.skr_submit(ctx, ops[c], params[c], params[c].numel(), b, x, m=a.m, k=k,
+                                            rtol=a.rtol, maxit=a.maxit, flags=mode)
+                        res[c][q] = skr.skr_wait(ctx, tk)
+                        prev = x
+            except BaseException as e:     # re-raised in the calling thread
+                errs.append(e)
+        th = [threading.Thread(target=chain_loop, args=(c,)) for c in range(nch)]
+        t0 = time.perf_counter()
+        for x_ in th:
+            x_.start()
+        for x_ in th:
+            x_.join()
+        wall = time.perf_counter() - t0
+        stats = skr.skr_serve_stats_get(ctx)
+        skr.skr_serve_stop(ctx)
+        skr.skr_ctx_destroy(ctx)
+        if errs:
+            raise errs[0]
+        flat = [r for rc in res for r in rc]
+        conv = sum(r["status"] in (skr.SKR_CONVERGED, skr.SKR_BREAKDOWN) for r in flat)
+        return dict(wall=wall, value=conv / wall, converged=conv, solves=len(flat),
+                    iters_mean=float(np.mean([r["iters"] for r in flat])),
+                    iters_first=float(np.mean([rc[0]["iters"] for rc in res])),
+                    iters_later=float(np.mean([r["iters"] for rc in res for r in rc[1:]])) if nsteps > 1 else None,
+                    max_relres=max(r["relres_true"] for r in flat), chains=stats["chains_created"])
+
+    log("warm-up")
+    run(min(C, 4), 2, a.k)
+    log(f"timed run: {C} chains x {T} steps")
+    main = run(C, T, a.k)
+    sub_c, sub_t = min(C, 8), min(T, 8)
+    log(f"GMRES(m) and GCRO-DR on {sub_c} chains x {sub_t} steps")
+    g = run(sub_c, sub_t, 0)
+    s_ = run(sub_c, sub_t, a.k)
+    out = {
+        "metric": "config-3: systems/s of backward-Euler advection-diffusion chains (GCRO-DR recycling along each chain)",
+        "value": round(main["value"], 3), "unit": "systems/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"advdiff2d-{N}x{N}-{C}chains-x{T}steps-gcrodr({a.m},{a.k})"
+                               + ("-fp32basis" if a.mixed else ""),
+                   "grid": N, "n": N * N, "chains": C, "steps": T, "dt": chains[0].dt, "m": a.m, "k": a.k,
+                   "rtol": a.rtol, "workers": a.serve_workers},
+        "run": main,
+        "subset": {"chains": sub_c, "steps": sub_t, "gmres": g, "gcrodr": s_,
+                   "speedup_vs_gmres": round(s_["value"] / g["value"], 2) if g["value"] > 0 else None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.serve and a.gpus == 1:
         serve_bench(a)
+        return
+    if a.advdiff and a.gpus == 1:
+        if a.grid is None or a.grid == 256 and "--grid" not in sys.argv:
+            a.grid = 512
+        if "--chains" not in sys.argv:
+            a.chains = 64
+        advdiff_bench(a)
         return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build measures one GPU. Sorted chains "

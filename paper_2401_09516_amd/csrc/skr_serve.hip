@@ -26,7 +26,8 @@
 #include "skr_host.hpp"
 
 namespace skr {
-void launch_dd_dist(hipStream_t s, const double* a, const double* b, long p, double* part, double* out);
+void launch_dd_dist(hipStream_t s, const double* a, const double* const* bs, int K, long p, double* part,
+                    double* out);
 long dd_slices(long p);
 
 namespace {
@@ -87,6 +88,8 @@ struct Server {
     size_t dpart_cap = 0;
     double* dout = nullptr;
     double* hout = nullptr;       // pinned
+    const double** dptrs = nullptr;   // device array of the candidates' tail pointers
+    const double** hptrs = nullptr;   // pinned staging of that array
     int dout_cap = 0;
     double* zero = nullptr;       // zeros, for ||params||^2 with the same exact arithmetic
     size_t zero_cap = 0;
@@ -115,7 +118,7 @@ void free_chain(Chain* c) {
 int distances(Server* S, const double* params, int64_t p, const std::vector<Chain*>& cand, std::vector<double>& d2) {
     d2.assign(cand.size(), NAN);
     if (cand.empty()) return SKR_OK;
-    const size_t need = 2 * (size_t)dd_slices((long)p);
+    const size_t need = 2 * (size_t)dd_slices((long)p) * cand.size();
     if (S->dpart_cap < need) {
         if (S->dpart) (void)hipFree(S->dpart);
         S->dpart = nullptr;
@@ -126,15 +129,23 @@ int distances(Server* S, const double* params, int64_t p, const std::vector<Chai
     if (S->dout_cap < (int)cand.size()) {
         if (S->dout) (void)hipFree(S->dout);
         if (S->hout) (void)hipHostFree(S->hout);
+        if (S->dptrs) (void)hipFree(S->dptrs);
+        if (S->hptrs) (void)hipHostFree(S->hptrs);
         S->dout = nullptr;
         S->hout = nullptr;
+        S->dptrs = nullptr;
+        S->hptrs = nullptr;
         S->dout_cap = 0;
         HIPCHK(hipMalloc((void**)&S->dout, cand.size() * sizeof(double)));
         HIPCHK(hipHostMalloc((void**)&S->hout, cand.size() * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipMalloc((void**)&S->dptrs, cand.size() * sizeof(double*)));
+        HIPCHK(hipHostMalloc((void**)&S->hptrs, cand.size() * sizeof(double*), hipHostMallocDefault));
         S->dout_cap = (int)cand.size();
     }
     hipStream_t s = S->owner->stream;
-    for (size_t c = 0; c < cand.size(); ++c) launch_dd_dist(s, params, cand[c]->tail, (long)p, S->dpart, S->dout + c);
+    for (size_t c = 0; c < cand.size(); ++c) S->hptrs[c] = cand[c]->tail;
+    HIPCHK(hipMemcpyAsync(S->dptrs, S->hptrs, cand.size() * sizeof(double*), hipMemcpyHostToDevice, s));
+    launch_dd_dist(s, params, S->dptrs, (int)cand.size(), (long)p, S->dpart, S->dout);
     HIPLAUNCHCHK();
     HIPCHK(hipMemcpyAsync(S->hout, S->dout, cand.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -479,6 +490,8 @@ int skr_serve_stop(skr_ctx* ctx) {
     if (S->dout) (void)hipFree(S->dout);
     if (S->hout) (void)hipHostFree(S->hout);
     if (S->zero) (void)hipFree(S->zero);
+    if (S->dptrs) (void)hipFree(S->dptrs);
+    if (S->hptrs) (void)hipHostFree(S->hptrs);
     delete S;
     ctx->server = nullptr;
     return SKR_OK;

@@ -202,11 +202,12 @@ void launch_sort(hipStream_t s, const double* P, long N, long p, long start, dou
 }
 
 // ---------------------------------------------------------------------------------------------
-// d2(a, b) of two parameter vectors for the serving runtime's nearest-chain choice, with the same
-// arithmetic as the all-pairs pass: exact squares accumulated in double-double, rounded once.
-// Slice q of the index (slen elements) goes to one workgroup: each thread sums a strided subset,
-// the 256 pairs are added in a fixed tree order with error-free sums, and the slice's pair is
-// stored; a one-thread kernel adds the slices in order and writes the rounded value.
+// d2(a, b_c) of a parameter vector against K others for the serving runtime's nearest-chain
+// choice, with the same arithmetic as the all-pairs pass: exact squares accumulated in
+// double-double, rounded once. Slice q of the index (slen elements) of vector c goes to one
+// workgroup: each thread sums a strided subset, the 256 pairs are added in a fixed tree order with
+// error-free sums, and the slice's pair is stored; one thread per vector then adds its slices in
+// order and writes the rounded value.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void dd_add(double& s, double& lo, double hi, double l2) {
     const double t = s + hi;
@@ -219,8 +220,8 @@ __device__ __forceinline__ void dd_add(double& s, double& lo, double hi, double 
     s = t2;
 }
 
-__global__ __launch_bounds__(256) void k_dd_slice(const double* __restrict__ a, const double* __restrict__ b, long p,
-                                                  long slen, double* __restrict__ part) {
+__device__ __forceinline__ void k_dd_slice_body(const double* __restrict__ a, const double* __restrict__ b, long p,
+                                                long slen, double* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ double ss[256], sl[256];
     const long p0 = (long)blockIdx.x * slen, p1 = (p0 + slen < p) ? p0 + slen : p;
@@ -263,21 +264,34 @@ __global__ __launch_bounds__(256) void k_dd_slice(const double* __restrict__ a, 
     }
 }
 
-__global__ void k_dd_combine(const double* __restrict__ part, int nslice, double* __restrict__ out) {
+// d2(a, b_c) for K vectors b_c at once: blockIdx.y = c, slice partials at part + 2 * nslice * c.
+__global__ __launch_bounds__(256) void k_dd_slice_multi(const double* __restrict__ a, const double* const* bs,
+                                                        long p, long slen, double* __restrict__ part) {
+    const int c = blockIdx.y;
+    k_dd_slice_body(a, bs[c], p, slen, part + 2 * (size_t)gridDim.x * c);
+}
+
+// One thread per vector: adds its slices in order and rounds once.
+__global__ void k_dd_combine(const double* __restrict__ part, int nslice, int K, double* __restrict__ out) {
 #pragma clang fp contract(off)
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= K) return;
     double s = 0.0, lo = 0.0;
-    for (int q = 0; q < nslice; ++q) dd_add(s, lo, part[2 * q], part[2 * q + 1]);
-    *out = s + lo;
+    const double* pc = part + 2 * (size_t)nslice * c;
+    for (int q = 0; q < nslice; ++q) dd_add(s, lo, pc[2 * q], pc[2 * q + 1]);
+    out[c] = s + lo;
 }
 
 constexpr long DD_SLICE = 8192;
 long dd_slices(long p) { return (p + DD_SLICE - 1) / DD_SLICE; }
 
-// out[0] = d2(a, b); part holds 2 * dd_slices(p) doubles.
-void launch_dd_dist(hipStream_t s, const double* a, const double* b, long p, double* part, double* out) {
+// out[c] = d2(a, bs[c]) for c < K (bs: device array of K device pointers); part holds
+// 2 * K * dd_slices(p) doubles.
+void launch_dd_dist(hipStream_t s, const double* a, const double* const* bs, int K, long p, double* part,
+                    double* out) {
     const long ns = dd_slices(p);
-    hipLaunchKernelGGL(k_dd_slice, dim3((unsigned)ns), dim3(256), 0, s, a, b, p, DD_SLICE, part);
-    hipLaunchKernelGGL(k_dd_combine, dim3(1), dim3(1), 0, s, (const double*)part, (int)ns, out);
+    hipLaunchKernelGGL(k_dd_slice_multi, dim3((unsigned)ns, (unsigned)K), dim3(256), 0, s, a, bs, p, DD_SLICE, part);
+    hipLaunchKernelGGL(k_dd_combine, dim3((K + 63) / 64), dim3(64), 0, s, (const double*)part, (int)ns, K, out);
 }
 
 }  // namespace skr

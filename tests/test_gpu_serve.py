@@ -219,3 +219,57 @@ def test_serve_errors(env):
         skr.skr_serve_stop(ctx)
     finally:
         skr.skr_ctx_destroy(ctx)
+
+
+def test_serve_time_stepping_chains(env):
+    """Backward-Euler advection-diffusion chains (24x24, 3 chains x 4 steps): the right-hand side
+    of step t + 1 is x^t / dt, so each chain's systems are submitted one after another and keep
+    their chain (identical parameters, d2 = 0) and its recycle space. Against the oracle stepping
+    the same chains from its own solutions."""
+    torch, skr = env
+    log("[serve] time-stepping advection-diffusion chains")
+    from workloads.advdiff import advdiff_chains
+    chains = advdiff_chains(24, 3, first_seed=900)
+    steps, m, k, rtol = 4, 20, 6, 1e-9
+    ctx = make_ctx(torch)
+    try:
+        skr.skr_serve_start(ctx, max_chains=8, workers=3, split_d2_rel=1e-12)
+        ops, _, _ = upload_systems(chains, "cuda:0")
+        params = [torch.from_numpy(c.params).cuda() for c in chains]
+        xs = [[torch.zeros(c.n, dtype=torch.float64, device="cuda") for _ in range(steps)] for c in chains]
+        bs = [torch.empty(c.n, dtype=torch.float64, device="cuda") for c in chains]
+        res = [[None] * steps for _ in chains]
+        where = [[None] * steps for _ in chains]
+        for t in range(steps):
+            tickets = []
+            for c, ch in enumerate(chains):
+                prev = torch.from_numpy(ch.x0).cuda() if t == 0 else xs[c][t - 1]
+                torch.div(prev, ch.dt, out=bs[c])
+                torch.cuda.synchronize()
+                tickets.append(skr.skr_submit(ctx, ops[c], params[c], params[c].numel(), bs[c], xs[c][t], m=m, k=k,
+                                              rtol=rtol, maxit=20000))
+            for c, tk in enumerate(tickets):
+                where[c][t] = skr.skr_ticket_chain(ctx, tk)
+                res[c][t] = skr.skr_wait(ctx, tk)
+        torch.cuda.synchronize()
+        xh = [[x.cpu().numpy() for x in xc] for xc in xs]
+        skr.skr_serve_stop(ctx)
+    finally:
+        skr.skr_ctx_destroy(ctx)
+    for c, ch in enumerate(chains):
+        assert [w for w in where[c]] == [(c, t) for t in range(steps)]
+        smin = np.linalg.svd(ch.A.toarray(), compute_uv=False)[-1]
+        Y, b = None, ch.x0 / ch.dt
+        for t in range(steps):
+            r = oracle.gcrodr(ch.A, b, Y, m, k, rtol, 20000)
+            g = res[c][t]
+            mu = np.linalg.norm(b) / smin / np.linalg.norm(r.x)
+            rel = np.linalg.norm(xh[c][t] - r.x) / np.linalg.norm(r.x)
+            log(f"  chain {c} step {t}: iters gpu {g['iters']} oracle {r.iters}  rel {rel:.2e}")
+            assert g["status"] == r.status == oracle.CONVERGED
+            assert g["relres_true"] <= rtol * (1 + 1e-9)
+            # both runs step from their own x^t, which agree to the solve tolerance: mu (rr + rr) per step,
+            # accumulated over the steps taken
+            assert rel <= max(1e-7, 1.01 * (t + 1) * mu * (g["relres_true"] + r.relres_true))
+            assert abs(g["iters"] - r.iters) <= (1 if t < 2 else max(3, 0.1 * r.iters))
+            Y, b = r.Y_next, r.x / ch.dt

@@ -88,6 +88,22 @@ def test_advdiff_operator():
     assert all(1e-3 <= s.nu <= 1e-2 for s in seq) and seq[0].A.shape == (36, 36)
 
 
+def test_advdiff_time_stepping_chains():
+    from workloads.advdiff import advdiff_chains
+    ch = advdiff_chains(12, 3, first_seed=5, dt=1e-2)
+    again = advdiff_chains(12, 3, first_seed=5, dt=1e-2)
+    N, n = 12, 144
+    interior = np.array([i * N + j for i in range(1, N - 1) for j in range(1, N - 1)])
+    for c, d in zip(ch, again):
+        assert 1e-3 <= c.nu <= 1e-2
+        assert np.array_equal(c.params, d.params) and np.array_equal(c.x0, d.x0)    # seeded
+        assert c.params.shape == (1 + 2 * n,) and c.params[0] == c.nu
+        # upwind advection and the Laplacian cancel in the row sums of interior rows: 1/dt
+        assert np.allclose(np.asarray(c.A.sum(axis=1)).ravel()[interior], 1.0 / c.dt, rtol=1e-12)
+        assert not np.allclose(c.A.toarray(), c.A.toarray().T)
+    assert len({c.nu for c in ch}) == 3
+
+
 def test_3d_structure_and_symmetry():
     from workloads import darcy3d_sequence
     for N in (1, 2, 5):

@@ -79,3 +79,41 @@ def advdiff_sequence(N: int, count: int, first_seed: int = 0, dt: float = 1e-2, 
         nu = 1e-3 + 9e-3 * np.random.default_rng([SEED_ROOT, 8, s]).random()
         out.append(AdvDiffSystem(N, nu, s, dt, amp))
     return out
+
+
+class AdvDiffChain:
+    """One time-stepping chain: a fixed operator A = I/dt - nu Lap_h + upwind(b . grad_h) with its own
+    nu ~ U[1e-3, 1e-2] and seeded divergence-free velocity b = curl(psi), and a seeded smooth initial
+    state x0 (a few low sine modes). Its systems are the backward-Euler steps A x^{t+1} = x^t / dt, so
+    the right-hand side of step t + 1 is the solution of step t divided by dt.
+
+    ``params`` identifies the operator (nu, then the two velocity components at the nodes): the
+    vector a chain's systems are admitted by.
+    """
+
+    def __init__(self, N: int, seed: int, dt: float = 1e-2, amp: float = 1.0):
+        self.N_g = N
+        self.dt = dt
+        self.nu = 1e-3 + 9e-3 * np.random.default_rng([SEED_ROOT, 9, int(seed)]).random()
+        self.bx, self.by = stream_velocity(N, 10_000 + int(seed), amp)
+        self.A = advdiff_matrix(N, self.nu, self.bx, self.by, dt)
+        rng = np.random.default_rng([SEED_ROOT, 10, int(seed)])
+        x = np.arange(1, N + 1) / (N + 1)
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        x0 = np.zeros((N, N))
+        for kx in range(1, 4):
+            for ky in range(1, 4):
+                x0 += rng.standard_normal() / (kx * ky) * np.sin(np.pi * kx * X) * np.sin(np.pi * ky * Y)
+        self.x0 = x0.ravel()
+        self.b = self.x0 / dt             # right-hand side of the first step
+        self.params = np.concatenate([[self.nu], self.bx.ravel(), self.by.ravel()])
+
+    @property
+    def n(self):
+        return self.N_g * self.N_g
+
+
+def advdiff_chains(N: int, count: int, first_seed: int = 0, dt: float = 1e-2, amp: float = 1.0):
+    """``count`` independent time-stepping chains on an N x N grid."""
+    return [AdvDiffChain(N, s, dt, amp) for s in range(first_seed, first_seed + count)]
+
