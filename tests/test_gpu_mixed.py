@@ -106,3 +106,21 @@ def test_mixed_fold_path(env):
                                      flags=skr.SKR_FLAG_MIXED | skr.SKR_FLAG_FOLD)
     assert rc == skr.SKR_OK
     compare_chain(systems, res, xs, _ref(systems, None, 30, 10, 1e-8), "mixed-fold")
+
+
+def test_mixed_config2_prefix(env):
+    """256x256 Darcy, the first 2 systems of the sorted 400-system chain, GCRO-DR(60,20), FP32 basis:
+    the bench workload's size and launch configuration, against the oracle's mixed mode."""
+    torch, skr, ctx = env
+    log("[mixed] config-2 prefix: 256x256, 2 systems of the sorted chain")
+    systems = darcy_sequence(256, 400)
+    P = param_matrix(systems)
+    Pd = torch.from_numpy(np.ascontiguousarray(P)).cuda()
+    order, _ = skr.skr_sort(ctx, Pd, P.shape[0], P.shape[1], 0)
+    del P, Pd
+    pre = [systems[i] for i in order[:2]]
+    ops, bs, xs = upload_systems(pre, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=60, k=20, rtol=1e-8, maxit=20000,
+                                     flags=skr.SKR_FLAG_MIXED)
+    assert rc == skr.SKR_OK
+    compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-cfg2-prefix")
