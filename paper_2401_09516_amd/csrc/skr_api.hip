@@ -275,6 +275,8 @@ int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double*
     double est = hc.beta;
     // r equals b - A x computed directly (at x = 0, or right after a true-residual product)
     bool r_is_true = kc == 0;
+    int prev_jd = 0, prev_scyc = 0;     // launch-length prediction (see the cycle loop)
+    double prev_rate = 0.0;
     if (hc.beta <= tol_abs) {
         launch_true_residual(s, w, op, b, x);
         HIPLAUNCHCHK();
@@ -296,14 +298,37 @@ int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double*
         r_is_true = false;
         int scyc = (kc == 0) ? m : m - kc;
         scyc = (int)std::min<int64_t>(scyc, maxit - iters);
+        // Launch length. A step launched after the cycle has stopped exits at once, but still costs a
+        // launch, so when this cycle is predicted to stop early (the previous cycle stopped early, or
+        // the previous cycle's contraction per step reaches the tolerance) only the predicted steps
+        // plus a margin are launched, the control block is read, and the rest follow only if the
+        // cycle has not stopped. The kernels and their order are the same either way.
+        int pred = 0;
+        if (cycles == 0) {
+            pred = ctx->pred_first;
+        } else if (prev_jd < prev_scyc) {
+            pred = prev_jd;
+        } else if (prev_rate > 0.0 && prev_rate < 1.0 && est > tol_abs) {
+            const double steps = std::ceil(std::log(tol_abs / est) / std::log(prev_rate));
+            if (steps < scyc) pred = std::max(1, (int)steps);
+        }
+        const int nfirst = pred > 0 ? std::min(scyc, pred + std::max(2, pred / 4)) : scyc;
         int nsamp = 0;
-        for (int j = 0; j < scyc; ++j) {
-            hipEvent_t* ev = nullptr;
-            if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
-                ev = ctx->ev + 6 * nsamp;
-                samp_j[nsamp++] = j;
+        auto launch_steps = [&](int j0, int j1) {
+            for (int j = j0; j < j1; ++j) {
+                hipEvent_t* ev = nullptr;
+                if (profile && (ctx->step_counter++ % PROF_PERIOD) == PROF_PERIOD / 2 && nsamp < PROF_MAXSAMP) {
+                    ev = ctx->ev + 6 * nsamp;
+                    samp_j[nsamp++] = j;
+                }
+                launch_step(s, w, op, kc, j, scyc, ev);
             }
-            launch_step(s, w, op, kc, j, scyc, ev);
+        };
+        launch_steps(0, nfirst);
+        if (nfirst < scyc) {
+            HIPLAUNCHCHK();
+            if ((rc = read_ctrl(ctx))) return rc;
+            if (!hc.stop) launch_steps(nfirst, scyc);
         }
         launch_close_basis(s, w, kc, scyc);
         if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
@@ -336,6 +361,10 @@ int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double*
             pr.steps += jd;
             pr.cycles += 1;
         }
+        if (cycles == 0) ctx->pred_first = jd < scyc ? jd : 0;
+        prev_jd = jd;
+        prev_scyc = scyc;
+        prev_rate = (hc.beta > 0.0 && hc.est > 0.0) ? std::pow(hc.est / hc.beta, 1.0 / jd) : 0.0;
         iters += jd;
         spmv += jd;
         cycles += 1;

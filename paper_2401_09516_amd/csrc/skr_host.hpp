@@ -30,6 +30,9 @@ struct skr_ctx {
     bool ev_ok = false;
     int64_t step_counter = 0;
     skr_profile prof = {};
+    // steps the first cycle of the previous system on this context ran when it stopped early (0: it
+    // ran the full cycle); predicts the launch length of the next system's first cycle
+    int pred_first = 0;
     // serving (skr_serve_start .. skr_serve_stop)
     skr::Server* server = nullptr;
 };
