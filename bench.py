@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--gmres-systems", type=int, default=4, help="prefix of the sorted chain solved by GMRES(m)")
     ap.add_argument("--cpu-systems", type=int, default=2, help="oracle sample: first systems of the sorted chain")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the untimed identity-order solve of the same systems (the sort ablation)")
     ap.add_argument("--spmv-grid", type=int, default=2048, help="grid of the > 256 MB SpMV bandwidth case")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="untimed: one pass of the hot path over --systems systems, then a device copy of "
@@ -449,6 +451,24 @@ def main():
                         frac=round(ach / HBM_PEAK_GBS, 4),
                         traffic=round(traffic) if traffic is not None else None, kernel=kernel_names[dom],
                         avg_us=round(kern[dom]["avg_us"], 2), bytes_per_launch=round(kern[dom]["avg_bytes"]))
+    # the sort ablation (Sec. 4.1): the same systems as one chain in their original order, untimed by
+    # the bench line; the library call is the same, only the order differs
+    ablation = None
+    if not a.no_ablation and a.dim == 2 and C == 1:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rci, resi = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
+                                           flags=mode)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - ta
+        convi = sum(r["status"] in (skr.SKR_CONVERGED, skr.SKR_BREAKDOWN) for r in resi)
+        ablation = dict(order="identity (unsorted)", value=round(convi / ta, 3), unit="systems/s", converged=convi,
+                        iters_total=int(np.sum([r["iters"] for r in resi])),
+                        iters_total_sorted=int(np.sum(iters)),
+                        iters_ratio_unsorted_over_sorted=round(float(np.sum([r["iters"] for r in resi]))
+                                                               / max(1, int(np.sum(iters))), 4))
+        log(f"ablation: identity order {ablation['value']} systems/s, iterations x{ablation['iters_ratio_unsorted_over_sorted']}")
+
     # timing of the sort alone
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -571,6 +591,7 @@ def main():
         "sort_ms": round(sort_ms, 2),
         "gmres": gmres,
         "speedup_vs_gmres": round(value / gmres["value"], 2) if gmres and gmres["value"] > 0 else None,
+        "sort_ablation": ablation,
         "kernels": kern,
         "arnoldi_steps_profiled": prof["steps"],
         "arnoldi_step_bytes_total": prof["step_bytes"],
