@@ -12,9 +12,15 @@ Printed: one JSON line with systems/s (converged systems only), the roofline of 
 Arnoldi-step kernel (sampled hipEvent timings inside the timed region), GMRES(60) on the same GPU
 for a prefix of the sorted chain, SpMV bandwidth, and the CPU oracle timed on a bounded sample.
 
---dim 3 is a secondary mode: 3-D Darcy on a 128^3 grid (n = 2,097,152; 7-point operator, CSR or
-matrix-free), 8 systems by default. Its working set (basis about 1.4 GB) is far beyond the 256 MB
-Infinity Cache, so its kernel rates are HBM rates. It reports no oracle sample.
+Secondary modes, each printing its own JSON line:
+--dim 3     3-D Darcy on a 128^3 grid (n = 2,097,152; 7-point operator, CSR or matrix-free), 8 systems
+            by default. Its working set (basis about 1.4 GB) is far beyond the 256 MB Infinity Cache,
+            so its kernel rates are HBM rates. No oracle sample.
+--mixed     FP32-stored basis and recycle space, FP64 arithmetic and refinement (any mode).
+--chains C  the sorted order split into C contiguous chains solved concurrently.
+--serve     Darcy systems of several grid sizes arriving one at a time (Poisson) through the serving
+            runtime: capacity, throughput and latency.
+--advdiff   time-stepping advection-diffusion chains (512^2, 64 chains x 32 backward-Euler steps).
 """
 import argparse
 import json
