@@ -124,3 +124,49 @@ def test_mixed_config2_prefix(env):
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
     compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-cfg2-prefix")
+
+
+def test_mixed_edge_cases(env):
+    """The refinement step around the exits of a solve: b = 0, NaN in b, maxit = 1, a happy breakdown
+    (identity operator), a start-up whose projection already solves the system, against the oracle's
+    mixed mode where it defines the outcome."""
+    torch, skr, ctx = env
+    log("[mixed] edge cases")
+    import types
+
+    import scipy.sparse as sp
+    M = skr.SKR_FLAG_MIXED
+    s = darcy_sequence(16, 1, first_seed=5)[0]
+    n = s.n
+    ops, bs, xs = upload_systems([s, s, s, s], "cuda:0")
+    bs[1].zero_()
+    bs[2][5] = float("nan")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=5000, flags=M)
+    assert rc == skr.SKR_OK
+    assert res[0]["status"] == skr.SKR_CONVERGED
+    assert res[1]["status"] == skr.SKR_CONVERGED and res[1]["iters"] == 0 and not xs[1].any()
+    assert res[2]["status"] == skr.SKR_NONFINITE and not xs[2].any()
+    assert res[3]["status"] == skr.SKR_CONVERGED          # recycles the space of system 0
+    ref = oracle.solve_sequence([s.A, s.A], [s.b, s.b], None, 20, 6, 1e-8, 5000, basis_fp32=True)
+    assert abs(res[0]["iters"] - ref[0].iters) <= 1 and abs(res[3]["iters"] - ref[1].iters) <= 1
+    # maxit = 1
+    ops1, bs1, xs1 = upload_systems([s], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops1, bs1, xs1, None, m=20, k=6, rtol=1e-8, maxit=1, flags=M)
+    assert rc == skr.SKR_WARN_NOTCONVERGED and res[0]["status"] == skr.SKR_MAXIT and res[0]["iters"] == 1
+    r1 = oracle.gcrodr(s.A, s.b, None, 20, 6, 1e-8, 1, basis_fp32=True)
+    assert abs(res[0]["relres_true"] - r1.relres_true) <= 1e-6 * r1.relres_true
+    # identity: the first step breaks down, x = b up to the FP32 rounding of the stored basis vector
+    ident = types.SimpleNamespace(A=sp.identity(n, format="csr"), b=s.b, n=n, N_g=s.N_g)
+    ops2, bs2, xs2 = upload_systems([ident], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops2, bs2, xs2, None, m=20, k=6, rtol=1e-8, maxit=100, flags=M)
+    assert res[0]["status"] in (skr.SKR_BREAKDOWN, skr.SKR_CONVERGED)
+    assert res[0]["relres_true"] <= 1e-8
+    np.testing.assert_allclose(xs2[0].cpu().numpy(), s.b, rtol=1e-7)
+    # the same right-hand side twice: the second system starts from a recycle space whose projection
+    # already gives a small residual; the result still meets the FP64 tolerance
+    ops3, bs3, xs3 = upload_systems([s, s], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops3, bs3, xs3, None, m=20, k=6, rtol=1e-8, maxit=5000, flags=M)
+    for r, x in zip(res, xs3):
+        xh = x.cpu().numpy()
+        assert r["status"] == skr.SKR_CONVERGED
+        assert np.linalg.norm(s.b - s.A @ xh) <= 1e-8 * np.linalg.norm(s.b) * (1 + 1e-9)
