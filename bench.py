@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the measured capacity")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-chains", type=int, default=8)
+    ap.add_argument("--serve-chain-cap", type=int, default=0,
+                    help="systems a chain takes before a new chain of the same shape is started (0: no limit)")
     ap.add_argument("--advdiff", action="store_true",
                     help="time-stepping mode: unsteady advection-diffusion, --chains chains of --steps-per-chain "
                          "backward-Euler steps on a --grid^2 mesh, each chain solved as a chain of the serving runtime")
@@ -145,7 +147,8 @@ def serve_bench(a):
 
     def run(gaps):
         ctx = skr.skr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
-        skr.skr_serve_start(ctx, max_chains=a.serve_chains, workers=a.serve_workers)
+        skr.skr_serve_start(ctx, max_chains=a.serve_chains, workers=a.serve_workers,
+                            max_chain_systems=a.serve_chain_cap)
         sub, done, res, tickets = {}, {}, {}, {}
         lock = threading.Lock()
         finished = threading.Event()
@@ -211,7 +214,8 @@ def serve_bench(a):
         "config": {"workload": f"darcy2d-serving-{'-'.join(map(str, sizes))}-{len(order)}sys-gcrodr({a.m},{a.k})"
                                + ("-fp32basis" if a.mixed else ""),
                    "sizes": sizes, "systems": len(order), "m": a.m, "k": a.k, "rtol": a.rtol,
-                   "workers": a.serve_workers, "max_chains": a.serve_chains, "load": a.serve_load},
+                   "workers": a.serve_workers, "max_chains": a.serve_chains,
+                   "max_chain_systems": a.serve_chain_cap, "load": a.serve_load},
         "capacity_systems_per_s": round(capacity, 3), "arrival_rate": round(lam, 3),
         "latency_ms": {"p50": round(float(np.percentile(L, 50)), 1), "p99": round(float(np.percentile(L, 99)), 1),
                        "max": round(float(L.max()), 1)},

@@ -205,7 +205,11 @@ int skr_profile_reset(skr_ctx* ctx);
  * squared distance of the parameter vectors, as in skr_sort; ties to the lower chain id), among the
  * chains of the same shape (n, p, m, k and SKR_FLAG_MIXED). It starts a new chain when no chain of
  * its shape exists, or when d2 > split_d2_rel * ||params||^2 and a chain can be added without
- * retiring one. Each chain
+ * retiring one. With max_chain_systems > 0 a chain that has taken that many systems is full: only
+ * chains that are not full are candidates, and when all of a shape are full the system starts a
+ * new chain if one can be added without retiring one (else it joins the nearest full chain) - the
+ * online form of cutting a sorted sequence into contiguous batches, one per worker (App. E), so
+ * that one shape's systems spread over several chains and workers. Each chain
  * owns a HIP stream, a workspace and its recycle space, which stays resident in device memory
  * between systems; its systems are solved in admission order, each starting from the recycle space
  * the previous one left (Alg. 2), so a result depends only on the chain's history, never on timing
@@ -223,6 +227,8 @@ typedef struct {
     int32_t workers;        /* host threads driving chains concurrently (>= 1)                  */
     uint64_t arena_bytes;   /* device bytes all chain workspaces may take together, 0 = no limit */
     double split_d2_rel;    /* start a new chain above this relative d2 (INFINITY: never)        */
+    int32_t max_chain_systems;  /* systems a chain takes before it is full (0: no limit)          */
+    int32_t pad0;
 } skr_serve_opts;
 
 typedef struct {

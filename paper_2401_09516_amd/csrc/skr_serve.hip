@@ -209,9 +209,18 @@ int new_chain(Server* S, const Job& j, Chain** out) {
 int assign(Server* S, uint64_t t, const double* params, bool& assigned) {
     assigned = false;
     Job& j = S->jobs[t];
-    std::vector<Chain*> cand;
+    // candidates: the chains of the job's shape that are not full (all of them when every one is
+    // full and no chain can be added, so the job still joins the nearest)
+    const size_t bytes = chain_bytes(j.op.n, j.opts.m, j.opts.k, j.p);
+    const int cap = S->o.max_chain_systems;
+    std::vector<Chain*> cand, full;
     for (auto& kv : S->chains)
-        if (same_shape(kv.second, j)) cand.push_back(kv.second);
+        if (same_shape(kv.second, j)) (cap > 0 && kv.second->admitted >= cap ? full : cand).push_back(kv.second);
+    bool all_full = cand.empty() && !full.empty();
+    if (all_full && !can_add(S, bytes)) {
+        cand.swap(full);
+        all_full = false;
+    }
     std::vector<double> d2;
     int rc = distances(S, params, j.p, cand, d2);
     if (rc) return rc;
@@ -225,10 +234,12 @@ int assign(Server* S, uint64_t t, const double* params, bool& assigned) {
     if (!best && !cand.empty()) best = cand[0];       // no finite distance: the lowest chain id
     // A shape without a chain gets one, retiring idle chains if needed, or waits (deferred). A shape
     // with chains splits off a new one only when there is room without retiring anything: which
-    // chains are idle depends on timing, and the choice must not.
-    const size_t bytes = chain_bytes(j.op.n, j.opts.m, j.opts.k, j.p);
+    // chains are idle depends on timing, and the choice must not. So does a shape whose chains are
+    // all full.
     Chain* target = best;
-    if (!best) {
+    if (all_full) {
+        if ((rc = new_chain(S, j, &target))) return rc;
+    } else if (!best) {
         make_room(S, bytes);
         if (!can_add(S, bytes)) return SKR_OK;       // deferred
         if ((rc = new_chain(S, j, &target))) return rc;
@@ -353,6 +364,7 @@ int skr_serve_start(skr_ctx* ctx, const skr_serve_opts* opts) {
     if (opts->max_chains < 1 || opts->workers < 1 || opts->workers > 64)
         return fail(SKR_EINVAL, "need max_chains >= 1 and 1 <= workers <= 64");
     if (!(opts->split_d2_rel >= 0.0)) return fail(SKR_EINVAL, "split_d2_rel must be >= 0 (INFINITY: never split)");
+    if (opts->max_chain_systems < 0) return fail(SKR_EINVAL, "max_chain_systems must be >= 0 (0: no limit)");
     HIPCHK(hipSetDevice(ctx->device));
     Server* S = new Server();
     S->owner = ctx;

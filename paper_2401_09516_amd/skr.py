@@ -78,7 +78,7 @@ class skr_profile(ctypes.Structure):
 
 class skr_serve_opts(ctypes.Structure):
     _fields_ = [("max_chains", ctypes.c_int32), ("workers", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64),
-                ("split_d2_rel", ctypes.c_double)]
+                ("split_d2_rel", ctypes.c_double), ("max_chain_systems", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 class skr_serve_stats(ctypes.Structure):
@@ -266,9 +266,10 @@ def skr_profile_reset(ctx: int) -> None:
 
 # ----------------------------------------------------------------------------------- serving
 def skr_serve_start(ctx: int, max_chains: int = 8, workers: int = 4, arena_bytes: int = 0,
-                    split_d2_rel: float = float("inf")) -> None:
+                    split_d2_rel: float = float("inf"), max_chain_systems: int = 0) -> None:
     """Start the serving runtime on ``ctx`` (skr.h: nearest-chain admission, one stream per chain)."""
-    o = skr_serve_opts(max_chains=max_chains, workers=workers, arena_bytes=arena_bytes, split_d2_rel=split_d2_rel)
+    o = skr_serve_opts(max_chains=max_chains, workers=workers, arena_bytes=arena_bytes, split_d2_rel=split_d2_rel,
+                       max_chain_systems=max_chain_systems)
     _check(load_library().skr_serve_start(ctx, ctypes.byref(o)))
 
 

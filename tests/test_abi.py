@@ -55,7 +55,7 @@ int main(void) {
   F(skr_profile, cycles); F(skr_profile, step_bytes);
   printf("skr_serve_opts %zu\nskr_serve_stats %zu\n", sizeof(skr_serve_opts), sizeof(skr_serve_stats));
   F(skr_serve_opts, max_chains); F(skr_serve_opts, workers); F(skr_serve_opts, arena_bytes);
-  F(skr_serve_opts, split_d2_rel);
+  F(skr_serve_opts, split_d2_rel); F(skr_serve_opts, max_chain_systems); F(skr_serve_opts, pad0);
   F(skr_serve_stats, submitted); F(skr_serve_stats, completed); F(skr_serve_stats, chains_live);
   F(skr_serve_stats, chains_created); F(skr_serve_stats, chains_retired); F(skr_serve_stats, deferred);
   F(skr_serve_stats, bytes_in_use);

@@ -5,7 +5,8 @@ Bars (written in the tests):
   over the same systems in submission order (the same kernels, the same recycle hand-over);
 * the chain each system joins, and its position there, equal the rule recomputed on the CPU from
   the oracle's exact squared distances (nearest chain of the same shape by d2, ties to the lower
-  id, a new chain above split_d2_rel * ||params||^2);
+  id, a new chain above split_d2_rel * ||params||^2 or when every chain of the shape holds
+  max_chain_systems systems);
 * every chain's results meet the oracle's for the same systems in chain order, to the parity bars
   of the sequence solver;
 * results are bit-identical with one worker and with four (the interleaving of chains is
@@ -53,10 +54,11 @@ def _upload(torch, systems, kind="csr"):
 
 
 def _serve(torch, skr, systems, m=20, k=6, rtol=1e-8, flags=None, workers=4, max_chains=8,
-           split=math.inf, kind="csr"):
+           split=math.inf, kind="csr", cap=0):
     ctx = make_ctx(torch)
     try:
-        skr.skr_serve_start(ctx, max_chains=max_chains, workers=workers, split_d2_rel=split)
+        skr.skr_serve_start(ctx, max_chains=max_chains, workers=workers, split_d2_rel=split,
+                            max_chain_systems=cap)
         ops, bs, xs, params = _upload(torch, systems, kind)
         flags = flags or [0] * len(systems)
         tickets = [skr.skr_submit(ctx, ops[i], params[i], params[i].numel(), bs[i], xs[i], m=m, k=k, rtol=rtol,
@@ -72,12 +74,22 @@ def _serve(torch, skr, systems, m=20, k=6, rtol=1e-8, flags=None, workers=4, max
     return res, xh, where, stats
 
 
-def _cpu_rule(systems, split=math.inf, max_chains=8, shape=lambda s: s.n):
+def _cpu_rule(systems, split=math.inf, max_chains=8, shape=lambda s: s.n, cap=0):
     """The admission rule of skr.h on the CPU with the oracle's exact d2 (no retirement needed)."""
     tails, shapes, counts, out = [], [], [], []
     for s in systems:
         p = s.a.ravel()
-        cand = [c for c in range(len(tails)) if shapes[c] == shape(s)]
+        same = [c for c in range(len(tails)) if shapes[c] == shape(s)]
+        cand = [c for c in same if not (cap > 0 and counts[c] >= cap)]
+        if same and not cand:                       # every chain of the shape is full
+            if len(tails) < max_chains:
+                tails.append(p)
+                shapes.append(shape(s))
+                counts.append(0)
+                out.append((len(tails) - 1, 0))
+                counts[-1] = 1
+                continue
+            cand = same
         best, bd = None, math.inf
         for c in cand:
             d = oracle.sq_distance(p, tails[c])
@@ -115,13 +127,17 @@ def test_serve_one_chain_equals_solve_sequence(env):
         skr.skr_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("split", [math.inf, 0.02])
-def test_serve_assignment_and_parity(env, split):
+@pytest.mark.parametrize("split,cap,max_chains", [(math.inf, 0, 8), (0.02, 0, 8), (math.inf, 3, 8),
+                                                  (math.inf, 3, 5)])
+def test_serve_assignment_and_parity(env, split, cap, max_chains):
     torch, skr = env
-    log(f"[serve] two sizes interleaved, split {split}")
+    log(f"[serve] two sizes interleaved, split {split}, chain cap {cap}, max_chains {max_chains}")
     systems = _stream()
-    res, xh, where, stats = _serve(torch, skr, systems, split=split)
-    want = _cpu_rule(systems, split=split)
+    res, xh, where, stats = _serve(torch, skr, systems, split=split, cap=cap, max_chains=max_chains)
+    want = _cpu_rule(systems, split=split, cap=cap, max_chains=max_chains)
+    if cap:
+        n_full = sum(1 for c in set(c for c, _ in want) if sum(1 for cc, _ in want if cc == c) > cap)
+        assert n_full == 0 or len({c for c, _ in want}) == max_chains     # over the cap only without room
     assert where == want
     assert stats["completed"] == len(systems) and stats["chains_created"] == len({c for c, _ in want})
     # per chain: the oracle's sequence solve over the chain's systems in chain order
