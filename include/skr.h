@@ -81,7 +81,7 @@ typedef struct {
     const double* az;       /* STENCIL7 only */
 } skr_op;
 
-/* Solver options. m: maximum subspace size per cycle (1..62); k: recycled vectors (0 = GMRES(m),
+/* Solver options. m: maximum subspace size per cycle (1..86); k: recycled vectors (0 = GMRES(m),
  * k < m, k <= 32); rtol: relative residual target; maxit: maximum Arnoldi steps per system;
  * flags: 0 or a combination of SKR_FLAG_PROFILE, SKR_FLAG_FOLD and SKR_FLAG_MIXED. */
 #define SKR_FLAG_PROFILE 1u   /* time every 16th Arnoldi step's kernels with hipEvents (see skr_profile_get) */

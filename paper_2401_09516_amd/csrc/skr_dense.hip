@@ -16,8 +16,8 @@
 
 namespace skr {
 
-constexpr int LDG = DMAX + 1;   // leading dimension of G and X/M in LDS
-constexpr int LDW = DMAX + 1;   // leading dimension of the eigenvector / Q_w / Qu work arrays
+constexpr int LDG = DS + 1;   // leading dimension of G and X/M in LDS
+constexpr int LDW = DS + 1;   // leading dimension of the eigenvector / Q_w / Qu work arrays
 
 __device__ __forceinline__ double wave_sum64(double x) { return wave_sum(x); }
 __device__ __forceinline__ double wave_max64(double x) { return wave_max(x); }
@@ -86,14 +86,15 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H, const double* __restrict__ Bm,
                                                    const double* __restrict__ gram, int kc, int jd_max, int k_target,
                                                    Coef* coef, DenseWork* dw, Ctrl* ctrl) {
-    __shared__ double G[LDG * DMAX];
-    __shared__ double X[LDG * DMAX];
-    __shared__ double rhs[DMAX + 1], gcs[DMAX], gsn[DMAX], Dk[KMAX], hv[DMAX + 1];
+    __shared__ double G[LDG * DS];
+    __shared__ double X[LDG * DS];
+    __shared__ double rhs[DS + 1], gcs[DS], gsn[DS], Dk[KMAX], hv[DS + 1];
     const int t = threadIdx.x;
     const int jd = ctrl->j_done;
     const double beta = ctrl->beta;
     const int d = kc + jd;
     const int nr = kc + 1;
+    if (d > DSM) return;       // the row-looped kernels take it
 
     // ---- D_k, G, X = W-hat^T V-hat (structured), right-hand side W-hat^T r. Global inputs are
     //      staged with eight loads in flight per lane.
@@ -232,22 +233,22 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 // its norm). Otherwise, or when an eigenvector comes out dependent on the others (a cluster) or
 // not finite, M is handed to the general stage.
 constexpr int DT = 256;         // threads of the symmetric stage
-constexpr int LDS_ = DMAX + 1;  // leading dimension of S and V in LDS
+constexpr int LDS_ = DS + 1;  // leading dimension of S and V in LDS
 constexpr int NSHIFT = 8;       // multisection: shifts per eigenvalue interval and round
 
 __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
                                                   Ctrl* ctrl) {
     if (dw->mode != DW_PENDING) return;
-    __shared__ double S[LDS_ * DMAX];
-    __shared__ double V[LDS_ * DMAX];
-    __shared__ double R[LDS_ * DMAX];
-    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX], Rd[DMAX];
+    __shared__ double S[LDS_ * DS];
+    __shared__ double V[LDS_ * DS];
+    __shared__ double R[LDS_ * DS];
+    __shared__ double gcs[DS], gsn[DS], Dk[KMAX], Rd[DS];
     __shared__ double red[DT / 64], red2[DT / 64];
-    __shared__ double ta[DMAX], tb[DMAX], tb2[DMAX], hb[DMAX], hv0[DMAX], hP[DMAX];
-    __shared__ double blo[DMAX], bhi[DMAX], lam[DMAX], lsel[KMAX], hsig[1], hkp[DT / 64];
-    __shared__ double bsh[DMAX * NSHIFT];
+    __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS], hv0[DS], hP[DS];
+    __shared__ double blo[DS], bhi[DS], lam[DS], lsel[KMAX], hsig[1], hkp[DT / 64];
+    __shared__ double bsh[DS * NSHIFT];
     __shared__ double junk[DT];
-    __shared__ int bcnt[DMAX * NSHIFT];
+    __shared__ int bcnt[DS * NSHIFT];
     __shared__ int sel[KMAX], isel[KMAX];
     __shared__ int nsel_s, sym_s, need2_s, fail_s;
     const int t = threadIdx.x;
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
     // the second pass gives the eigenvector. D+ and D- live in V (columns of 32), z overwrites D+.
     // Quotients use v_rcp_f64 with two Newton steps.
     double* Fp = V;
-    double* Fm = V + DMAX * KMAX;
+    double* Fm = V + DS * KMAX;
     if (t < 64) {
         const int o = t >> 1, side = t & 1;
         const bool act = o < kn;
@@ -772,13 +773,13 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
 // basis Q_w of them, and the recycle-space coefficients Qu = R_G^{-1} Q_w, Qc = Q_G [Q_w; 0].
 __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     if (dw->mode != DW_GEN) return;
-    __shared__ double G[LDG * DMAX];
-    __shared__ double X[LDG * DMAX];
-    __shared__ double Z[DMAX * DMAX];
+    __shared__ double G[LDG * DS];
+    __shared__ double X[LDG * DS];
+    __shared__ double Z[DS * DS];
     __shared__ double Wv[LDW * KMAX];
     __shared__ double Uq[LDW * KMAX];
-    __shared__ double gcs[DMAX], gsn[DMAX], Dk[KMAX], wr[DMAX], wi[DMAX], hv[DMAX + 1];
-    __shared__ int taken[DMAX], sel_pos[KMAX], sel_cplx[KMAX], sel_col[KMAX];
+    __shared__ double gcs[DS], gsn[DS], Dk[KMAX], wr[DS], wi[DS], hv[DS + 1];
+    __shared__ int taken[DS], sel_pos[KMAX], sel_cplx[KMAX], sel_col[KMAX];
     const int t = threadIdx.x;
     const int d = dw->d, kc = dw->kc;
     const double eps = 2.220446049250313e-16;
@@ -789,7 +790,7 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
     __syncthreads();
     // Z = I
     for (int c = 0; c < d; ++c)
-        if (t < d) Z[t + c * DMAX] = (t == c) ? 1.0 : 0.0;
+        if (t < d) Z[t + c * DS] = (t == c) ? 1.0 : 0.0;
     __syncthreads();
 
     // ---- Householder reduction of M to upper Hessenberg form, Z accumulates the reflectors
@@ -814,13 +815,13 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
             double s = 0.0, sz = 0.0;
             for (int q = c + 1; q < d; ++q) {
                 s = fma(X[t + q * LDG], hv[q], s);
-                sz = fma(Z[t + q * DMAX], hv[q], sz);
+                sz = fma(Z[t + q * DS], hv[q], sz);
             }
             s *= tau;
             sz *= tau;
             for (int q = c + 1; q < d; ++q) {
                 X[t + q * LDG] = fma(-s, hv[q], X[t + q * LDG]);
-                Z[t + q * DMAX] = fma(-sz, hv[q], Z[t + q * DMAX]);
+                Z[t + q * DS] = fma(-sz, hv[q], Z[t + q * DS]);
             }
         }
         __syncthreads();
@@ -876,9 +877,9 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
                     X[t + q * LDG] = -sn * c0 + cs * c1;
                 }
                 if (t < d) {
-                    const double z0 = Z[t + p * DMAX], z1 = Z[t + q * DMAX];
-                    Z[t + p * DMAX] = cs * z0 + sn * z1;
-                    Z[t + q * DMAX] = -sn * z0 + cs * z1;
+                    const double z0 = Z[t + p * DS], z1 = Z[t + q * DS];
+                    Z[t + p * DS] = cs * z0 + sn * z1;
+                    Z[t + q * DS] = -sn * z0 + cs * z1;
                 }
                 __syncthreads();
                 if (t == 0) {
@@ -943,11 +944,11 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
                     X[t + (kk + 2) * LDG] = c - s * v2;
                 }
                 if (t < d) {
-                    const double a = Z[t + kk * DMAX], b = Z[t + (kk + 1) * DMAX], c = Z[t + (kk + 2) * DMAX];
+                    const double a = Z[t + kk * DS], b = Z[t + (kk + 1) * DS], c = Z[t + (kk + 2) * DS];
                     const double s = tau * (a + v1 * b + v2 * c);
-                    Z[t + kk * DMAX] = a - s;
-                    Z[t + (kk + 1) * DMAX] = b - s * v1;
-                    Z[t + (kk + 2) * DMAX] = c - s * v2;
+                    Z[t + kk * DS] = a - s;
+                    Z[t + (kk + 1) * DS] = b - s * v1;
+                    Z[t + (kk + 2) * DS] = c - s * v2;
                 }
                 __syncthreads();
             }
@@ -983,10 +984,10 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
                     X[t + (kk + 1) * LDG] = b - s * v1;
                 }
                 if (t < d) {
-                    const double a = Z[t + kk * DMAX], b = Z[t + (kk + 1) * DMAX];
+                    const double a = Z[t + kk * DS], b = Z[t + (kk + 1) * DS];
                     const double s = tau * (a + v1 * b);
-                    Z[t + kk * DMAX] = a - s;
-                    Z[t + (kk + 1) * DMAX] = b - s * v1;
+                    Z[t + kk * DS] = a - s;
+                    Z[t + (kk + 1) * DS] = b - s * v1;
                 }
                 __syncthreads();
             }
@@ -1126,7 +1127,7 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
     for (int o = 0; o < ncols; ++o) {
         if (t < d) {
             double s = 0.0;
-            for (int c = 0; c < d; ++c) s = fma(Z[t + c * DMAX], Wv[c + o * LDW], s);
+            for (int c = 0; c < d; ++c) s = fma(Z[t + c * DS], Wv[c + o * LDW], s);
             Uq[t + o * LDW] = s;
         }
     }
@@ -1170,6 +1171,569 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
         }
         if (kc < d || d == 0) coef->Qc[kc + t * LDQC] = carry;
         for (int c = 0; c < kc; ++c) coef->Qc[c + t * LDQC] = Wv[c + t * LDW];
+    }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Cycle end for DSM < d <= MMAX: the same computation by one wavefront whose row and column loops
+// are strided over its 64 lanes (rows t and t + 64). The eigenproblem always takes the general
+// route (Hessenberg form, Francis double-shift QR, back-substitution), which serves a symmetric M
+// as well. LDS holds three d x d regions, each reused across the phases of the general stage.
+// ---------------------------------------------------------------------------------------------
+constexpr int LDP = MMAX + 2;   // leading dimension of G and X ((d + 1) x d) in the first stage
+constexpr int LDL = MMAX + 1;   // leading dimension of the d x d arrays of the general stage
+
+__global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ H, const double* __restrict__ Bm,
+                                                     const double* __restrict__ gram, int kc, int jd_max,
+                                                     int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    __shared__ double G[LDP * MMAX];
+    __shared__ double X[LDP * MMAX];
+    __shared__ double rhs[MMAX + 2], gcs[MMAX + 1], gsn[MMAX + 1], Dk[KMAX], hv[MMAX + 2], yv[MMAX + 1];
+    const int t = threadIdx.x;
+    const int jd = ctrl->j_done;
+    const double beta = ctrl->beta;
+    const int d = kc + jd;
+    const int nr = kc + 1;
+    if (d <= DSM) return;       // the one-row-per-lane kernels take it
+
+    // ---- D_k, G = [[D_k, B], [0, Hbar]], X = W-hat^T V-hat, right-hand side W-hat^T r
+    if (t < kc) Dk[t] = 1.0 / sqrt(gram[(kc + jd_max + 1 + t) * nr + t]);
+    for (int c = 0; c < d; ++c)
+        for (int r = t; r <= d; r += 64) {
+            G[r + c * LDP] = 0.0;
+            X[r + c * LDP] = (c >= kc && r == c) ? 1.0 : 0.0;   // V_{jd+1}^T V_jd = I_{jd+1,jd}, C^T V = 0
+        }
+    __syncthreads();
+    for (int e = t; e < (jd + 1) * jd; e += 64) {
+        const int c = e / (jd + 1), r = e - c * (jd + 1);
+        if (r <= c + 1) G[kc + r + (kc + c) * LDP] = H[r + c * LDH];
+    }
+    for (int e = t; e < kc * jd; e += 64) {
+        const int c = e / kc, r = e - c * kc;
+        G[r + (kc + c) * LDP] = Bm[r + c * KMAX];
+    }
+    __syncthreads();
+    for (int e = t; e < (d + 1) * kc; e += 64) {
+        const int c = e / (d + 1), r = e - c * (d + 1);
+        X[r + c * LDP] = gram[r * nr + c] * Dk[c];
+    }
+    if (t < kc) G[t + t * LDP] = Dk[t];
+    for (int r = t; r <= d; r += 64) rhs[r] = (r < kc) ? gram[r * nr + kc] : (r == kc ? beta : 0.0);
+    __syncthreads();
+
+    // ---- Givens QR of G (the Hessenberg block)
+    for (int c = kc; c < d; ++c) {
+        const double a = G[c + c * LDP], b = G[c + 1 + c * LDP];
+        const double rho = hypot(a, b);
+        const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? b / rho : 0.0;
+        __syncthreads();
+        for (int q = t; q < d; q += 64) {
+            if (q >= c) {
+                const double g0 = G[c + q * LDP], g1 = G[c + 1 + q * LDP];
+                G[c + q * LDP] = cs * g0 + sn * g1;
+                G[c + 1 + q * LDP] = -sn * g0 + cs * g1;
+            }
+            const double x0 = X[c + q * LDP], x1 = X[c + 1 + q * LDP];
+            X[c + q * LDP] = cs * x0 + sn * x1;
+            X[c + 1 + q * LDP] = -sn * x0 + cs * x1;
+        }
+        if (t == 0) {
+            const double r0 = rhs[c], r1 = rhs[c + 1];
+            rhs[c] = cs * r0 + sn * r1;
+            rhs[c + 1] = -sn * r0 + cs * r1;
+            gcs[c] = cs;
+            gsn[c] = sn;
+        }
+        __syncthreads();
+        if (t == 0) G[c + 1 + c * LDP] = 0.0;
+        __syncthreads();
+    }
+
+    // ---- least squares: y = R_G^{-1} rhs[0:d] (column-oriented back-substitution)
+    for (int r = t; r < d; r += 64) yv[r] = rhs[r];
+    __syncthreads();
+    for (int c = d - 1; c >= 0; --c) {
+        const double yc = yv[c] / G[c + c * LDP];
+        __syncthreads();
+        if (t == 0) yv[c] = yc;
+        for (int r = t; r < c; r += 64) yv[r] = fma(-G[r + c * LDP], yc, yv[r]);
+        __syncthreads();
+    }
+    for (int r = t; r < d; r += 64) {
+        if (r < kc) coef->yU[r] = Dk[r] * yv[r];
+        else coef->yV[r - kc] = yv[r];
+    }
+    // G y = Q_G [rhs[0:d]; 0]
+    for (int r = t; r <= d; r += 64) hv[r] = (r < d) ? rhs[r] : 0.0;
+    __syncthreads();
+    if (t == 0) {
+        for (int c = d - 1; c >= kc; --c) {
+            const double a = hv[c], b = hv[c + 1];
+            hv[c] = gcs[c] * a - gsn[c] * b;
+            hv[c + 1] = gsn[c] * a + gcs[c] * b;
+        }
+    }
+    __syncthreads();
+    for (int r = t; r <= d; r += 64) {
+        if (r < kc) coef->rC[r] = hv[r];
+        else coef->rV[r - kc] = hv[r];
+    }
+
+    const bool recycle = k_target > 0 && (kc > 0 || jd > k_target);
+    if (!recycle) {
+        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; dw->mode = DW_NONE; }
+        return;
+    }
+    // hand over R_G (d x d, upper), X'' (d x d), rotations and D_k
+    for (int c = 0; c < d; ++c)
+        for (int r = t; r < d; r += 64) {
+            dw->R[r + c * DMAX] = (r <= c) ? G[r + c * LDP] : 0.0;
+            dw->X[r + c * DMAX] = X[r + c * LDP];
+        }
+    for (int r = t; r < d; r += 64) { dw->gcs[r] = gcs[r]; dw->gsn[r] = gsn[r]; }
+    if (t < kc) dw->Dk[t] = Dk[t];
+    if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_GEN_L; }
+}
+
+// General stage for d > DSM. LDS regions: XR (X'', then M, then the Schur form T, then the
+// back-transformed vectors and the back-substitution scratch), ZR (R_G, then the Schur vectors,
+// then R_G again), WV (the selected eigenvectors in the Schur basis, then Q_w).
+__global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    if (dw->mode != DW_GEN_L) return;
+    __shared__ double XR[LDL * MMAX];
+    __shared__ double ZR[LDL * MMAX];
+    __shared__ double WV[LDL * KMAX];
+    __shared__ double gcs[MMAX], gsn[MMAX], Dk[KMAX], wr[MMAX], wi[MMAX], hv[MMAX + 1], Rd[MMAX];
+    __shared__ int taken[MMAX], sel_pos[KMAX], sel_cplx[KMAX], sel_col[KMAX];
+    double* X = XR;
+    double* Z = ZR;
+    double* Wv = WV;
+    double* Uq = XR;
+    const int t = threadIdx.x;
+    const int d = dw->d, kc = dw->kc;
+    const double eps = 2.220446049250313e-16;
+    stage_block(X, LDL, dw->X, DMAX, d, d, t, 64);
+    stage_block(Z, LDL, dw->R, DMAX, d, d, t, 64);
+    for (int r = t; r < d; r += 64) { gcs[r] = dw->gcs[r]; gsn[r] = dw->gsn[r]; }
+    if (t < kc) Dk[t] = dw->Dk[t];
+    __syncthreads();
+
+    // ---- M = X'' R_G^{-1}: row r solves m R = x'' (right-looking over the columns)
+    for (int r = t; r < d; r += 64) Rd[r] = 1.0 / Z[r + r * LDL];
+    __syncthreads();
+    for (int r = t; r < d; r += 64)
+        for (int c = 0; c < d; ++c) {
+            const double mc = X[r + c * LDL] * Rd[c];
+            X[r + c * LDL] = mc;
+            for (int q = c + 1; q < d; ++q) X[r + q * LDL] = fma(-mc, Z[c + q * LDL], X[r + q * LDL]);
+        }
+    __syncthreads();
+    // Z = I
+    for (int c = 0; c < d; ++c)
+        for (int r = t; r < d; r += 64) Z[r + c * LDL] = (r == c) ? 1.0 : 0.0;
+    __syncthreads();
+
+    // ---- Householder reduction of M to upper Hessenberg form, Z accumulates the reflectors
+    for (int c = 0; c + 2 < d; ++c) {
+        double sp = 0.0;
+        for (int r = t; r < d; r += 64)
+            if (r >= c + 2) sp = fma(X[r + c * LDL], X[r + c * LDL], sp);
+        const double sig = wave_sum64(sp);
+        const double x0 = X[c + 1 + c * LDL];
+        if (sig == 0.0) continue;
+        const double mu = sqrt(x0 * x0 + sig);
+        const double v0 = (x0 <= 0.0) ? x0 - mu : -sig / (x0 + mu);
+        const double tau = 2.0 * v0 * v0 / (sig + v0 * v0);
+        for (int r = t; r < d; r += 64)
+            if (r >= c + 1) hv[r] = (r == c + 1) ? 1.0 : X[r + c * LDL] / v0;
+        __syncthreads();
+        for (int q = t; q < d; q += 64)
+            if (q >= c) {
+                double s = 0.0;
+                for (int r = c + 1; r < d; ++r) s = fma(hv[r], X[r + q * LDL], s);
+                s *= tau;
+                for (int r = c + 1; r < d; ++r) X[r + q * LDL] = fma(-s, hv[r], X[r + q * LDL]);
+            }
+        __syncthreads();
+        for (int r = t; r < d; r += 64) {
+            double s = 0.0, sz = 0.0;
+            for (int q = c + 1; q < d; ++q) {
+                s = fma(X[r + q * LDL], hv[q], s);
+                sz = fma(Z[r + q * LDL], hv[q], sz);
+            }
+            s *= tau;
+            sz *= tau;
+            for (int q = c + 1; q < d; ++q) {
+                X[r + q * LDL] = fma(-s, hv[q], X[r + q * LDL]);
+                Z[r + q * LDL] = fma(-sz, hv[q], Z[r + q * LDL]);
+            }
+        }
+        __syncthreads();
+        for (int r = t; r < d; r += 64)
+            if (r >= c + 2) X[r + c * LDL] = 0.0;
+        if (t == 0) X[c + 1 + c * LDL] = mu;
+        __syncthreads();
+    }
+
+    // ---- Francis double-shift QR to real Schur form (T in X, Z accumulated)
+    double tn = 0.0;
+    for (int r = t; r < d; r += 64)
+        for (int c = 0; c < d; ++c) tn = fmax(tn, fabs(X[r + c * LDL]));
+    const double tnorm = wave_max64(tn);
+    int hi = d - 1, its = 0, total = 0;
+    bool failed = false;
+    while (hi >= 0) {
+        // l: the largest row index in 1..hi whose subdiagonal entry is negligible (0 if none)
+        bool small0 = false, small1 = false;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int r = t + 64 * half;
+            bool sm = false;
+            if (r >= 1 && r <= hi) {
+                double sc = fabs(X[r - 1 + (r - 1) * LDL]) + fabs(X[r + r * LDL]);
+                if (sc == 0.0) sc = tnorm;
+                sm = fabs(X[r + (r - 1) * LDL]) <= eps * sc;
+            }
+            if (half == 0) small0 = sm;
+            else small1 = sm;
+        }
+        const unsigned long long m0 = __ballot(small0), m1 = __ballot(small1);
+        const int l = m1 ? 64 + 63 - __clzll(m1) : (m0 ? 63 - __clzll(m0) : 0);
+        __syncthreads();
+        if (l > 0 && t == 0) X[l + (l - 1) * LDL] = 0.0;
+        __syncthreads();
+        if (l == hi) {
+            if (t == 0) { wr[hi] = X[hi + hi * LDL]; wi[hi] = 0.0; }
+            hi -= 1;
+            its = 0;
+            __syncthreads();
+            continue;
+        }
+        if (l == hi - 1) {
+            const int p = hi - 1, q = hi;
+            const double a = X[p + p * LDL], b = X[p + q * LDL], c = X[q + p * LDL], dd = X[q + q * LDL];
+            const double pp = 0.5 * (a - dd), bc = b * c, disc = pp * pp + bc;
+            if (disc >= 0.0) {
+                const double zz = pp + copysign(sqrt(disc), pp);
+                const double rho = hypot(zz, c);
+                const double cs = rho > 0.0 ? zz / rho : 1.0, sn = rho > 0.0 ? c / rho : 0.0;
+                __syncthreads();
+                for (int e = t; e < d; e += 64)
+                    if (e >= p) {
+                        const double r0 = X[p + e * LDL], r1 = X[q + e * LDL];
+                        X[p + e * LDL] = cs * r0 + sn * r1;
+                        X[q + e * LDL] = -sn * r0 + cs * r1;
+                    }
+                __syncthreads();
+                for (int e = t; e <= q; e += 64) {
+                    const double c0 = X[e + p * LDL], c1 = X[e + q * LDL];
+                    X[e + p * LDL] = cs * c0 + sn * c1;
+                    X[e + q * LDL] = -sn * c0 + cs * c1;
+                }
+                for (int e = t; e < d; e += 64) {
+                    const double z0 = Z[e + p * LDL], z1 = Z[e + q * LDL];
+                    Z[e + p * LDL] = cs * z0 + sn * z1;
+                    Z[e + q * LDL] = -sn * z0 + cs * z1;
+                }
+                __syncthreads();
+                if (t == 0) {
+                    X[q + p * LDL] = 0.0;
+                    wr[p] = X[p + p * LDL];
+                    wr[q] = X[q + q * LDL];
+                    wi[p] = 0.0;
+                    wi[q] = 0.0;
+                }
+            } else {
+                if (t == 0) {
+                    wr[p] = wr[q] = dd + pp;
+                    wi[p] = sqrt(-disc);
+                    wi[q] = -wi[p];
+                }
+            }
+            hi -= 2;
+            its = 0;
+            __syncthreads();
+            continue;
+        }
+        if (total >= 30 * d) { failed = true; break; }
+        ++its;
+        ++total;
+        double h11, h12, h21, h22;
+        if (its == 10) {
+            const double s = fabs(X[l + 1 + l * LDL]) + fabs(X[l + 2 + (l + 1) * LDL]);
+            h11 = 0.75 * s + X[l + l * LDL]; h12 = -0.4375 * s; h21 = s; h22 = h11;
+        } else if (its == 20) {
+            const double s = fabs(X[hi + (hi - 1) * LDL]) + fabs(X[hi - 1 + (hi - 2) * LDL]);
+            h11 = 0.75 * s + X[hi + hi * LDL]; h12 = -0.4375 * s; h21 = s; h22 = h11;
+        } else {
+            h11 = X[hi - 1 + (hi - 1) * LDL]; h12 = X[hi - 1 + hi * LDL];
+            h21 = X[hi + (hi - 1) * LDL]; h22 = X[hi + hi * LDL];
+        }
+        const double str = h11 + h22, sdet = h11 * h22 - h12 * h21;
+        const double a00 = X[l + l * LDL], a01 = X[l + (l + 1) * LDL];
+        const double a10 = X[l + 1 + l * LDL], a11 = X[l + 1 + (l + 1) * LDL], a21 = X[l + 2 + (l + 1) * LDL];
+        double px = a00 * a00 + a01 * a10 - str * a00 + sdet;
+        double py = a10 * (a00 + a11 - str);
+        double pz = a10 * a21;
+        for (int kk = l; kk <= hi - 2; ++kk) {
+            double v1, v2, tau, alpha;
+            house3(px, py, pz, v1, v2, tau, alpha);
+            __syncthreads();
+            if (tau != 0.0) {
+                const int c0 = (kk > l) ? kk - 1 : l;
+                for (int e = t; e < d; e += 64)
+                    if (e >= c0) {
+                        const double a = X[kk + e * LDL], b = X[kk + 1 + e * LDL], c = X[kk + 2 + e * LDL];
+                        const double s = tau * (a + v1 * b + v2 * c);
+                        X[kk + e * LDL] = a - s;
+                        X[kk + 1 + e * LDL] = b - s * v1;
+                        X[kk + 2 + e * LDL] = c - s * v2;
+                    }
+                __syncthreads();
+                const int r1 = min(kk + 3, hi);
+                for (int e = t; e <= r1; e += 64) {
+                    const double a = X[e + kk * LDL], b = X[e + (kk + 1) * LDL], c = X[e + (kk + 2) * LDL];
+                    const double s = tau * (a + v1 * b + v2 * c);
+                    X[e + kk * LDL] = a - s;
+                    X[e + (kk + 1) * LDL] = b - s * v1;
+                    X[e + (kk + 2) * LDL] = c - s * v2;
+                }
+                for (int e = t; e < d; e += 64) {
+                    const double a = Z[e + kk * LDL], b = Z[e + (kk + 1) * LDL], c = Z[e + (kk + 2) * LDL];
+                    const double s = tau * (a + v1 * b + v2 * c);
+                    Z[e + kk * LDL] = a - s;
+                    Z[e + (kk + 1) * LDL] = b - s * v1;
+                    Z[e + (kk + 2) * LDL] = c - s * v2;
+                }
+                __syncthreads();
+            }
+            if (kk > l && t == 0) {
+                X[kk + (kk - 1) * LDL] = alpha;
+                X[kk + 1 + (kk - 1) * LDL] = 0.0;
+                X[kk + 2 + (kk - 1) * LDL] = 0.0;
+            }
+            __syncthreads();
+            px = X[kk + 1 + kk * LDL];
+            py = X[kk + 2 + kk * LDL];
+            pz = (kk < hi - 2) ? X[kk + 3 + kk * LDL] : 0.0;
+        }
+        // closing 2-element reflector on rows/columns hi-1, hi
+        {
+            const int kk = hi - 1;
+            double v1, v2, tau, alpha;
+            house3(px, py, 0.0, v1, v2, tau, alpha);
+            __syncthreads();
+            if (tau != 0.0) {
+                const int c0 = kk - 1;
+                for (int e = t; e < d; e += 64)
+                    if (e >= c0) {
+                        const double a = X[kk + e * LDL], b = X[kk + 1 + e * LDL];
+                        const double s = tau * (a + v1 * b);
+                        X[kk + e * LDL] = a - s;
+                        X[kk + 1 + e * LDL] = b - s * v1;
+                    }
+                __syncthreads();
+                for (int e = t; e <= hi; e += 64) {
+                    const double a = X[e + kk * LDL], b = X[e + (kk + 1) * LDL];
+                    const double s = tau * (a + v1 * b);
+                    X[e + kk * LDL] = a - s;
+                    X[e + (kk + 1) * LDL] = b - s * v1;
+                }
+                for (int e = t; e < d; e += 64) {
+                    const double a = Z[e + kk * LDL], b = Z[e + (kk + 1) * LDL];
+                    const double s = tau * (a + v1 * b);
+                    Z[e + kk * LDL] = a - s;
+                    Z[e + (kk + 1) * LDL] = b - s * v1;
+                }
+                __syncthreads();
+            }
+            if (t == 0) {
+                X[kk + (kk - 1) * LDL] = alpha;
+                X[kk + 1 + (kk - 1) * LDL] = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    if (failed) {
+        // keep the current recycle space: C_new = C, U_new = U
+        const int kn = kc;
+        for (int o = 0; o < kn; ++o)
+            for (int r = t; r <= d; r += 64) {
+                coef->Qc[r + o * LDQC] = (r == o) ? 1.0 : 0.0;
+                if (r < d) coef->Qu[r + o * LDQU] = (r == o) ? 1.0 : 0.0;
+            }
+        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; dw->mode = DW_DONE; }
+        return;
+    }
+
+    // ---- select the k eigenvalues of largest |mu| (smallest |theta|); a conjugate pair counts two.
+    // Each lane takes the better of its two rows (the lower index on a tie), then a butterfly picks
+    // the largest key, ties to the lower index.
+    for (int r = t; r < d; r += 64) taken[r] = 0;
+    __syncthreads();
+    int nsel = 0, ncols = 0;
+    while (ncols < k_target) {
+        double key = -1.0;
+        int idx = t;
+        for (int r = t; r < d; r += 64) {
+            if (!taken[r] && wi[r] >= 0.0) {
+                const double mag = hypot(wr[r], wi[r]);
+                if (mag > 0.0 && mag > key) { key = mag; idx = r; }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ok = __shfl_xor(key, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+        }
+        if (key <= 0.0) break;
+        const int cplx = wi[idx] > 0.0 ? 1 : 0;
+        if (ncols + 1 + cplx > k_target) break;
+        if (t == 0) {
+            sel_pos[nsel] = idx;
+            sel_cplx[nsel] = cplx;
+            sel_col[nsel] = ncols;
+            taken[idx] = 1;
+        }
+        __syncthreads();
+        ++nsel;
+        ncols += 1 + cplx;
+    }
+    __syncthreads();
+
+    // ---- eigenvectors of the quasi-triangular T by back-substitution (one lane per selection),
+    //      written to Wv in the Schur basis
+    const double smin = fmax(eps * tnorm, 1e-290);
+    if (t < nsel) {
+        const int p = sel_pos[t], col = sel_col[t];
+        double* xr = Wv + col * LDL;
+        if (!sel_cplx[t]) {
+            const double lam = wr[p];
+            for (int r = 0; r < d; ++r) xr[r] = 0.0;
+            xr[p] = 1.0;
+            int r = p - 1;
+            while (r >= 0) {
+                if (r > 0 && X[r + (r - 1) * LDL] != 0.0) {
+                    double s1 = 0.0, s2 = 0.0;
+                    for (int c = r + 1; c <= p; ++c) {
+                        s1 = fma(X[r - 1 + c * LDL], xr[c], s1);
+                        s2 = fma(X[r + c * LDL], xr[c], s2);
+                    }
+                    const double a = X[r - 1 + (r - 1) * LDL] - lam, b = X[r - 1 + r * LDL];
+                    const double c = X[r + (r - 1) * LDL], dd = X[r + r * LDL] - lam;
+                    double det = a * dd - b * c;
+                    if (fabs(det) < smin * smin) det = copysign(smin * smin, det);
+                    xr[r - 1] = (-s1 * dd + b * s2) / det;
+                    xr[r] = (-a * s2 + c * s1) / det;
+                    r -= 2;
+                } else {
+                    double s = 0.0;
+                    for (int c = r + 1; c <= p; ++c) s = fma(X[r + c * LDL], xr[c], s);
+                    double den = X[r + r * LDL] - lam;
+                    if (fabs(den) < smin) den = copysign(smin, den);
+                    xr[r] = -s / den;
+                    r -= 1;
+                }
+            }
+        } else {
+            // pair at (p, p+1), lambda = wr + i wi: x_p = lambda - T_{p+1,p+1}, x_{p+1} = T_{p+1,p}
+            const double lr = wr[p], li = wi[p];
+            double* xi = Wv + (col + 1) * LDL;
+            for (int r = 0; r < d; ++r) { xr[r] = 0.0; xi[r] = 0.0; }
+            xr[p] = lr - X[p + 1 + (p + 1) * LDL];
+            xi[p] = li;
+            xr[p + 1] = X[p + 1 + p * LDL];
+            xi[p + 1] = 0.0;
+            int r = p - 1;
+            while (r >= 0) {
+                if (r > 0 && X[r + (r - 1) * LDL] != 0.0) {
+                    double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+                    for (int c = r + 1; c <= p + 1; ++c) {
+                        s1r = fma(X[r - 1 + c * LDL], xr[c], s1r);
+                        s1i = fma(X[r - 1 + c * LDL], xi[c], s1i);
+                        s2r = fma(X[r + c * LDL], xr[c], s2r);
+                        s2i = fma(X[r + c * LDL], xi[c], s2i);
+                    }
+                    const double ar = X[r - 1 + (r - 1) * LDL] - lr, ai = -li;
+                    const double b = X[r - 1 + r * LDL], c = X[r + (r - 1) * LDL];
+                    const double dr = X[r + r * LDL] - lr, di = -li;
+                    double detr = ar * dr - ai * di - b * c, deti = ar * di + ai * dr;
+                    if (fabs(detr) + fabs(deti) < smin * smin) detr = smin * smin;
+                    const double n1r = -(s1r * dr - s1i * di) + b * s2r, n1i = -(s1r * di + s1i * dr) + b * s2i;
+                    const double n2r = -(ar * s2r - ai * s2i) + c * s1r, n2i = -(ar * s2i + ai * s2r) + c * s1i;
+                    cdiv(n1r, n1i, detr, deti, xr[r - 1], xi[r - 1]);
+                    cdiv(n2r, n2i, detr, deti, xr[r], xi[r]);
+                    r -= 2;
+                } else {
+                    double sr = 0.0, si = 0.0;
+                    for (int c = r + 1; c <= p + 1; ++c) {
+                        sr = fma(X[r + c * LDL], xr[c], sr);
+                        si = fma(X[r + c * LDL], xi[c], si);
+                    }
+                    double denr = X[r + r * LDL] - lr, deni = -li;
+                    if (fabs(denr) + fabs(deni) < smin) denr = smin;
+                    cdiv(-sr, -si, denr, deni, xr[r], xi[r]);
+                    r -= 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // back to the basis of M: w = Z x (lane = row), into Uq (T is no longer needed)
+    for (int o = 0; o < ncols; ++o)
+        for (int r = t; r < d; r += 64) {
+            double s = 0.0;
+            for (int c = 0; c < d; ++c) s = fma(Z[r + c * LDL], Wv[c + o * LDL], s);
+            Uq[r + o * LDL] = s;
+        }
+    __syncthreads();
+
+    // ---- orthonormal basis Q_w of the selected vectors (modified Gram-Schmidt, two passes)
+    const int r0 = t, r1 = t + 64;
+    const bool v0 = r0 < d, v1 = r1 < d;
+    int kn = 0;
+    for (int o = 0; o < ncols; ++o) {
+        double w0 = v0 ? Uq[r0 + o * LDL] : 0.0, w1 = v1 ? Uq[r1 + o * LDL] : 0.0;
+        const double n0 = sqrt(wave_sum64(fma(w0, w0, w1 * w1)));
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < kn; ++q) {
+                const double q0 = v0 ? Wv[r0 + q * LDL] : 0.0, q1 = v1 ? Wv[r1 + q * LDL] : 0.0;
+                const double h = wave_sum64(fma(q0, w0, q1 * w1));
+                w0 = fma(-h, q0, w0);
+                w1 = fma(-h, q1, w1);
+            }
+        const double nw = sqrt(wave_sum64(fma(w0, w0, w1 * w1)));
+        __syncthreads();
+        if (nw > 1e-12 * n0 && n0 > 0.0) {
+            if (v0) Wv[r0 + kn * LDL] = w0 / nw;
+            if (v1) Wv[r1 + kn * LDL] = w1 / nw;
+            ++kn;
+        }
+        __syncthreads();
+    }
+
+    // ---- Qu = R_G^{-1} Q_w with D_k folded into the rows of U (lane = column), R_G staged again
+    stage_block(Z, LDL, dw->R, DMAX, d, d, t, 64);
+    __syncthreads();
+    if (t < kn) {
+        double* u = Uq + t * LDL;
+        for (int r = d - 1; r >= 0; --r) {
+            double s = Wv[r + t * LDL];
+            for (int c = r + 1; c < d; ++c) s = fma(-Z[r + c * LDL], u[c], s);
+            u[r] = s / Z[r + r * LDL];
+        }
+        for (int r = 0; r < d; ++r) coef->Qu[r + t * LDQU] = (r < kc ? Dk[r] : 1.0) * u[r];
+        // Qc = Q_G [Q_w; 0]
+        double carry = 0.0;
+        for (int c = d - 1; c >= kc; --c) {
+            const double a = Wv[c + t * LDL];
+            coef->Qc[c + 1 + t * LDQC] = gsn[c] * a + gcs[c] * carry;
+            carry = gcs[c] * a - gsn[c] * carry;
+        }
+        if (kc < d || d == 0) coef->Qc[kc + t * LDQC] = carry;
+        for (int c = 0; c < kc; ++c) coef->Qc[c + t * LDQC] = Wv[c + t * LDL];
     }
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
 }
@@ -1234,6 +1798,15 @@ void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_
         const double sym_tol = w.mixed ? 1e-4 : 1e-10;
         hipLaunchKernelGGL(k_dense_sym, dim3(1), dim3(DT), 0, s, k_target, sym_tol, w.coef, w.dense, w.ctrl);
         hipLaunchKernelGGL(k_dense_gen, dim3(1), dim3(64), 0, s, k_target, w.coef, w.dense, w.ctrl);
+    }
+    if (w.m > DSM) {
+        // d = kc + j_done is known on the device only: the kernels of both sizes are queued and each
+        // returns at once unless d falls in its range (the mode set by the first stage selects the
+        // general stage)
+        hipLaunchKernelGGL(k_dense_prep_L, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
+                           (const double*)w.gram, kc, jd_max, k_target, w.coef, w.dense, w.ctrl);
+        if (k_target > 0)
+            hipLaunchKernelGGL(k_dense_gen_L, dim3(1), dim3(64), 0, s, k_target, w.coef, w.dense, w.ctrl);
     }
 }
 void launch_chol(hipStream_t s, const Work& w, int kin, int with_drop) {

@@ -14,12 +14,15 @@ namespace skr {
 // ---------------------------------------------------------------------------------------------
 constexpr int ROWS = 256;        // rows per workgroup in every row-parallel kernel (1 row / thread)
 constexpr int NWAVE = ROWS / 64; // wavefronts per row workgroup
-constexpr int NC = 64;           // width of the column reductions of the Arnoldi step
-constexpr int MMAX = 62;         // largest m: the basis [C V] has kc + j + 1 <= m + 1 < NC columns
+constexpr int NC = 128;          // stride of the per-workgroup column partials (two 64-lane groups)
+constexpr int MMAX = 86;         // largest m: the basis [C V] has kc + j + 1 <= m + 1 columns, and a
+                                 // pass-A reduction (those plus ||w||^2) m + 2 <= 88 columns
 constexpr int KMAX = 32;         // largest k (recycled vectors)
 constexpr int LDH = MMAX + 2;    // leading dimension of the Hessenberg store (rows)
-constexpr int DMAX = 64;         // largest projected dimension d = kc + j (<= m) plus one
-constexpr int NORM_COL = NC - 1; // reduction column that carries ||A v_j||^2 in the first pass
+constexpr int DMAX = MMAX + 2;   // leading dimension of the projected matrices (d = kc + j <= m)
+constexpr int DSM = 62;          // largest d of the one-row-per-lane dense kernels (larger d: the
+                                 // row-looped kernels)
+constexpr int DS = 64;           // LDS dimension of the one-row-per-lane dense kernels
 constexpr int NFOLD = 64;        // rows of folded partials (large grids)
 constexpr int FOLD_MIN = 256;    // grids above this many workgroups fold their partials
 
@@ -162,7 +165,8 @@ struct Coef {
     int pad;
 };
 // Hand-over from the first cycle-end stage to the eigen stages (device).
-enum { DW_NONE = 0, DW_PENDING = 1, DW_GEN = 2, DW_DONE = 3 };
+// DW_GEN_L: d > DSM, X holds X'' (M is formed by the row-looped general stage).
+enum { DW_NONE = 0, DW_PENDING = 1, DW_GEN = 2, DW_DONE = 3, DW_GEN_L = 4 };
 struct DenseWork {
     int mode, d, kc, pad;
     double Dk[KMAX];
@@ -314,7 +318,6 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[NR]) {
     return v[0];
 }
 
-__device__ __forceinline__ double wave_reduce_scatter64(double (&v)[NC]) { return wave_reduce_scatter<NC>(v); }
 
 
 // Arrive at the end of a grid-wide reduction. Returns true in exactly one workgroup, the last
@@ -332,41 +335,6 @@ __device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nb
     __syncthreads();
     if (is_last) __threadfence();
     return is_last != 0;
-}
-
-// Column sums over the per-workgroup partials part[b * NC + c] (b < nblk, c < nr <= NC), fixed
-// order: each wave sums a contiguous range of workgroups (loads issued 16 at a time so that their
-// latencies overlap), then the waves are added in order. Called by all ROWS threads of the last
-// workgroup; result in out[0..nr).
-__device__ __forceinline__ void final_reduce(const double* part, int nblk, int nr, double* sh, double* out) {
-    const int lane = lane_id(), w = wave_id();
-    const int per = (nblk + NWAVE - 1) / NWAVE;
-    const int b0 = w * per, b1 = min(nblk, b0 + per);
-    double s = 0.0;
-    if (lane < nr) {
-        int b = b0;
-        for (; b + 16 <= b1; b += 16) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(&part[(b + u) * NC + lane]);
-#pragma unroll
-            for (int u = 0; u < 16; ++u) s += v[u];
-        }
-        for (; b < b1; ++b) s += __builtin_nontemporal_load(&part[b * NC + lane]);
-    }
-    sh[w * NC + lane] = s;
-    __syncthreads();
-    if (threadIdx.x < nr) {
-        double t = sh[lane];
-#pragma unroll
-        for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + lane];
-        out[lane] = t;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void final_reduce64(const double* part, int nblk, double* sh, double* out) {
-    final_reduce(part, nblk, NC, sh, out);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -410,32 +378,36 @@ __device__ __forceinline__ double sum_partials1(const double* part, int nblk, do
     return r;
 }
 
-// Column sums of part[b * NC + c] (b < nblk, c < nr) into out[0..nr) (LDS), fixed order: each wave
-// sums a contiguous quarter of the workgroups (up to 64 loads in flight per lane), then the quarters
-// are added in order. Called by all threads of a workgroup.
+// Column sums of part[b * NC + c] (b < nblk, c < nr <= NC) into out[0..nr) (LDS), fixed order: each
+// wave sums a contiguous quarter of the workgroups (up to 64 loads in flight per lane), then the
+// quarters are added in order. Columns 64.. (nr > 64) are a second pass of the same form. Called by
+// all threads of a workgroup; sh holds NWAVE * 64 doubles.
 __device__ __forceinline__ void sum_partials(const double* part, int nblk, int nr, double* sh, double* out) {
     const int lane = lane_id(), w = wave_id();
     const int per = (nblk + NWAVE - 1) / NWAVE;
     const int b0 = w * per, b1 = min(nblk, b0 + per);
-    double s = 0.0;
-    if (lane < nr) {
-        for (int b = b0; b < b1; b += 64) {
-            double v[64];
+    for (int c0 = 0; c0 < nr; c0 += 64) {
+        const int col = c0 + lane;
+        double s = 0.0;
+        if (col < nr) {
+            for (int b = b0; b < b1; b += 64) {
+                double v[64];
 #pragma unroll
-            for (int u = 0; u < 64; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + lane] : 0.0;
+                for (int u = 0; u < 64; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + col] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 64; ++u) s += v[u];
+                for (int u = 0; u < 64; ++u) s += v[u];
+            }
         }
-    }
-    sh[w * NC + lane] = s;
-    __syncthreads();
-    if (threadIdx.x < nr) {
-        double t = sh[lane];
+        sh[w * 64 + lane] = s;
+        __syncthreads();
+        if (threadIdx.x < 64 && col < nr) {
+            double t = sh[lane];
 #pragma unroll
-        for (int q = 1; q < NWAVE; ++q) t += sh[q * NC + lane];
-        out[lane] = t;
+            for (int q = 1; q < NWAVE; ++q) t += sh[q * 64 + lane];
+            out[col] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // Sum of one value per thread over the grid, for kernels that run once per system: the partial of

@@ -94,9 +94,12 @@ __global__ __launch_bounds__(ROWS) void k_zero(double* __restrict__ x, int n) {
 // columns past the last one used re-read the last column (same address, a cache hit) and get a zero
 // coefficient. Rows past n re-read row n-1 and contribute zero. NR is the reduction width.
 // ---------------------------------------------------------------------------------------------
+// NR covers columns 0..63, NR2 the columns from 64 on (NL > 64): a lane of the reduce-scatter then
+// holds one column of each group.
 template <int NL>
 struct Width {
     static constexpr int NR = NL <= 16 ? 16 : (NL <= 32 ? 32 : 64);
+    static constexpr int NR2 = NL <= 64 ? 0 : (NL <= 80 ? 16 : 32);
 };
 
 __device__ __forceinline__ size_t qoff(int c, int kc, int vbase, int ld) {
@@ -104,8 +107,8 @@ __device__ __forceinline__ size_t qoff(int c, int kc, int vbase, int ld) {
 }
 
 // Block-combine NR column values (one reduce-scattered value per lane) into the per-workgroup
-// partial part[lb * NC + c], c < NR.
-template <int NR>
+// partial part[lb * NC + OFF + c], c < NR. sh: NWAVE * NR doubles of its own.
+template <int NR, int OFF = 0>
 __device__ __forceinline__ void block_partials(double s, double* sh, double* part, int lb) {
     if (lane_id() < NR) sh[wave_id() * NR + lane_id()] = s;
     __syncthreads();
@@ -113,7 +116,7 @@ __device__ __forceinline__ void block_partials(double s, double* sh, double* par
         double t = sh[threadIdx.x];
 #pragma unroll
         for (int q = 1; q < NWAVE; ++q) t += sh[q * NR + threadIdx.x];
-        part[lb * NC + threadIdx.x] = t;
+        part[lb * NC + OFF + threadIdx.x] = t;
     }
 }
 
@@ -123,7 +126,8 @@ __device__ __forceinline__ void block_partials(double s, double* sh, double* par
 // least-squares residual estimate |g_{jj+1}|. Run by wave 0 of every calling workgroup on identical
 // inputs, so all get identical results; only the writer workgroup stores the column, the new
 // rotation and g_{jj+1}. Only the running entry of the rotated column is needed: after rotation q
-// it is a_{q+1} = -sn_q a_q + cs_q col[q+1], run by lane 0 from LDS copies (shc, 3 x 64 doubles).
+// it is a_{q+1} = -sn_q a_q + cs_q col[q+1], run by lane 0 from LDS copies (shc, 3 x 128 doubles;
+// lane t handles the column entries t and t + 64).
 __device__ __forceinline__ double close_step(int jj, int kc, double tot, const double* __restrict__ h1,
                                              const double* __restrict__ h2, double* H, double* Bm, Ctrl* ctrl,
                                              bool writer, int& brk_out, double& hnorm_out, double* shc) {
@@ -133,22 +137,26 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
     const double anorm = sqrt(h1[ncol]);
     const int brk = (hnorm <= 1e-14 * anorm) ? 1 : 0;
     const double hlast = brk ? 0.0 : hnorm;
-    double colt = 0.0;
-    if (t <= jj) colt = h1[kc + t] + h2[kc + t];
-    if (writer) {
-        if (t < kc) Bm[t + jj * KMAX] = h1[t] + h2[t];
-        if (t <= jj) H[t + jj * LDH] = colt;
-        if (t == 0) H[jj + 1 + jj * LDH] = hlast;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int e = t + 64 * half;
+        double colt = 0.0;
+        if (e <= jj) colt = h1[kc + e] + h2[kc + e];
+        if (writer) {
+            if (e < kc) Bm[e + jj * KMAX] = h1[e] + h2[e];
+            if (e <= jj) H[e + jj * LDH] = colt;
+        }
+        shc[e] = colt;
+        shc[128 + e] = (e < jj) ? ctrl->cs[e] : 0.0;
+        shc[256 + e] = (e < jj) ? ctrl->sn[e] : 0.0;
     }
-    shc[t] = colt;
-    shc[64 + t] = (t < jj) ? ctrl->cs[t] : 0.0;
-    shc[128 + t] = (t < jj) ? ctrl->sn[t] : 0.0;
+    if (writer && t == 0) H[jj + 1 + jj * LDH] = hlast;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     double a = 0.0;
     if (t == 0) {
         a = shc[0];
-        for (int q = 0; q < jj; ++q) a = fma(-shc[128 + q], a, shc[64 + q] * shc[q + 1]);
+        for (int q = 0; q < jj; ++q) a = fma(-shc[256 + q], a, shc[128 + q] * shc[q + 1]);
     }
     a = first_lane(a);
     const double rho = hypot(a, hlast);
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
                                                  const double* __restrict__ part_n, double* __restrict__ part_a,
                                                  const double* __restrict__ red1, const double* __restrict__ red2,
                                                  double* H, double* Bm, Ctrl* ctrl) {
-    constexpr int NR = Width<NL>::NR;
+    constexpr int NR = Width<NL>::NR, NR2 = Width<NL>::NR2;
     __shared__ double sh[NWAVE * NC];
     __shared__ double s_scale;
     __shared__ int s_stop;
@@ -276,13 +284,21 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     } else {
         w = 0.0;
     }
+    auto col_val = [&](int c) {
+        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
+        return (c < nst) ? qc * w : (c == nst ? vj * w : (c == ncol ? w * w : 0.0));
+    };
     double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-        acc[c] = (c < nst) ? qc * w : (c == nst ? vj * w : (c == ncol ? w * w : 0.0));
-    }
+    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
     const double s = wave_reduce_scatter<NR>(acc);
+    if constexpr (NR2 > 0) {
+        double acc2[NR2];
+#pragma unroll
+        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
+        const double s2 = wave_reduce_scatter<NR2>(acc2);
+        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb);
+    }
     block_partials<NR>(s, sh, part_a, lb);
 }
 
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
                                                  double* __restrict__ red1, const Ctrl* ctrl) {
-    constexpr int NR = Width<NL>::NR;
+    constexpr int NR = Width<NL>::NR, NR2 = Width<NL>::NR2;
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
     const int ncol = kc + j + 1;
@@ -317,6 +333,16 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
     const double s = wave_reduce_scatter<NR>(acc);
+    if constexpr (NR2 > 0) {
+        double acc2[NR2];
+#pragma unroll
+        for (int c = 0; c < NR2; ++c) {
+            const int cc = 64 + c;
+            acc2[c] = (cc < NL && cc < ncol) ? q[cc < NL ? cc : 0] * w : 0.0;
+        }
+        const double s2 = wave_reduce_scatter<NR2>(acc2);
+        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb);
+    }
     block_partials<NR>(s, sh, part_b, lb);
 }
 
@@ -561,7 +587,8 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
                                                        double* part_n, Ctrl* ctrl) {
     constexpr int NO = 2 * KB + 2;
     constexpr int NTN = (NO + 15) / 16, NP = 16 * NTN;        // output tiles, padded outputs
-    constexpr int MAXQ = 2 * KMAX + MMAX + 1, KP = (MAXQ + 3) / 4 * 4;
+    // input columns 2 kc + jd + 1 with jd <= m - kc: at most KMAX + MMAX + 1
+    constexpr int MAXQ = KMAX + MMAX + 1, KP = (MAXQ + 3) / 4 * 4;
     constexpr int OQC = offsetof(Coef, Qc) / sizeof(double), OQU = offsetof(Coef, Qu) / sizeof(double);
     constexpr int OYU = offsetof(Coef, yU) / sizeof(double), OYV = offsetof(Coef, yV) / sizeof(double);
     constexpr int ORC = offsetof(Coef, rC) / sizeof(double), ORV = offsetof(Coef, rV) / sizeof(double);
@@ -815,31 +842,36 @@ __global__ __launch_bounds__(ROWS) void k_spmv(DevOp op, const double* __restric
 // rows [g per, (g + 1) per) in a fixed order (lane = column, the four waves take contiguous quarters,
 // added in wave order), and the consumer re-sums the NFOLD rows.
 // ---------------------------------------------------------------------------------------------
+// Columns [0, width) (width <= NC), 64 per pass.
 __global__ __launch_bounds__(ROWS) void k_fold(const double* __restrict__ part, int nblk, int width,
                                                double* __restrict__ out) {
-    __shared__ double sh[NWAVE * NC];
+    __shared__ double sh[NWAVE * 64];
     const int lane = lane_id(), w = wave_id();
     const int per = (nblk + NFOLD - 1) / NFOLD;
     const int g0 = blockIdx.x * per, g1 = min(nblk, g0 + per);
     const int q = (per + NWAVE - 1) / NWAVE;
     const int b0 = min(g1, g0 + w * q), b1 = min(g1, b0 + q);
-    double s = 0.0;
-    if (lane < width) {
-        for (int b = b0; b < b1; b += 16) {
-            double v[16];
+    for (int c0 = 0; c0 < width; c0 += 64) {
+        const int col = c0 + lane;
+        double s = 0.0;
+        if (col < width) {
+            for (int b = b0; b < b1; b += 16) {
+                double v[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = part[(size_t)min(b + u, b1 - 1) * NC + lane];
+                for (int u = 0; u < 16; ++u) v[u] = part[(size_t)min(b + u, b1 - 1) * NC + col];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s += (b + u < b1) ? v[u] : 0.0;
+                for (int u = 0; u < 16; ++u) s += (b + u < b1) ? v[u] : 0.0;
+            }
         }
-    }
-    sh[w * NC + lane] = s;
-    __syncthreads();
-    if (threadIdx.x < NC) {
-        double t = sh[threadIdx.x];
+        sh[w * 64 + lane] = s;
+        __syncthreads();
+        if (threadIdx.x < 64 && col < width) {
+            double t = sh[threadIdx.x];
 #pragma unroll
-        for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[q2 * NC + threadIdx.x];
-        out[blockIdx.x * NC + threadIdx.x] = t;
+            for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[q2 * 64 + threadIdx.x];
+            out[blockIdx.x * NC + col] = t;
+        }
+        __syncthreads();
     }
 }
 __global__ __launch_bounds__(ROWS) void k_fold1(const double* __restrict__ part, int nblk, double* __restrict__ out) {
@@ -937,7 +969,10 @@ static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hip
         case 40: CALL(40); break;                       \
         case 48: CALL(48); break;                       \
         case 56: CALL(56); break;                       \
-        default: CALL(64); break;                       \
+        case 64: CALL(64); break;                       \
+        case 72: CALL(72); break;                       \
+        case 80: CALL(80); break;                       \
+        default: CALL(88); break;                       \
     }
 
 // One Arnoldi step (three kernels). With ev != nullptr, ev[2q], ev[2q+1] take the start and end of
@@ -954,11 +989,11 @@ static void launch_step_t(hipStream_t s, const Work& w, const DevOp& op, int kc,
 #define CALL_A(NL) step_a<NL, BT>(s, w, op, src, dst, kc, j, e[0], e[1])
     SKR_DISPATCH8(nla, CALL_A)
 #undef CALL_A
-    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_a, w.nblk, NC, w.fold_a);
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_a, w.nblk, ncol + 1, w.fold_a);
 #define CALL_B(NL) step_b<NL, BT>(s, w, dst, kc, j, e[2], e[3])
     SKR_DISPATCH8(nlb, CALL_B)
 #undef CALL_B
-    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_b, w.nblk, NC, w.fold_b);
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_b, w.nblk, ncol, w.fold_b);
 #define CALL_C(NL) step_c<NL, BT>(s, w, dst, kc, j, e[4], e[5])
     SKR_DISPATCH8(nlb, CALL_C)
 #undef CALL_C

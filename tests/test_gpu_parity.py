@@ -195,7 +195,7 @@ def test_invalid_arguments(env):
     log("[api] invalid arguments are rejected")
     s = darcy_sequence(8, 1)[0]
     ops, bs, xs = upload_systems([s], "cuda:0")
-    for m, k, rtol in ((5, 5, 1e-8), (70, 10, 1e-8), (10, -1, 1e-8), (10, 2, 0.0)):
+    for m, k, rtol in ((5, 5, 1e-8), (87, 10, 1e-8), (10, -1, 1e-8), (10, 2, 0.0)):
         with pytest.raises(skr.SkrError):
             skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=m, k=k, rtol=rtol, maxit=10)
     with pytest.raises(skr.SkrError):
