@@ -14,8 +14,8 @@ for a prefix of the sorted chain, SpMV bandwidth, and the CPU oracle timed on a 
 
 Secondary modes, each printing its own JSON line:
 --dim 3     3-D Darcy on a 128^3 grid (n = 2,097,152; 7-point operator, CSR or matrix-free), 8 systems
-            by default. Its working set (basis about 1.4 GB) is far beyond the 256 MB Infinity Cache,
-            so its kernel rates are HBM rates. No oracle sample.
+            by default, GCRO-DR(80, 20). Its working set (basis about 1.7 GB) is far beyond the 256 MB
+            Infinity Cache, so its kernel rates are HBM rates. No oracle sample.
 --mixed     FP32-stored basis and recycle space, FP64 arithmetic and refinement (any mode).
 --chains C  the sorted order split into C contiguous chains solved concurrently.
 --serve     Darcy systems of several grid sizes arriving one at a time (Poisson) through the serving
@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--dim", type=int, choices=[2, 3], default=2,
                     help="2: the 2-D Darcy workload; 3: 3-D Darcy on a grid^3 mesh (7-point), a secondary mode")
     ap.add_argument("--grid", type=int, default=None, help="grid side (default 256 in 2-D, 128 in 3-D)")
-    ap.add_argument("--m", type=int, default=60)
+    ap.add_argument("--m", type=int, default=None, help="default 60 in 2-D, 80 in 3-D")
     ap.add_argument("--k", type=int, default=20)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=40000)
@@ -109,6 +109,8 @@ def parse():
         a.grid = 256 if a.dim == 2 else 128
     if a.systems is None:
         a.systems = 400 if a.dim == 2 else 8
+    if a.m is None:
+        a.m = 60 if a.dim == 2 else 80
     if a.dim == 3:
         a.spmv_grid = 0          # the 3-D matrix at the config grid is already the HBM-sized case
     return a

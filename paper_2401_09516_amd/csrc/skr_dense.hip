@@ -1176,10 +1176,10 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
 }
 
 // ---------------------------------------------------------------------------------------------
-// Cycle end for DSM < d <= MMAX: the same computation by one wavefront whose row and column loops
-// are strided over its 64 lanes (rows t and t + 64). The eigenproblem always takes the general
-// route (Hessenberg form, Francis double-shift QR, back-substitution), which serves a symmetric M
-// as well. LDS holds three d x d regions, each reused across the phases of the general stage.
+// Cycle end for DSM < d <= MMAX: the same three stages with their thread mappings stretched to
+// d <= MMAX (rows looped over the lanes where one row per lane no longer fits). Each large-d eigen
+// stage forms M = X'' R_G^{-1} itself; the symmetric one hands over to the general one exactly as
+// in the small case. LDS holds two or three d x d regions, each reused across the phases.
 // ---------------------------------------------------------------------------------------------
 constexpr int LDP = MMAX + 2;   // leading dimension of G and X ((d + 1) x d) in the first stage
 constexpr int LDL = MMAX + 1;   // leading dimension of the d x d arrays of the general stage
@@ -1293,7 +1293,486 @@ __global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ 
         }
     for (int r = t; r < d; r += 64) { dw->gcs[r] = gcs[r]; dw->gsn[r] = gsn[r]; }
     if (t < kc) dw->Dk[t] = Dk[t];
-    if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_GEN_L; }
+    if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_PENDING_L; }
+}
+
+// Symmetric stage for d > DSM (DT threads): the route of k_dense_sym (M, symmetry test,
+// Householder tridiagonalization, multisection, twisted factorizations, back-transformation and
+// Gram-Schmidt, Qc and Qu) with every thread mapping stretched to d <= MMAX. Two LDS regions: S
+// (X'', then M, then S = (M + M^T)/2 reduced to tridiagonal form with the reflectors below the
+// subdiagonal, then R_G again for Qu) and V (R_G while M is formed, then the pivots of the twisted
+// factorizations and the eigenvectors). dw->X keeps X'' for the general stage if this one declines.
+constexpr int RPL = (MMAX + 7) / 8;   // rows per lane when eight lanes share a column
+
+__global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
+                                                    Ctrl* ctrl) {
+    if (dw->mode != DW_PENDING_L) return;
+    __shared__ double S[LDL * MMAX];
+    __shared__ double V[LDL * MMAX];
+    __shared__ double gcs[MMAX], gsn[MMAX], Dk[KMAX], Rd[MMAX];
+    __shared__ double red[DT / 64], red2[DT / 64];
+    __shared__ double ta[MMAX], tb[MMAX], tb2[MMAX], hb[MMAX], hv0[MMAX], hP[MMAX];
+    __shared__ double blo[MMAX], bhi[MMAX], lam[MMAX], lsel[KMAX], hsig[1], hkp[DT / 64];
+    __shared__ double bsh[MMAX * NSHIFT];
+    __shared__ int bcnt[MMAX * NSHIFT];
+    __shared__ int sel[KMAX], isel[KMAX];
+    __shared__ int nsel_s, sym_s, need2_s, fail_s;
+    const int t = threadIdx.x;
+    const int d = dw->d, kc = dw->kc;
+    double* R = V;
+    stage_block(R, LDL, dw->R, DMAX, d, d, t, DT);
+    stage_block(S, LDL, dw->X, DMAX, d, d, t, DT);
+    if (t < d) { gcs[t] = dw->gcs[t]; gsn[t] = dw->gsn[t]; }
+    if (t < kc) Dk[t] = dw->Dk[t];
+    __syncthreads();
+    if (t < d) Rd[t] = 1.0 / R[t + t * LDL];
+    __syncthreads();
+    // ---- M = X'' R^{-1}: thread r solves m R = x'' for row r (right-looking over the columns)
+    if (t < d) {
+        for (int c = 0; c < d; ++c) {
+            const double mc = S[t + c * LDL] * Rd[c];
+            S[t + c * LDL] = mc;
+            for (int q = c + 1; q < d; ++q) S[t + q * LDL] = fma(-mc, R[c + q * LDL], S[t + q * LDL]);
+        }
+    }
+    __syncthreads();
+    // ---- symmetry test: max |M - M^T| <= sym_tol max |M|
+    double amax = 0.0, dmax = 0.0;
+    for (int e = t; e < d * d; e += DT) {
+        const int r = e % d, c = e / d;
+        const double a = S[r + c * LDL];
+        amax = fmax(amax, fabs(a));
+        dmax = fmax(dmax, fabs(a - S[c + r * LDL]));
+    }
+    amax = wave_max64(amax);
+    dmax = wave_max64(dmax);
+    if ((t & 63) == 0) { red[t >> 6] = amax; red2[t >> 6] = dmax; }
+    __syncthreads();
+    if (t == 0) {
+        double ga = red[0], gd = red2[0];
+        for (int q = 1; q < DT / 64; ++q) { ga = fmax(ga, red[q]); gd = fmax(gd, red2[q]); }
+        sym_s = (gd <= sym_tol * ga) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sym_s) {
+        if (t == 0) dw->mode = DW_GEN_L;
+        return;
+    }
+    // S = (M + M^T) / 2 in place (each unordered pair by one thread)
+    for (int e = t; e < d * d; e += DT) {
+        const int r = e % d, c = e / d;
+        if (r < c) {
+            const double v = 0.5 * (S[r + c * LDL] + S[c + r * LDL]);
+            S[r + c * LDL] = v;
+            S[c + r * LDL] = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- Householder tridiagonalization (as in k_dense_sym): p = beta S' v with two threads per
+    // row, the rank-2 update strided over all threads (products added without contraction, so S
+    // stays exactly symmetric), sigma of the next step from column j + 1 by wave 0.
+    if (t < 64) {
+        double x2 = 0.0;
+        for (int r = 2 + t; r < d; r += 64) x2 = fma(S[r], S[r], x2);
+        const double sg = wave_sum64(x2);
+        if (t == 0) hsig[0] = sg;
+    }
+    __syncthreads();
+    for (int j = 0; j + 2 < d; ++j) {
+        const int j1 = j + 1;
+        const double sig = hsig[0];
+        const double xh = S[j1 + j * LDL];
+        double beta = 0.0, v0 = 0.0, alpha = xh;
+        if (sig > 0.0) {
+            const double mu = sqrt(fma(xh, xh, sig));
+            v0 = (xh >= 0.0) ? xh + mu : xh - mu;
+            alpha = (xh >= 0.0) ? -mu : mu;
+            beta = 2.0 / fma(v0, v0, sig);
+        }
+        if (t == 0) { ta[j] = S[j + j * LDL]; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; }
+        if (beta != 0.0) {   // same in every thread
+            {
+                const int r = j1 + (t >> 1), q = t & 1;
+                const int rr = min(r, d - 1);
+                double acc0 = 0.0, acc1 = 0.0;
+                int u = 0;
+                for (int c = j1 + q; c < d; c += 2, ++u) {
+                    const double vc = (c == j1) ? v0 : S[c + j * LDL];
+                    const double sv = S[rr + c * LDL];
+                    if (u & 1) acc1 = fma(sv, vc, acc1);
+                    else acc0 = fma(sv, vc, acc0);
+                }
+                double acc = acc0 + acc1;
+                acc += row_partner<1>(acc);
+                const double pr = beta * acc;
+                const double vr = (rr == j1) ? v0 : S[rr + j * LDL];
+                const double kp = wave_sum64((q == 0 && r < d) ? pr * vr : 0.0);
+                if (q == 0 && r < d) hP[r] = pr;
+                if ((t & 63) == 0) hkp[t >> 6] = kp;
+            }
+            __syncthreads();
+            {
+                const double K = 0.5 * beta * ((hkp[0] + hkp[1]) + (hkp[2] + hkp[3]));
+                const int nt = d - j1;
+                for (int e = t; e < nt * nt; e += DT) {
+                    const int r = j1 + e % nt, c = j1 + e / nt;
+                    const double vr = (r == j1) ? v0 : S[r + j * LDL];
+                    const double vc = (c == j1) ? v0 : S[c + j * LDL];
+                    const double wr = fma(-K, vr, hP[r]);
+                    const double wc = fma(-K, vc, hP[c]);
+                    S[r + c * LDL] = S[r + c * LDL] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vc));
+                }
+            }
+        }
+        __syncthreads();
+        if (t < 64) {
+            double x2 = 0.0;
+            for (int r = j1 + 2 + t; r < d; r += 64) x2 = fma(S[r + j1 * LDL], S[r + j1 * LDL], x2);
+            const double sg = wave_sum64(x2);
+            if (t == 0) hsig[0] = sg;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ta[d - 2] = S[d - 2 + (d - 2) * LDL];
+        tb[d - 2] = S[d - 1 + (d - 2) * LDL];
+        ta[d - 1] = S[d - 1 + (d - 1) * LDL];
+    }
+    __syncthreads();
+    if (t < d - 1) tb2[t] = tb[t] * tb[t];
+    __syncthreads();
+
+    // ---- eigenvalues of T by multisection (as in k_dense_sym; the eigenvalue indices i and i + 64
+    // share a lane, and thread i narrows interval i)
+    const double eps = 2.220446049250313e-16;
+    double tnorm = 0.0, pivmin = 0.0;
+    {
+        double glo = __builtin_inf(), ghi = -__builtin_inf(), bm2 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            const double rad = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < d ? fabs(tb[i]) : 0.0);
+            glo = fmin(glo, ta[i] - rad);
+            ghi = fmax(ghi, ta[i] + rad);
+            if (i + 1 < d) bm2 = fmax(bm2, tb2[i]);
+        }
+        tnorm = fmax(fabs(glo), fabs(ghi));
+        pivmin = 2.2250738585072014e-308 * fmax(1.0, bm2);
+        const double widen = 2.0 * eps * tnorm * d + 2.0 * pivmin;
+        if (t < d) { blo[t] = glo - widen; bhi[t] = ghi + widen; }
+    }
+    __syncthreads();
+    for (int round = 0; round < 48; ++round) {
+        const int q = t >> 6;
+        for (int i0 = 0; i0 < d; i0 += 64) {
+            const int i = i0 + (t & 63);
+            const int ii = min(i, d - 1);
+            const double lo = blo[ii], wdt = bhi[ii] - lo;
+            double sh[2], D[2];
+            int cnt[2];
+#pragma unroll
+            for (int s4 = 0; s4 < 2; ++s4) {
+                sh[s4] = lo + wdt * ((double)(q * 2 + s4 + 1) / (double)(NSHIFT + 1));
+                D[s4] = ta[0] - sh[s4];
+                if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+                cnt[s4] = D[s4] < 0.0;
+            }
+            for (int m0 = 1; m0 < d; m0 += 8) {
+                double av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int mm = min(m0 + u, d - 1);
+                    av[u] = ta[mm];
+                    bv[u] = tb2[mm - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (m0 + u < d) {
+#pragma unroll
+                        for (int s4 = 0; s4 < 2; ++s4) {
+                            double rc = __builtin_amdgcn_rcp(D[s4]);
+                            rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                            rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                            D[s4] = fma(-bv[u], rc, av[u] - sh[s4]);
+                            if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+                            cnt[s4] += D[s4] < 0.0;
+                        }
+                    }
+                }
+            }
+            if (i < d) {
+#pragma unroll
+                for (int s4 = 0; s4 < 2; ++s4) {
+                    bsh[i * NSHIFT + q * 2 + s4] = sh[s4];
+                    bcnt[i * NSHIFT + q * 2 + s4] = cnt[s4];
+                }
+            }
+        }
+        __syncthreads();
+        int open = 0;
+        if (t < d) {
+            const int i = t;
+            double nl = blo[i], nh = bhi[i], shv[NSHIFT];
+            int cv[NSHIFT];
+#pragma unroll
+            for (int p2 = 0; p2 < NSHIFT; ++p2) {
+                shv[p2] = bsh[i * NSHIFT + p2];
+                cv[p2] = bcnt[i * NSHIFT + p2];
+            }
+#pragma unroll
+            for (int p2 = 0; p2 < NSHIFT; ++p2) nl = (cv[p2] <= i) ? shv[p2] : nl;
+#pragma unroll
+            for (int p2 = NSHIFT - 1; p2 >= 0; --p2) nh = (cv[p2] > i) ? shv[p2] : nh;
+            if (nh < nl) nh = nl;
+            blo[i] = nl;
+            bhi[i] = nh;
+            open = (nh - nl) > 2e-8 * tnorm;
+        }
+        if (!__syncthreads_or(open)) break;
+    }
+    if (t < d) lam[t] = 0.5 * (blo[t] + bhi[t]);
+    __syncthreads();
+
+    // ---- the k_target eigenvalues of largest |mu| (as in k_dense_sym)
+    if (t == 0) {
+        int lo = 0, hi = d - 1, ns = 0;
+        while (ns < k_target && lo <= hi) {
+            const int pick = (fabs(lam[hi]) >= fabs(lam[lo])) ? hi-- : lo++;
+            if (!(fabs(lam[pick]) > 0.0)) break;
+            isel[ns] = pick;
+            lsel[ns++] = lam[pick];
+        }
+        nsel_s = ns;
+        need2_s = 0;
+        fail_s = 0;
+    }
+    __syncthreads();
+    const int kn = nsel_s;
+
+    // ---- eigenvectors of T by twisted factorizations (as in k_dense_sym), pivots in V
+    double* Fp = V;
+    double* Fm = V + DMAX * KMAX;
+    if (t < 64) {
+        const int o = t >> 1, side = t & 1;
+        const bool act = o < kn;
+        const int oc = min(o, KMAX - 1);
+        const int ie = act ? isel[oc] : 0;
+        const double lo_ = blo[ie], hi_ = bhi[ie];
+        double lm = act ? lsel[oc] : 0.0;
+        auto frcp = [](double v) {
+            double rc = __builtin_amdgcn_rcp(v);
+            rc = fma(rc, fma(-v, rc, 1.0), rc);
+            return fma(rc, fma(-v, rc, 1.0), rc);
+        };
+        for (int pass = 0; pass < 2; ++pass) {
+            if (act) {
+                if (side == 0) {
+                    double dp = ta[0] - lm;
+                    if (fabs(dp) < pivmin) dp = -pivmin;
+                    Fp[o] = dp;
+                    for (int s2 = 1; s2 < d; ++s2) {
+                        dp = fma(-tb2[s2 - 1], frcp(dp), ta[s2] - lm);
+                        if (fabs(dp) < pivmin) dp = -pivmin;
+                        Fp[s2 * KMAX + o] = dp;
+                    }
+                } else {
+                    double dm = ta[d - 1] - lm;
+                    if (fabs(dm) < pivmin) dm = -pivmin;
+                    Fm[(d - 1) * KMAX + o] = dm;
+                    for (int ib = d - 2; ib >= 0; --ib) {
+                        dm = fma(-tb2[ib], frcp(dm), ta[ib] - lm);
+                        if (fabs(dm) < pivmin) dm = -pivmin;
+                        Fm[ib * KMAX + o] = dm;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int rt = 0;
+            double gam = 0.0, nz = 0.0;
+            if (act) {
+                double gb = __builtin_inf();
+                for (int i = 0; i < d; ++i) {
+                    const double g = Fp[i * KMAX + o] + Fm[i * KMAX + o] - (ta[i] - lm);
+                    if (fabs(g) < gb) { gb = fabs(g); gam = g; rt = i; }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (act) {
+                double z = 1.0;
+                if (side == 0) {
+                    for (int i = rt - 1; i >= 0; --i) {
+                        z = -tb[i] * z * frcp(Fp[i * KMAX + o]);
+                        Fp[i * KMAX + o] = z;
+                        nz = fma(z, z, nz);
+                    }
+                    Fp[rt * KMAX + o] = 1.0;
+                } else {
+                    for (int i = rt; i + 1 < d; ++i) {
+                        z = -tb[i] * z * frcp(Fm[(i + 1) * KMAX + o]);
+                        Fp[(i + 1) * KMAX + o] = z;
+                        nz = fma(z, z, nz);
+                    }
+                }
+            }
+            const double nzo = row_partner<1>(nz);
+            const double nz2 = 1.0 + (side == 0 ? nz + nzo : nzo + nz);
+            if (act && pass == 0) {
+                const double ln = lm + gam / nz2;
+                if (ln == ln) lm = fmin(fmax(ln, lo_), hi_);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+
+    // ---- back-transformation and modified Gram-Schmidt, eight lanes per column (column c = t / 8,
+    // rows t % 8 + 8 i, i < RPL, in registers); the finished columns go to V
+    const int zc = t >> 3, part = t & 7;
+    double zr[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = part + 8 * i;
+        zr[i] = (zc < kn && r < d) ? Fp[r * KMAX + zc] : 0.0;
+    }
+    __syncthreads();
+    for (int j = d - 3; j >= 0; --j) {
+        const double beta = hb[j];
+        if (beta == 0.0) continue;
+        const double v0 = hv0[j];
+        double vr[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = part + 8 * i;
+            const double sv = S[min(r, d - 1) + j * LDL];
+            const double m1 = (r > j + 1 && r < d) ? 1.0 : 0.0, m0 = (r == j + 1) ? 1.0 : 0.0;
+            vr[i] = fma(m1, sv, m0 * v0);
+        }
+        double dt0 = 0.0, dt1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            if (i & 1) dt1 = fma(vr[i], zr[i], dt1);
+            else dt0 = fma(vr[i], zr[i], dt0);
+        }
+        double dot = dt0 + dt1;
+        dot = group8_sum(dot);
+        dot *= beta;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) zr[i] = fma(-dot, vr[i], zr[i]);
+    }
+    auto sq8 = [&]() {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            if (i & 1) a1 = fma(zr[i], zr[i], a1);
+            else a0 = fma(zr[i], zr[i], a0);
+        }
+        return sqrt(group8_sum(a0 + a1));
+    };
+    const double n0 = sq8();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < kn; ++j) {
+            const double nr = sq8();
+            if (zc == j) {
+                if (pass == 0) {
+                    if (!(nr > 1e-8 * n0) || !(n0 < __builtin_inf())) fail_s = 1;
+                    else if (nr < 0.7 * n0) need2_s = 1;
+                }
+                const double inv = (nr > 0.0) ? 1.0 / nr : 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    zr[i] *= inv;
+                    const int r = part + 8 * i;
+                    if (r < d) V[r + j * LDL] = zr[i];
+                }
+            }
+            __syncthreads();
+            double qv[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int r = part + 8 * i;
+                qv[i] = (r < d) ? V[r + j * LDL] : 0.0;
+            }
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                if (i & 1) d1 = fma(qv[i], zr[i], d1);
+                else d0 = fma(qv[i], zr[i], d0);
+            }
+            double dot = d0 + d1;
+            dot = group8_sum(dot);
+            const double f = (zc > j && zc < kn) ? dot : 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) zr[i] = fma(-f, qv[i], zr[i]);
+        }
+        __syncthreads();
+        if (fail_s || !need2_s) break;
+    }
+    if (fail_s) {
+        if (t == 0) dw->mode = DW_GEN_L;
+        return;
+    }
+    if (t < kn) sel[t] = t;
+    // R_G again, in S (the reflectors are no longer needed)
+    stage_block(S, LDL, dw->R, DMAX, d, d, t, DT);
+    __syncthreads();
+    // Qc = Q_G [Q_w; 0]: one lane per column, the rotations of Q_G in reverse order
+    if (t < kn) {
+        const int o = t, col = sel[o];
+        double carry = 0.0;
+        for (int c = d - 1; c >= kc; --c) {
+            const double a = V[c + col * LDL];
+            coef->Qc[c + 1 + o * LDQC] = gsn[c] * a + gcs[c] * carry;
+            carry = gcs[c] * a - gsn[c] * carry;
+        }
+        coef->Qc[kc + o * LDQC] = carry;
+        for (int c = 0; c < kc; ++c) coef->Qc[c + o * LDQC] = V[c + col * LDL];
+    }
+    // Qu = R_G^{-1} Q_w by back-substitution, eight lanes per column with lane part p holding rows
+    // RPL p .. RPL p + RPL - 1 (y_i broadcast from its owner); the rows of the recycled part carry D_k
+    {
+        const int o = t >> 3, p = t & 7;
+        const int col = sel[min(o, KMAX - 1)];
+        double y[RPL];
+#pragma unroll
+        for (int s2 = 0; s2 < RPL; ++s2) {
+            const int r = RPL * p + s2;
+            y[s2] = (o < kn && r < d) ? V[r + col * LDL] : 0.0;
+        }
+        for (int i0 = ((d - 1) / RPL) * RPL; i0 >= 0; i0 -= RPL) {
+            const int owner = i0 / RPL;
+#pragma unroll
+            for (int s1 = RPL - 1; s1 >= 0; --s1) {
+                const int i = i0 + s1;
+                if (i < d) {
+                    double rq[RPL];
+#pragma unroll
+                    for (int s2 = 0; s2 < RPL; ++s2) rq[s2] = S[min(RPL * p + s2, d - 1) + i * LDL];
+                    const double yl = y[s1] * Rd[i];
+                    y[s1] = (p == owner) ? yl : y[s1];
+                    const double yi = __shfl(yl, (t & ~7) | owner, 64);
+#pragma unroll
+                    for (int s2 = 0; s2 < RPL; ++s2) {
+                        const double f = (RPL * p + s2 < i) ? yi : 0.0;
+                        y[s2] = fma(-f, rq[s2], y[s2]);
+                    }
+                }
+            }
+        }
+        if (o < kn) {
+#pragma unroll
+            for (int s2 = 0; s2 < RPL; ++s2) {
+                const int r = RPL * p + s2;
+                if (r < d) coef->Qu[r + o * LDQU] = (r < kc ? Dk[r < KMAX ? r : 0] : 1.0) * y[s2];
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
 }
 
 // General stage for d > DSM. LDS regions: XR (X'', then M, then the Schur form T, then the
@@ -1805,8 +2284,11 @@ void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_
         // general stage)
         hipLaunchKernelGGL(k_dense_prep_L, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
                            (const double*)w.gram, kc, jd_max, k_target, w.coef, w.dense, w.ctrl);
-        if (k_target > 0)
+        if (k_target > 0) {
+            const double sym_tol = w.mixed ? 1e-4 : 1e-10;
+            hipLaunchKernelGGL(k_dense_sym_L, dim3(1), dim3(DT), 0, s, k_target, sym_tol, w.coef, w.dense, w.ctrl);
             hipLaunchKernelGGL(k_dense_gen_L, dim3(1), dim3(64), 0, s, k_target, w.coef, w.dense, w.ctrl);
+        }
     }
 }
 void launch_chol(hipStream_t s, const Work& w, int kin, int with_drop) {

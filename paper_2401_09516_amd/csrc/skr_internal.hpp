@@ -165,8 +165,8 @@ struct Coef {
     int pad;
 };
 // Hand-over from the first cycle-end stage to the eigen stages (device).
-// DW_GEN_L: d > DSM, X holds X'' (M is formed by the row-looped general stage).
-enum { DW_NONE = 0, DW_PENDING = 1, DW_GEN = 2, DW_DONE = 3, DW_GEN_L = 4 };
+// DW_PENDING_L, DW_GEN_L: d > DSM, X holds X'' (each large-d stage forms M itself).
+enum { DW_NONE = 0, DW_PENDING = 1, DW_GEN = 2, DW_DONE = 3, DW_GEN_L = 4, DW_PENDING_L = 5 };
 struct DenseWork {
     int mode, d, kc, pad;
     double Dk[KMAX];
@@ -380,8 +380,10 @@ __device__ __forceinline__ double sum_partials1(const double* part, int nblk, do
 
 // Column sums of part[b * NC + c] (b < nblk, c < nr <= NC) into out[0..nr) (LDS), fixed order: each
 // wave sums a contiguous quarter of the workgroups (up to 64 loads in flight per lane), then the
-// quarters are added in order. Columns 64.. (nr > 64) are a second pass of the same form. Called by
-// all threads of a workgroup; sh holds NWAVE * 64 doubles.
+// quarters are added in order. Columns 64.. (nr > 64) are a second pass of the same form. BATCH loads
+// are issued together (16 suffice for folded partials, 16 rows per wave, and keep registers free).
+// Called by all threads of a workgroup; sh holds NWAVE * 64 doubles.
+template <int BATCH = 64>
 __device__ __forceinline__ void sum_partials(const double* part, int nblk, int nr, double* sh, double* out) {
     const int lane = lane_id(), w = wave_id();
     const int per = (nblk + NWAVE - 1) / NWAVE;
@@ -390,12 +392,12 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblk, int n
         const int col = c0 + lane;
         double s = 0.0;
         if (col < nr) {
-            for (int b = b0; b < b1; b += 64) {
-                double v[64];
+            for (int b = b0; b < b1; b += BATCH) {
+                double v[BATCH];
 #pragma unroll
-                for (int u = 0; u < 64; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + col] : 0.0;
+                for (int u = 0; u < BATCH; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + col] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 64; ++u) s += v[u];
+                for (int u = 0; u < BATCH; ++u) s += v[u];
             }
         }
         sh[w * 64 + lane] = s;

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 
 // Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
 // partials of Q^T w.
-template <int NL, typename BT>
+template <int NL, typename BT, bool FOLDED>
 __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
     for (int c = 0; c < NL; ++c) q[c] = (double)basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
-    sum_partials(part_a, npa, ncol + 1, sh, hs);
+    sum_partials<FOLDED ? 16 : 64>(part_a, npa, ncol + 1, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
 }
 
 // Pass C: h2 = Q^T w (sum of pass B's partials, stored), w -= Q h2, partials of ||w||^2.
-template <int NL, typename BT>
+template <int NL, typename BT, bool FOLDED>
 __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npb,
                                                  const double* __restrict__ part_b, double* __restrict__ part_n,
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
     for (int c = 0; c < NL; ++c) q[c] = (double)basis[qoff(c < ncol ? c : ncol - 1, kc, vbase, ld) + ii];
     double w = w_io[ii];
     const int stopped = ctrl->stop;
-    sum_partials(part_b, npb, ncol, sh, hs);
+    sum_partials<FOLDED ? 16 : 64>(part_b, npb, ncol, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x < ncol) red2[threadIdx.x] = hs[threadIdx.x];
 #pragma unroll
@@ -945,19 +945,28 @@ static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* 
     else
         step_a_k<NL, SKR_OP_STENCIL5, BT>(s, w, op, src, dst, kc, j, e0, e1);
 }
+// Passes B and C re-sum NFOLD folded partial rows (w.fold) or one row per workgroup.
 template <int NL, typename BT>
 static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_step_b<NL, BT>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
-                          (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
-                          (const double*)(w.fold ? w.fold_a : w.part_a), w.part_b, w.red1,
-                          (const Ctrl*)w.ctrl);
+    if (w.fold)
+        hipExtLaunchKernelGGL((k_step_b<NL, BT, true>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                              (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, NFOLD, (const double*)w.fold_a,
+                              w.part_b, w.red1, (const Ctrl*)w.ctrl);
+    else
+        hipExtLaunchKernelGGL((k_step_b<NL, BT, false>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                              (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.nblk, (const double*)w.part_a,
+                              w.part_b, w.red1, (const Ctrl*)w.ctrl);
 }
 template <int NL, typename BT>
 static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_step_c<NL, BT>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
-                          (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
-                          (const double*)(w.fold ? w.fold_b : w.part_b), w.part_n, w.red2,
-                          (const Ctrl*)w.ctrl);
+    if (w.fold)
+        hipExtLaunchKernelGGL((k_step_c<NL, BT, true>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                              (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, NFOLD, (const double*)w.fold_b,
+                              w.part_n, w.red2, (const Ctrl*)w.ctrl);
+    else
+        hipExtLaunchKernelGGL((k_step_c<NL, BT, false>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+                              (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.nblk, (const double*)w.part_b,
+                              w.part_n, w.red2, (const Ctrl*)w.ctrl);
 }
 
 #define SKR_DISPATCH8(NLV, CALL)                        \

@@ -2,7 +2,7 @@
 that hold at any size, recomputed on the CPU from the returned solutions.
 
 * 3-D Darcy at 128^3 (n = 2,097,152; the bench's --dim 3 workload and launch configuration), matrix-free
-  7-point operator, FP64 and FP32-stored basis: the FP64 residual ||b - A x|| / ||b|| of every
+  7-point operator, GCRO-DR(80,20) with FP64 and FP32-stored basis, and GCRO-DR(60,20): the FP64 residual ||b - A x|| / ||b|| of every
   returned x, recomputed with the assembled CSR matrix, is at most rtol (1 + 1e-9); the 7-point
   operator matches the CSR product row by row on sampled rows, within 8 eps sum_j |a_ij x_j|.
 * Config-3 time-stepping at 512^2: one chain of 3 backward-Euler steps through the serving runtime;
@@ -30,15 +30,15 @@ def env():
     skr.skr_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_3d_128_residuals(env, mixed):
+@pytest.mark.parametrize("m,mixed", [(80, False), (80, True), (60, False)])
+def test_3d_128_residuals(env, m, mixed):
     torch, skr, ctx = env
-    log(f"[full] 3-D 128^3 stencil, 2 systems of the sorted chain, mixed={mixed}")
+    log(f"[full] 3-D 128^3 stencil, 2 systems of the sorted chain, GCRO-DR({m},20), mixed={mixed}")
     systems = darcy3d_sequence(128, 2, with_csr=False)
     P = param_matrix(systems)
     order, _ = skr.skr_sort(ctx, torch.from_numpy(P).cuda(), P.shape[0], P.shape[1], 0)
     ops, bs, xs = upload_systems(systems, "cuda:0", "stencil")
-    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=60, k=20, rtol=1e-8, maxit=40000,
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=m, k=20, rtol=1e-8, maxit=40000,
                                      flags=skr.SKR_FLAG_MIXED if mixed else 0)
     assert rc == skr.SKR_OK
     torch.cuda.synchronize()
