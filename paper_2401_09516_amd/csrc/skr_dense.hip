@@ -244,10 +244,9 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
     __shared__ double R[LDS_ * DS];
     __shared__ double gcs[DS], gsn[DS], Dk[KMAX], Rd[DS];
     __shared__ double red[DT / 64], red2[DT / 64];
-    __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS], hv0[DS], hP[DS];
-    __shared__ double blo[DS], bhi[DS], lam[DS], lsel[KMAX], hsig[1], hkp[DT / 64];
+    __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS], hv0[DS];
+    __shared__ double blo[DS], bhi[DS], lam[DS], lsel[KMAX];
     __shared__ double bsh[DS * NSHIFT];
-    __shared__ double junk[DT];
     __shared__ int bcnt[DS * NSHIFT];
     __shared__ int sel[KMAX], isel[KMAX];
     __shared__ int nsel_s, sym_s, need2_s, fail_s;
@@ -340,93 +339,93 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
     __syncthreads();
 
     // ---- Householder tridiagonalization. Step j maps x = S[j+1:d, j] to alpha e_1 with
-    // H_j = I - beta v v^T, v = x - alpha e_1: the first entry of v is kept in hv0[j], the others
-    // stay in S[j+2:d, j]. Trailing block update S' -= v w^T + w v^T with p = beta S' v,
-    // w = p - (beta p^T v / 2) v; the two products are added without contraction so that S stays
-    // exactly symmetric. sigma = ||x(2:)||^2 of the next step and p^T v come from wave reductions.
-    if (t < 64) {
-        const double x = (t >= 2 && t < d) ? S[t] : 0.0;
-        const double sg = wave_sum64(x * x);
-        if (t == 0) hsig[0] = sg;
-    }
-    __syncthreads();
-    for (int j = 0; j + 2 < d; ++j) {
-        const int j1 = j + 1;
-        const double sig = hsig[0];
-        const double xh = S[j1 + j * LDS_];
-        double beta = 0.0, v0 = 0.0, alpha = xh;
-        if (sig > 0.0) {
-            const double mu = sqrt(fma(xh, xh, sig));
-            v0 = (xh >= 0.0) ? xh + mu : xh - mu;
-            alpha = (xh >= 0.0) ? -mu : mu;
-            beta = 2.0 / fma(v0, v0, sig);
+    // H_j = I - beta v v^T, v = x - alpha e_1: the first entry of v is kept in hv0[j], the others in
+    // S[j+2:d, j] (LDS, for the back-transformation). The trailing matrix lives in registers: thread
+    // t holds row r = t % 64 at the columns c = t / 64 + 4u (u < 16). Step j: the wave holding column
+    // j forms the reflector and publishes v (double-buffered); every thread adds its part of
+    // p = beta S' v; every wave then sums the four parts of its rows in the same order, so all waves
+    // hold the same p and K = beta p^T v / 2, and w = p - K v. The update S' -= v w^T + w v^T takes w
+    // at its columns from the lane that holds that row, and adds the two products without
+    // contraction so that S stays exactly symmetric.
+    __shared__ double hvb[2][64], hbeta[2], ppart[DT / 64][64];
+    {
+        const int r = t & 63;
+        const int wv = __builtin_amdgcn_readfirstlane(t >> 6);   // this wave's column class
+        double s[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = wv + 4 * u;
+            s[u] = (r < d && c < d) ? S[r + c * LDS_] : 0.0;
         }
-        if (t == 0) { ta[j] = S[j + j * LDS_]; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; }
-        if (beta != 0.0) {   // same in every thread
-            {   // p = beta S' v: four threads per row, sixteen columns each; partial sums of p^T v per wave
-                const int r = j1 + (t >> 2), q = t & 3;
-                const int rr = min(r, d - 1);
-                double sv[16], vv[16];
+        for (int j = 0; j + 2 < d; ++j) {
+            const int j1 = j + 1, buf = j & 1;
+            if (wv == (j & 3)) {
+                double x = 0.0;    // S[r, j]
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int c = min(j1 + q + 4 * u, d - 1);
-                    sv[u] = S[rr + c * LDS_];
-                    vv[u] = S[c + j * LDS_];
+                for (int u = 0; u < 16; ++u) x = (u == (j >> 2)) ? s[u] : x;
+                const double sig = wave_sum64((r >= j + 2 && r < d) ? x * x : 0.0);
+                const double xh = __shfl(x, j1, 64), diag = __shfl(x, j, 64);
+                double beta = 0.0, v0 = 0.0, alpha = xh;
+                if (sig > 0.0) {
+                    const double mu = sqrt(fma(xh, xh, sig));
+                    v0 = (xh >= 0.0) ? xh + mu : xh - mu;
+                    alpha = (xh >= 0.0) ? -mu : mu;
+                    beta = 2.0 / fma(v0, v0, sig);
                 }
-                double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int c = j1 + q + 4 * u;
-                    const double vc = (c == j1) ? v0 : ((c < d) ? vv[u] : 0.0);
-                    if (u & 1) acc1 = fma(sv[u], vc, acc1);
-                    else acc0 = fma(sv[u], vc, acc0);
-                }
-                double acc = acc0 + acc1;
-                acc = group4_sum(acc);
-                const double pr = beta * acc;
-                const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
-                const double kp = wave_sum64((q == 0 && r < d) ? pr * vr : 0.0);
-                if (q == 0 && r < d) hP[r] = pr;
-                if ((t & 63) == 0) hkp[t >> 6] = kp;
+                hvb[buf][r] = (r == j1) ? v0 : ((r > j1 && r < d) ? x : 0.0);
+                if (r > j1 && r < d) S[r + j * LDS_] = x;
+                if (r == 0) { ta[j] = diag; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; hbeta[buf] = beta; }
             }
             __syncthreads();
-            {   // rank-2 update, thread (row j1 + t % 64, columns j1 + t / 64 + 4u)
-                const double K = 0.5 * beta * ((hkp[0] + hkp[1]) + (hkp[2] + hkp[3]));
-                const int r = j1 + (t & 63), rr = min(r, d - 1);
-                const double vr = (rr == j1) ? v0 : S[rr + j * LDS_];
-                const double wr = fma(-K, vr, hP[rr]);
-                double sv[16], vc[16], pc[16];
+            const double beta = hbeta[buf];
+            if (beta != 0.0) {   // same in every thread
+                double vc[16];
+                double pp = 0.0;
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
-                    const int c = min(j1 + (t >> 6) + 4 * u, d - 1);
-                    sv[u] = S[rr + c * LDS_];
-                    vc[u] = S[c + j * LDS_];
-                    pc[u] = hP[c];
+                    vc[u] = hvb[buf][min(wv + 4 * u, 63)];
+                    pp = fma(s[u], vc[u], pp);
                 }
+                ppart[wv][r] = pp;
+                __syncthreads();
+                const double pr = beta * ((ppart[0][r] + ppart[1][r]) + (ppart[2][r] + ppart[3][r]));
+                const double vr = hvb[buf][r];
+                const double kp = wave_sum64((r >= j1 && r < d) ? pr * vr : 0.0);
+                const double K = 0.5 * beta * kp;
+                const double wr = fma(-K, vr, pr);
+                const unsigned long long wu = (unsigned long long)__double_as_longlong(wr);
+                const bool rin = r >= j1 && r < d;
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
-                    const int c = j1 + (t >> 6) + 4 * u;
-                    const double vcc = (c == j1) ? v0 : vc[u];
-                    const double wc = fma(-K, vcc, pc[u]);
-                    const double nv = sv[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vcc));
-                    double* dst = (r < d && c < d) ? &S[r + c * LDS_] : &junk[t];
-                    *dst = nv;
+                    const int c = wv + 4 * u;
+                    const int cl = min(c, 63);
+                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)wu, cl);
+                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wu >> 32), cl);
+                    const double wc = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+                    const double nv = s[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vc[u]));
+                    s[u] = (rin && c >= j1 && c < d) ? nv : s[u];
                 }
             }
         }
-        // sigma of the next step from column j1 (wave 0 wrote or holds rows j1 + lane of it)
-        if (t < 64) {
-            const int r = j1 + t;
-            const double x = (r >= j1 + 2 && r < d) ? S[r + j1 * LDS_] : 0.0;
-            const double sg = wave_sum64(x * x);
-            if (t == 0) hsig[0] = sg;
+        // the last 2 x 2 block: T(d-2, d-2), T(d-1, d-2), T(d-1, d-1)
+        if (d >= 2) {
+            const int c2 = d - 2, c1 = d - 1;
+            if (wv == (c2 & 3)) {
+                double x = 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x = (u == (c2 >> 2)) ? s[u] : x;
+                if (r == c2) ta[c2] = x;
+                if (r == c1) tb[c2] = x;
+            }
+            if (wv == (c1 & 3)) {
+                double x = 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x = (u == (c1 >> 2)) ? s[u] : x;
+                if (r == c1) ta[c1] = x;
+            }
+        } else if (d == 1 && t == 0) {
+            ta[0] = S[0];
         }
-        __syncthreads();
-    }
-    __syncthreads();
-    if (t == 0) {
-        if (d >= 2) { ta[d - 2] = S[d - 2 + (d - 2) * LDS_]; tb[d - 2] = S[d - 1 + (d - 2) * LDS_]; }
-        ta[d - 1] = S[d - 1 + (d - 1) * LDS_];
     }
     __syncthreads();
     if (t < d - 1) tb2[t] = tb[t] * tb[t];
