@@ -306,7 +306,7 @@ def advdiff_bench(a):
     g = run(sub_c, sub_t, 0)
     s_ = run(sub_c, sub_t, a.k)
     out = {
-        "metric": "config-3: systems/s of backward-Euler advection-diffusion chains (GCRO-DR recycling along each chain)",
+        "metric": "systems/s of backward-Euler advection-diffusion chains (GCRO-DR recycling along each chain)",
         "value": round(main["value"], 3), "unit": "systems/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"advdiff2d-{N}x{N}-{C}chains-x{T}steps-gcrodr({a.m},{a.k})"

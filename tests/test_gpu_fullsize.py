@@ -5,7 +5,7 @@ that hold at any size, recomputed on the CPU from the returned solutions.
   7-point operator, GCRO-DR(80,20) with FP64 and FP32-stored basis, and GCRO-DR(60,20): the FP64 residual ||b - A x|| / ||b|| of every
   returned x, recomputed with the assembled CSR matrix, is at most rtol (1 + 1e-9); the 7-point
   operator matches the CSR product row by row on sampled rows, within 8 eps sum_j |a_ij x_j|.
-* Config-3 time-stepping at 512^2: one chain of 3 backward-Euler steps through the serving runtime;
+* Advection-diffusion time-stepping at 512^2: one chain of 3 backward-Euler steps through the serving runtime;
   every step's residual, recomputed on the CPU, is at most rtol (1 + 1e-9), and the chain keeps its
   recycle space (fewer Arnoldi steps after the first).
 """
@@ -65,7 +65,7 @@ def test_3d_128_residuals(env, m, mixed):
 
 def test_advdiff_512_time_stepping(env):
     torch, skr, ctx = env
-    log("[full] config-3 chain at 512^2, 3 backward-Euler steps through the serving runtime")
+    log("[full] advection-diffusion chain at 512^2, 3 backward-Euler steps through the serving runtime")
     from workloads.advdiff import advdiff_chains
     ch = advdiff_chains(512, 1, first_seed=0)[0]
     sctx = make_ctx(torch)

@@ -35,17 +35,17 @@ def _ref(systems, order, m, k, rtol, maxit=20000):
 
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-def test_mixed_config1(env, kind):
+def test_mixed_darcy32_chain(env, kind):
     """32x32 Darcy, 16 systems sorted into one chain, GCRO-DR(30,10), rel-res 1e-8."""
     torch, skr, ctx = env
-    log(f"[mixed] config-1 chain kind={kind}")
+    log(f"[mixed] 32x32 chain of 16 systems kind={kind}")
     systems = darcy_sequence(32, 16)
     order = oracle.greedy_sort(param_matrix(systems))
     ops, bs, xs = upload_systems(systems, "cuda:0", kind)
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8), f"mixed-cfg1-{kind}", order)
+    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8), f"mixed-darcy32-{kind}", order)
 
 
 def test_mixed_gmres_k0(env):
@@ -97,9 +97,9 @@ def test_mixed_3d_chain(env, kind):
 
 
 def test_mixed_fold_path(env):
-    """Config-1 chain with the folded reductions forced on (the large-grid path) in mixed mode."""
+    """32x32 chain with the folded reductions forced on (the large-grid path) in mixed mode."""
     torch, skr, ctx = env
-    log("[mixed] config-1 chain, folded reductions")
+    log("[mixed] 32x32 chain, folded reductions")
     systems = darcy_sequence(32, 8)
     ops, bs, xs = upload_systems(systems, "cuda:0")
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=30, k=10, rtol=1e-8, maxit=20000,
@@ -108,11 +108,11 @@ def test_mixed_fold_path(env):
     compare_chain(systems, res, xs, _ref(systems, None, 30, 10, 1e-8), "mixed-fold")
 
 
-def test_mixed_config2_prefix(env):
+def test_mixed_darcy256_prefix(env):
     """256x256 Darcy, the first 2 systems of the sorted 400-system chain, GCRO-DR(60,20), FP32 basis:
     the bench workload's size and launch configuration, against the oracle's mixed mode."""
     torch, skr, ctx = env
-    log("[mixed] config-2 prefix: 256x256, 2 systems of the sorted chain")
+    log("[mixed] 256x256 prefix: 2 systems of the sorted 400-system chain")
     systems = darcy_sequence(256, 400)
     P = param_matrix(systems)
     Pd = torch.from_numpy(np.ascontiguousarray(P)).cuda()
@@ -123,7 +123,7 @@ def test_mixed_config2_prefix(env):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=60, k=20, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-cfg2-prefix")
+    compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-darcy256-prefix")
 
 
 def test_mixed_edge_cases(env):

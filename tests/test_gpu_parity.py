@@ -53,7 +53,7 @@ def _sort_gpu(torch, skr, ctx, P, start=0):
     return skr.skr_sort(ctx, Pd, P.shape[0], P.shape[1], start)
 
 
-def test_sort_config1(env):
+def test_sort_darcy32_16sys(env):
     torch, skr, ctx = env
     log("[sort] 32x32 Darcy, 16 systems")
     P = param_matrix(darcy_sequence(32, 16))
@@ -93,7 +93,7 @@ def test_sort_nonfinite_rows(env):
     assert np.array_equal(order, ref)
 
 
-def test_sort_config2_sampled(env):
+def test_sort_darcy256_400sys_sampled(env):
     """256x256 Darcy parameter fields, 400 systems: permutation plus sampled steps re-derived
     by the oracle (exact distance, arg-min over the remaining systems)."""
     torch, skr, ctx = env
@@ -112,10 +112,10 @@ def test_sort_config2_sampled(env):
 
 # ------------------------------------------------------------------------------------------ solves
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-def test_solve_config1(env, kind):
+def test_solve_darcy32_chain(env, kind):
     """32x32 Darcy, 16 systems sorted into one chain, GCRO-DR(30,10), rel-res 1e-8."""
     torch, skr, ctx = env
-    log(f"[solve] config-1 chain kind={kind}")
+    log(f"[solve] 32x32 chain of 16 systems kind={kind}")
     systems = darcy_sequence(32, 16)
     P = param_matrix(systems)
     order = oracle.greedy_sort(P)
@@ -123,7 +123,7 @@ def test_solve_config1(env, kind):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000)
     assert rc == skr.SKR_OK
     ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, 30, 10, 1e-8, 20000)
-    _compare(systems, res, xs, ref, f"cfg1-{kind}", order)
+    _compare(systems, res, xs, ref, f"darcy32-{kind}", order)
 
 
 def test_gmres_k0(env):
@@ -202,11 +202,11 @@ def test_invalid_arguments(env):
         skr.skr_solve_sequence(ctx, ops, bs, xs, [1], m=10, k=2, rtol=1e-8, maxit=10)
 
 
-def test_solve_config2_prefix(env):
+def test_solve_darcy256_prefix(env):
     """256x256 Darcy (n = 65536), the first 2 systems of the sorted 400-system chain,
     GCRO-DR(60,20), rel-res 1e-8, GPU against the oracle."""
     torch, skr, ctx = env
-    log("[solve] config-2 prefix: 256x256, 2 systems of the sorted chain, GCRO-DR(60,20)")
+    log("[solve] 256x256 prefix: 2 systems of the sorted 400-system chain, GCRO-DR(60,20)")
     systems = darcy_sequence(256, 400)
     P = param_matrix(systems)
     order, _ = _sort_gpu(torch, skr, ctx, P)
@@ -216,7 +216,7 @@ def test_solve_config2_prefix(env):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=60, k=20, rtol=1e-8, maxit=20000)
     assert rc == skr.SKR_OK
     ref = oracle.solve_sequence([s.A for s in pre], [s.b for s in pre], None, 60, 20, 1e-8, 20000)
-    _compare(pre, res, xs, ref, "cfg2-prefix")
+    _compare(pre, res, xs, ref, "darcy256-prefix")
 
 
 def test_solve_nonsymmetric_advdiff(env):
@@ -280,7 +280,7 @@ def test_solve_3d_chain(env, kind):
 def test_fold_path(env):
     """The folded two-level partial reductions (forced at a small grid) against the oracle."""
     torch, skr, ctx = env
-    log("[solve] config-1 chain with folded partials")
+    log("[solve] 32x32 chain with folded partials")
     systems = darcy_sequence(32, 16)
     order = oracle.greedy_sort(param_matrix(systems))
     ops, bs, xs = upload_systems(systems, "cuda:0")
@@ -288,4 +288,4 @@ def test_fold_path(env):
                                      flags=skr.SKR_FLAG_FOLD)
     assert rc == skr.SKR_OK
     ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, 30, 10, 1e-8, 20000)
-    _compare(systems, res, xs, ref, "cfg1-fold", order)
+    _compare(systems, res, xs, ref, "darcy32-fold", order)
