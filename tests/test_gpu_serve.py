@@ -109,16 +109,17 @@ def _cpu_rule(systems, split=math.inf, max_chains=8, shape=lambda s: s.n, cap=0)
     return out
 
 
-def test_serve_one_chain_equals_solve_sequence(env):
+@pytest.mark.parametrize("m,k", [(20, 6), (80, 20)])
+def test_serve_one_chain_equals_solve_sequence(env, m, k):
     torch, skr = env
-    log("[serve] one chain vs skr_solve_sequence, 32x32, 6 systems")
+    log(f"[serve] one chain vs skr_solve_sequence, 32x32, 6 systems, GCRO-DR({m},{k})")
     systems = darcy_sequence(32, 6, first_seed=300)
-    res, xh, where, _ = _serve(torch, skr, systems, max_chains=1, workers=2)
+    res, xh, where, _ = _serve(torch, skr, systems, m=m, k=k, max_chains=1, workers=2)
     assert [w for w in where] == [(0, i) for i in range(6)]
     ctx = make_ctx(torch)
     try:
         ops, bs, xs, _ = _upload(torch, systems)
-        rc, ref = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=20000)
+        rc, ref = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=m, k=k, rtol=1e-8, maxit=20000)
         torch.cuda.synchronize()
         for i in range(6):
             assert res[i] == ref[i], i

@@ -181,14 +181,15 @@ def test_startup_relations_and_rank_drop(darcy16):
     np.testing.assert_allclose(x1 + 0, U @ (C.T @ np.ones(n)))
 
 
-def test_recycle_space_relations_after_solve(darcy16):
+@pytest.mark.parametrize("m,k", [(20, 6), (80, 20)])
+def test_recycle_space_relations_after_solve(darcy16, m, k):
     A, b = darcy16[0].A, darcy16[0].b
-    r = gcrodr(A, b, None, 20, 6, 1e-10, 5000)
+    r = gcrodr(A, b, None, m, k, 1e-10, 5000)
     U, C = r.Y_next, r.C_last
-    assert U.shape == (A.shape[0], 6) and C.shape == U.shape
+    assert U.shape == (A.shape[0], k) and C.shape == U.shape
     # v1 = r/||r|| carries the rounding of r = r - W G y, of size eps*||b||, along C: relative to the
     # shrinking residual it grows to ~eps/relres, so C's orthonormality is bounded through relres.
-    assert np.abs(C.T @ C - np.eye(6)).max() <= 1e-13 / r.relres_true
+    assert np.abs(C.T @ C - np.eye(k)).max() <= 1e-13 / r.relres_true
     assert np.linalg.norm(A @ U - C) <= 1e-10 * spla.norm(A) * np.linalg.norm(U)
 
 
@@ -226,9 +227,10 @@ def test_tiny_solve_against_dense_lu(kind):
         Y = r.Y_next
 
 
-def test_sequence_solutions_match_direct(darcy16):
+@pytest.mark.parametrize("m,k", [(30, 10), (80, 20)])
+def test_sequence_solutions_match_direct(darcy16, m, k):
     As, bs = [s.A for s in darcy16], [s.b for s in darcy16]
-    res = solve_sequence(As, bs, None, 30, 10, 1e-8, 5000)
+    res = solve_sequence(As, bs, None, m, k, 1e-8, 5000)
     for A, b, r in zip(As, bs, res):
         xs = spla.spsolve(A.tocsc(), b)
         lam_min = spla.eigsh(A, k=1, sigma=0, return_eigenvectors=False)[0]
