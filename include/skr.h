@@ -83,7 +83,7 @@ typedef struct {
 
 /* Solver options. m: maximum subspace size per cycle (1..86); k: recycled vectors (0 = GMRES(m),
  * k < m, k <= 32); rtol: relative residual target; maxit: maximum Arnoldi steps per system;
- * flags: 0 or a combination of SKR_FLAG_PROFILE, SKR_FLAG_FOLD and SKR_FLAG_MIXED. */
+ * flags: 0 or a combination of SKR_FLAG_PROFILE, SKR_FLAG_FOLD, SKR_FLAG_MIXED and SKR_FLAG_CONTINUE. */
 #define SKR_FLAG_PROFILE 1u   /* time every 16th Arnoldi step's kernels with hipEvents (see skr_profile_get) */
 #define SKR_FLAG_FOLD    2u   /* fold the per-workgroup partials of every grid reduction into 64 rows
                                  before they are re-summed; done anyway above 256 workgroups
@@ -97,6 +97,10 @@ typedef struct {
                                  as the inner correction. relres_true is the FP64 residual of the
                                  FP64 solution, so rtol keeps its meaning. An extension of the
                                  paper's method (Alg. 2 is stated in exact arithmetic). */
+#define SKR_FLAG_CONTINUE 8u  /* skr_solve_sequence: the first system starts from the recycle space
+                                 the context carries (left by the previous skr_solve_sequence on it,
+                                 or set with skr_recycle_set) instead of none; it must belong to the
+                                 same n, m, k and SKR_FLAG_MIXED setting, else SKR_EINVAL */
 
 typedef struct {
     int32_t m;
@@ -163,6 +167,31 @@ int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64
 int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_dev,
                        double* const* x_dev, int64_t N, const int64_t* order,
                        const skr_opts* opts, skr_result* results_host);
+
+/*
+ * Checkpoint and resume of a chain. After skr_solve_sequence the context carries the recycle space
+ * U_k that the next system of the chain would start from (the Y~_k handed from system to system,
+ * App. B.1; Alg. 2 start-up). With the order and the index of the next system it is the whole
+ * state of the chain: every other quantity of a solve is rebuilt from A, b and U_k. A chain split
+ * into several skr_solve_sequence calls, the later ones with SKR_FLAG_CONTINUE after
+ * skr_recycle_get / skr_recycle_set (also across contexts or processes), gives results identical
+ * bit for bit to the uninterrupted call.
+ *
+ * skr_recycle_get: *k_out receives the number of carried columns (0 after GMRES, k = 0, or when no
+ * recycle space was formed). If U_dev is not NULL, U_dev (device, FP64, column-major, leading
+ * dimension ld >= n) receives the n x *k_out block; with SKR_FLAG_MIXED the stored FP32 values are
+ * widened exactly. Errors: SKR_EINVAL (NULL ctx or k_out, no completed solve on this context,
+ * ld < n).
+ *
+ * skr_recycle_set: makes U_dev (device, FP64, n x kcols, column-major, leading dimension ld) the
+ * recycle space the next skr_solve_sequence with SKR_FLAG_CONTINUE and these options starts from.
+ * The workspace is sized for (n, opts->m, opts->k) as by a solve; with SKR_FLAG_MIXED the values are
+ * rounded to FP32 (nearest even). The caller keeps ownership of U_dev. Errors: SKR_EINVAL (bad
+ * options, n < 1, kcols outside [0, opts->k], NULL U_dev or ld < n with kcols > 0), SKR_ENOMEM.
+ */
+int skr_recycle_get(skr_ctx* ctx, int32_t* k_out, double* U_dev, int64_t ld);
+int skr_recycle_set(skr_ctx* ctx, const skr_opts* opts, int64_t n, int32_t kcols, const double* U_dev,
+                    int64_t ld);
 
 /* y_dev = A x_dev for one operator (the sparse product of the Arnoldi step; Eq. 3). */
 int skr_spmv(skr_ctx* ctx, const skr_op* op, const double* x_dev, double* y_dev);

@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["skr_solver.hip", "skr_dense.hip", "skr_sort.hip", "skr_api.hip", "skr_serve.hip"]
+SOURCES = ["skr_solver.hip", "skr_dense.hip", "skr_sort.hip", "skr_api.hip", "skr_serve.hip", "skr_state.hip"]
 OUTPUT = os.path.join(HERE, "libskr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

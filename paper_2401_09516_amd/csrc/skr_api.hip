@@ -18,6 +18,7 @@ void launch_init(hipStream_t, const Work&, const double*, double*, double);
 void launch_clear_nonfinite(hipStream_t, const Work&);
 void launch_check_finite(hipStream_t, const Work&, const double*, long);
 void launch_zero(hipStream_t, double*, int);
+void launch_copy_u(hipStream_t, const Work&, double*, long, int, int);
 void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int, hipEvent_t* ev);
 void launch_close_basis(hipStream_t, const Work&, int, int);
 void launch_cycle_gram(hipStream_t, const Work&, int, int);
@@ -92,6 +93,7 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     Work& w = ctx->w;
     if (w.basis && w.n == n && w.m == m && w.k == k) return SKR_OK;
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->carry_valid = false;      // the carried recycle space goes with the old workspace
     free_work(w);
     w.n = n;
     w.m = m;
@@ -594,8 +596,16 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
         rc = to_devop(ops[idx], d, nv);
         if (rc) return rc;
     }
+    const int mixed = (opts->flags & SKR_FLAG_MIXED) ? 1 : 0;
+    const bool cont = (opts->flags & SKR_FLAG_CONTINUE) != 0;
+    if (cont && !(ctx->carry_valid && ctx->carry_n == n && ctx->carry_m == opts->m &&
+                  ctx->carry_kmax == opts->k && ctx->carry_mixed == mixed))
+        return fail(SKR_EINVAL, "SKR_FLAG_CONTINUE: the context carries no recycle space for n = %d, m = %d, "
+                    "k = %d and this precision", n, opts->m, opts->k);
     if ((rc = prepare_solve(ctx, n, *opts))) return rc;
-    int kin = 0;   // recycled vectors carried from the previous system (held in w.U)
+    // recycled vectors carried from the previous system (held in w.U)
+    int kin = cont ? ctx->carry_k : 0;
+    ctx->carry_valid = false;
     bool any_maxit = false;
     for (int64_t q = 0; q < N; ++q) {
         const int64_t idx = order ? order[q] : q;
@@ -604,7 +614,46 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
         results_host[idx] = res;
         any_maxit = any_maxit || res.status == SKR_MAXIT;
     }
+    ctx->carry_valid = true;
+    ctx->carry_k = kin;
+    ctx->carry_n = n;
+    ctx->carry_m = opts->m;
+    ctx->carry_kmax = opts->k;
+    ctx->carry_mixed = mixed;
     return any_maxit ? SKR_WARN_NOTCONVERGED : SKR_OK;
+}
+
+int skr_recycle_get(skr_ctx* ctx, int32_t* k_out, double* U_dev, int64_t ld) {
+    if (!ctx || !k_out) return fail(SKR_EINVAL, "NULL context or k_out");
+    if (!ctx->carry_valid) return fail(SKR_EINVAL, "the context carries no recycle space (no completed solve)");
+    *k_out = ctx->carry_k;
+    if (!U_dev || ctx->carry_k == 0) return SKR_OK;
+    if (ld < ctx->carry_n) return fail(SKR_EINVAL, "ld (%lld) < n (%d)", (long long)ld, ctx->carry_n);
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_copy_u(ctx->stream, ctx->w, U_dev, (long)ld, ctx->carry_k, 0);
+    HIPLAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+
+int skr_recycle_set(skr_ctx* ctx, const skr_opts* opts, int64_t n, int32_t kcols, const double* U_dev, int64_t ld) {
+    if (!ctx || !opts) return fail(SKR_EINVAL, "NULL context or options");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (n < 1 || n > INT32_MAX) return fail(SKR_EINVAL, "n must be in [1, 2^31)");
+    if (kcols < 0 || kcols > opts->k) return fail(SKR_EINVAL, "kcols must be in [0, k] (got %d, k = %d)", kcols, opts->k);
+    if (kcols > 0 && (!U_dev || ld < n)) return fail(SKR_EINVAL, "need U_dev and ld >= n");
+    if ((rc = prepare_solve(ctx, (int)n, *opts))) return rc;
+    launch_copy_u(ctx->stream, ctx->w, const_cast<double*>(U_dev), (long)ld, kcols, 1);
+    HIPLAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->carry_valid = true;
+    ctx->carry_k = kcols;
+    ctx->carry_n = (int)n;
+    ctx->carry_m = opts->m;
+    ctx->carry_kmax = opts->k;
+    ctx->carry_mixed = (opts->flags & SKR_FLAG_MIXED) ? 1 : 0;
+    return SKR_OK;
 }
 
 }  // extern "C"

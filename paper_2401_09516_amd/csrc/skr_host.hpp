@@ -33,6 +33,10 @@ struct skr_ctx {
     // steps the first cycle of the previous system on this context ran when it stopped early (0: it
     // ran the full cycle); predicts the launch length of the next system's first cycle
     int pred_first = 0;
+    // recycle space carried in w.U after the last solve on this context (or skr_recycle_set): its
+    // column count and the (n, m, k, mixed) it belongs to; valid only while the workspace keeps it
+    bool carry_valid = false;
+    int carry_k = 0, carry_n = 0, carry_m = 0, carry_kmax = 0, carry_mixed = 0;
     // serving (skr_serve_start .. skr_serve_stop)
     skr::Server* server = nullptr;
 };

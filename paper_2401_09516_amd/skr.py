@@ -35,11 +35,12 @@ SKR_OP_STENCIL7 = 2
 SKR_FLAG_PROFILE = 1
 SKR_FLAG_FOLD = 2
 SKR_FLAG_MIXED = 4
+SKR_FLAG_CONTINUE = 8
 
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
             "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
             "skr_serve_start", "skr_submit", "skr_poll", "skr_wait", "skr_ticket_chain", "skr_serve_stats_get",
-            "skr_serve_stop")
+            "skr_serve_stop", "skr_recycle_get", "skr_recycle_set")
 
 
 class SkrError(RuntimeError):
@@ -137,6 +138,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.skr_serve_stats_get.restype = i32
     lib.skr_serve_stop.argtypes = [vp]
     lib.skr_serve_stop.restype = i32
+    lib.skr_recycle_get.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp, i64]
+    lib.skr_recycle_get.restype = i32
+    lib.skr_recycle_set.argtypes = [vp, ctypes.POINTER(skr_opts), i64, ctypes.c_int32, vp, i64]
+    lib.skr_recycle_set.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -232,6 +237,26 @@ def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 
     res = (skr_result * max(N, 1))()
     rc = _check(load_library().skr_solve_sequence(ctx, arr, bp, xp, N, optr, ctypes.byref(opts), res))
     return rc, [_result_dict(r) for r in list(res)[:N]]
+
+
+def skr_recycle_get(ctx: int, U=None, ld: int = 0) -> int:
+    """Number of recycled columns the context carries; with ``U`` (device float64, column j in row j of a
+    (k, n) tensor, i.e. n x k column-major with leading dimension ``ld``, default the row stride) also
+    copies them."""
+    k = ctypes.c_int32()
+    if U is not None and not ld:
+        ld = U.stride(0) if U.dim() == 2 else U.numel()
+    _check(load_library().skr_recycle_get(ctx, ctypes.byref(k), _ptr(U) if U is not None else None, ld))
+    return k.value
+
+
+def skr_recycle_set(ctx: int, U, n: int, kcols: int, m: int, k: int, ld: int = 0, rtol: float = 1e-8,
+                    maxit: int = 10000, flags: int = 0) -> None:
+    """Make ``U`` (device float64, n x kcols column-major, leading dimension ``ld``, default n) the
+    recycle space the next skr_solve_sequence with SKR_FLAG_CONTINUE and the same m, k, flags starts from."""
+    opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
+    _check(load_library().skr_recycle_set(ctx, ctypes.byref(opts), n, kcols,
+                                          _ptr(U) if U is not None else None, ld or n))
 
 
 def _result_dict(r: skr_result) -> dict:
