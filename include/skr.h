@@ -120,12 +120,20 @@ typedef struct {
     int64_t spmv;          /* products with A: Arnoldi, start-up A*Y columns, true residuals      */
     double relres_true;    /* ||b - A x|| / ||b||, computed on the device at exit                 */
     double relres_est;     /* least-squares residual estimate / ||b|| at exit                     */
+    double seconds;        /* host wall-clock time of the system's solve (start-up to exit test;   */
+                           /* the call waits for the device at the end of every system)            */
 } skr_result;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t, NULL for
  * the default stream). Device workspace is allocated by the library on first use and owned by the
  * context. Returns SKR_EINVAL for a bad device, SKR_EHIP on runtime failure. */
 int skr_ctx_create(int device, void* hip_stream, skr_ctx** out);
+
+/* Device bytes of the workspace a context allocates for solves of size n with GCRO-DR(m, k) (basis
+ * [C V] and U, work vectors, reduction partials, small dense state); the same for both storage modes
+ * (flags: SKR_FLAG_* of the solve). A serving chain adds p doubles for its parameter tail. Returns 0
+ * for sizes a solve would reject (n < 1 or n >= 2^31, m outside [1, 86], k < 0, k >= m, k > 32). */
+size_t skr_workspace_bytes(int64_t n, int32_t m, int32_t k, uint32_t flags);
 
 /* Free the context and its workspace (waits for its stream). NULL is accepted. */
 int skr_ctx_destroy(skr_ctx* ctx);

@@ -3,6 +3,7 @@
 // skr_dense.hip and skr_sort.hip; the host only sequences launches and reads a small control
 // block once per Arnoldi cycle.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -206,7 +207,7 @@ int skr::to_devop(const skr_op& o, DevOp& d, int64_t& nvals) {
 // context holds (kin columns of U, left by the system solved before on this context) and leaving
 // the next one there (kin updated). The workspace must be sized for (n, m, k), with the fold and
 // storage modes set (prepare_solve). Returns SKR_OK with the outcome in res, or an error code.
-int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double* x, const skr_opts& opts, int& kin,
+static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, double* x, const skr_opts& opts, int& kin,
                  skr_result& res) {
     Work& w = ctx->w;
     hipStream_t s = ctx->stream;
@@ -405,6 +406,15 @@ int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double*
     res.relres_est = est / bnorm;
     kin = (k > 0) ? kc : 0;
     return SKR_OK;
+}
+
+// One system of a chain (solve_system_body) with its host wall-clock time in res.seconds.
+int skr::solve_system(skr_ctx* ctx, const skr_op& opin, const double* b, double* x, const skr_opts& opts, int& kin,
+                 skr_result& res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = solve_system_body(ctx, opin, b, x, opts, kin, res);
+    res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
 }
 
 // Checks m, k, rtol and maxit (Alg. 2 inputs).
@@ -621,6 +631,12 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
     ctx->carry_kmax = opts->k;
     ctx->carry_mixed = mixed;
     return any_maxit ? SKR_WARN_NOTCONVERGED : SKR_OK;
+}
+
+size_t skr_workspace_bytes(int64_t n, int32_t m, int32_t k, uint32_t flags) {
+    (void)flags;
+    if (n < 1 || n > INT32_MAX || m < 1 || m > MMAX || k < 0 || k >= m || k > KMAX) return 0;
+    return work_bytes((int)n, m, k);
 }
 
 int skr_recycle_get(skr_ctx* ctx, int32_t* k_out, double* U_dev, int64_t ld) {

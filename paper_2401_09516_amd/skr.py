@@ -40,7 +40,7 @@ SKR_FLAG_CONTINUE = 8
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
             "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
             "skr_serve_start", "skr_submit", "skr_poll", "skr_wait", "skr_ticket_chain", "skr_serve_stats_get",
-            "skr_serve_stop", "skr_recycle_get", "skr_recycle_set")
+            "skr_serve_stop", "skr_recycle_get", "skr_recycle_set", "skr_workspace_bytes")
 
 
 class SkrError(RuntimeError):
@@ -65,7 +65,7 @@ class skr_opts(ctypes.Structure):
 class skr_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("k_start", ctypes.c_int32),
                 ("rank_dropped", ctypes.c_int32), ("iters", ctypes.c_int64), ("spmv", ctypes.c_int64),
-                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double)]
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class skr_kernel_stat(ctypes.Structure):
@@ -138,6 +138,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.skr_serve_stats_get.restype = i32
     lib.skr_serve_stop.argtypes = [vp]
     lib.skr_serve_stop.restype = i32
+    lib.skr_workspace_bytes.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]
+    lib.skr_workspace_bytes.restype = ctypes.c_size_t
     lib.skr_recycle_get.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp, i64]
     lib.skr_recycle_get.restype = i32
     lib.skr_recycle_set.argtypes = [vp, ctypes.POINTER(skr_opts), i64, ctypes.c_int32, vp, i64]
@@ -239,6 +241,11 @@ def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 
     return rc, [_result_dict(r) for r in list(res)[:N]]
 
 
+def skr_workspace_bytes(n: int, m: int, k: int, flags: int = 0) -> int:
+    """Device bytes a context allocates for solves of size n with GCRO-DR(m, k); 0 for invalid sizes."""
+    return int(load_library().skr_workspace_bytes(n, m, k, flags))
+
+
 def skr_recycle_get(ctx: int, U=None, ld: int = 0) -> int:
     """Number of recycled columns the context carries; with ``U`` (device float64, column j in row j of a
     (k, n) tensor, i.e. n x k column-major with leading dimension ``ld``, default the row stride) also
@@ -261,7 +268,7 @@ def skr_recycle_set(ctx: int, U, n: int, kcols: int, m: int, k: int, ld: int = 0
 
 def _result_dict(r: skr_result) -> dict:
     return dict(status=r.status, cycles=r.cycles, k_start=r.k_start, rank_dropped=r.rank_dropped,
-                iters=r.iters, spmv=r.spmv, relres_true=r.relres_true, relres_est=r.relres_est)
+                iters=r.iters, spmv=r.spmv, relres_true=r.relres_true, relres_est=r.relres_est, seconds=r.seconds)
 
 
 def skr_spmv(ctx: int, op: Operator, x, y) -> None:

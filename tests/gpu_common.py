@@ -68,3 +68,8 @@ def compare_chain(systems, res_gpu, xs, res_ref, tag, order=None, strict=False, 
         tot_g += g["iters"]
         tot_r += r.iters
     assert abs(tot_g - tot_r) <= max(2, 0.03 * tot_r), (tag, tot_g, tot_r)
+
+
+def same_result(a: dict, b: dict) -> bool:
+    """Result dicts equal in every field but the measured wall-clock seconds."""
+    return {k: v for k, v in a.items() if k != "seconds"} == {k: v for k, v in b.items() if k != "seconds"}

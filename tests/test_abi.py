@@ -49,6 +49,7 @@ int main(void) {
   F(skr_opts, m); F(skr_opts, k); F(skr_opts, rtol); F(skr_opts, maxit); F(skr_opts, flags);
   F(skr_result, status); F(skr_result, cycles); F(skr_result, k_start); F(skr_result, rank_dropped);
   F(skr_result, iters); F(skr_result, spmv); F(skr_result, relres_true); F(skr_result, relres_est);
+  F(skr_result, seconds);
   printf("skr_kernel_stat %zu\nskr_profile %zu\n", sizeof(skr_kernel_stat), sizeof(skr_profile));
   F(skr_kernel_stat, launches); F(skr_kernel_stat, ms); F(skr_kernel_stat, bytes);
   F(skr_profile, step_a); F(skr_profile, step_b); F(skr_profile, step_c); F(skr_profile, steps);
@@ -77,3 +78,15 @@ int main(void) {
 def test_binding_rejects_missing_library(tmp_path):
     with pytest.raises(ImportError):
         skr.load_library(str(tmp_path / "nope.so"))
+
+
+def test_workspace_bytes_query():
+    """skr_workspace_bytes is host arithmetic (no device): positive for valid sizes, at least the
+    basis [C V] and U in FP64, growing with n and m, 0 for sizes a solve rejects."""
+    n, m, k = 65536, 60, 20
+    b = skr.skr_workspace_bytes(n, m, k)
+    assert b >= (k + m + 1 + k) * n * 8
+    assert skr.skr_workspace_bytes(2 * n, m, k) > b and skr.skr_workspace_bytes(n, 80, k) > b
+    assert skr.skr_workspace_bytes(n, m, k, skr.SKR_FLAG_MIXED) == b
+    for args in ((0, m, k), (n, 87, 20), (n, 20, 20), (n, 60, 33), (n, 60, -1), (2 ** 31, m, k)):
+        assert skr.skr_workspace_bytes(*args) == 0, args

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import compare_chain, log, make_ctx, need_gpu
+from gpu_common import same_result as _same, compare_chain, log, make_ctx, need_gpu
 from workloads import darcy_sequence, param_matrix
 from workloads.device import upload_systems
 
@@ -122,7 +122,7 @@ def test_serve_one_chain_equals_solve_sequence(env, m, k):
         rc, ref = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=m, k=k, rtol=1e-8, maxit=20000)
         torch.cuda.synchronize()
         for i in range(6):
-            assert res[i] == ref[i], i
+            assert _same(res[i], ref[i]), i
             assert np.array_equal(xh[i], xs[i].cpu().numpy()), i
     finally:
         skr.skr_ctx_destroy(ctx)
@@ -167,7 +167,7 @@ def test_serve_workers_do_not_change_results(env):
     r4, x4, w4, _ = _serve(torch, skr, systems, workers=4, split=0.02)
     assert w1 == w4
     for i in range(len(systems)):
-        assert r1[i] == r4[i], i
+        assert _same(r1[i], r4[i]), i
         assert np.array_equal(x1[i], x4[i]), i
 
 
