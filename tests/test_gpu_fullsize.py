@@ -5,6 +5,10 @@ that hold at any size, recomputed on the CPU from the returned solutions.
   7-point operator, GCRO-DR(80,20) with FP64 and FP32-stored basis, and GCRO-DR(60,20): the FP64 residual ||b - A x|| / ||b|| of every
   returned x, recomputed with the assembled CSR matrix, is at most rtol (1 + 1e-9); the 7-point
   operator matches the CSR product row by row on sampled rows, within 8 eps sum_j |a_ij x_j|.
+* Darcy 256^2, the whole sorted 400-system chain with GCRO-DR(60,20) (the bench workload in the
+  launch configuration the bench times): every returned x has FP64 residual ||b - A x|| / ||b|| at
+  most rtol (1 + 1e-9), recomputed on the CPU with the CSR matrix; every system converged and
+  reuses a recycle space (k_start > 0 after the first).
 * Advection-diffusion time-stepping at 512^2: one chain of 3 backward-Euler steps through the serving runtime;
   every step's residual, recomputed on the CPU, is at most rtol (1 + 1e-9), and the chain keeps its
   recycle space (fewer Arnoldi steps after the first).
@@ -61,6 +65,32 @@ def test_3d_128_residuals(env, m, mixed):
     ref = s.A[rows] @ xr
     bound = 8 * EPS * (abs(s.A[rows]) @ np.abs(xr))
     assert np.all(np.abs(y[rows] - ref) <= bound)
+
+
+def test_darcy256_full_chain_residuals(env):
+    torch, skr, ctx = env
+    log("[full] 256x256 Darcy, the sorted 400-system chain, GCRO-DR(60,20)")
+    from workloads import darcy_sequence
+    systems = darcy_sequence(256, 400)
+    P = param_matrix(systems)
+    order, _ = skr.skr_sort(ctx, torch.from_numpy(P).cuda(), P.shape[0], P.shape[1], 0)
+    del P
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=60, k=20, rtol=1e-8, maxit=40000)
+    assert rc == skr.SKR_OK
+    torch.cuda.synchronize()
+    worst = 0.0
+    for pos, i in enumerate(int(v) for v in order):
+        s, r = systems[i], res[i]
+        x = xs[i].cpu().numpy()
+        rel = np.linalg.norm(s.b - s.A @ x) / np.linalg.norm(s.b)
+        worst = max(worst, rel)
+        assert r["status"] == skr.SKR_CONVERGED, (pos, i, r)
+        assert rel <= 1e-8 * (1 + 1e-9), (pos, i, rel)
+        assert abs(rel - r["relres_true"]) <= 1e-3 * rel + 1e-16, (pos, i, rel, r["relres_true"])
+        assert pos == 0 or r["k_start"] > 0, (pos, i, r)
+    log(f"  400 systems converged, worst CPU-recomputed relres {worst:.3e}, "
+        f"mean steps {np.mean([r['iters'] for r in res]):.1f}")
 
 
 def test_advdiff_512_time_stepping(env):
