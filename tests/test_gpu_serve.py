@@ -159,6 +159,31 @@ def test_serve_assignment_and_parity(env, split, cap, max_chains):
         compare_chain(chain_sys, [res[i] for i in idx], [_X(xh[i]) for i in idx], ref, f"serve-chain{c}")
 
 
+def test_serve_mix_equals_alone(env):
+    """Every chain of a served mix (two sizes interleaved, several chains of each size, four workers)
+    gives results and solutions identical bit for bit to the same systems solved alone, in chain
+    order, by skr_solve_sequence on a fresh context."""
+    torch, skr = env
+    log("[serve] each chain of the mix against the chain alone")
+    systems = _stream(seed=13, count=8)
+    res, xh, where, stats = _serve(torch, skr, systems, split=0.02, workers=4)
+    chains = sorted({c for c, _ in where})
+    assert len(chains) >= 3
+    for c in chains:
+        idx = sorted((p, i) for i, (cc, p) in enumerate(where) if cc == c)
+        idx = [i for _, i in idx]
+        ctx = make_ctx(torch)
+        try:
+            ops, bs, xs, _ = _upload(torch, [systems[i] for i in idx])
+            rc, ref = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=20000)
+            torch.cuda.synchronize()
+            for q, i in enumerate(idx):
+                assert _same(res[i], ref[q]), (c, q, i)
+                assert np.array_equal(xh[i], xs[q].cpu().numpy()), (c, q, i)
+        finally:
+            skr.skr_ctx_destroy(ctx)
+
+
 def test_serve_workers_do_not_change_results(env):
     torch, skr = env
     log("[serve] 1 worker vs 4 workers, bitwise")
