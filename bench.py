@@ -333,7 +333,7 @@ def main():
         advdiff_bench(a)
         return
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} is not supported: this build measures one GPU. Sorted chains "
+        print(f"bench.py: --gpus {a.gpus} is not supported: the benchmark measures one GPU. Sorted chains "
               "would shard across GPUs without communication (contiguous slices of the sorted order).",
               file=sys.stderr)
         sys.exit(2)
