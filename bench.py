@@ -445,6 +445,9 @@ def main():
     maxit_hits = sum(r["status"] == skr.SKR_MAXIT for r in res)
     value = a.steps * converged / elapsed
     iters = [r["iters"] for r in res]
+    secs = np.array([r["seconds"] for r in res]) * 1e3
+    per_system_ms = dict(p50=round(float(np.percentile(secs, 50)), 2), p99=round(float(np.percentile(secs, 99)), 2),
+                         max=round(float(secs.max()), 2), first=round(float(secs[int(order[0])]), 2)) if len(secs) else None
     prof = skr.skr_profile_get(ctx)
     kern = {}
     for name, kst in prof["kernels"].items():
@@ -598,6 +601,7 @@ def main():
         "cpu_baseline": cpu,
         "converged": converged,
         "maxit_hits": maxit_hits,
+        "per_system_ms": per_system_ms,
         "iters_mean": float(np.mean(iters)),
         "iters_total": int(np.sum(iters)),
         "sort_ms": round(sort_ms, 2),
