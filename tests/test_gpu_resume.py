@@ -116,3 +116,27 @@ def test_resume_errors(env):
         assert rc == skr.SKR_OK and all(r["k_start"] == 0 for r in res)
     finally:
         skr.skr_ctx_destroy(ctx)
+
+
+def test_split_chain_bench_size(env):
+    """256^2 Darcy, the first 4 systems of a seeded chain with GCRO-DR(60,20) (the bench's system size
+    and launch configuration), split after 2: bitwise equal to the uninterrupted chain."""
+    torch, skr = env
+    log("[resume] 256x256, 4 systems, GCRO-DR(60,20), split after 2")
+    chain = darcy_sequence(256, 4, first_seed=300)
+    n = chain[0].n
+    ctx, ctx1, ctx2 = make_ctx(torch), make_ctx(torch), make_ctx(torch)
+    try:
+        ref, xref = _solve(torch, skr, ctx, chain, 60, 20, 0)
+        r1, x1 = _solve(torch, skr, ctx1, chain[:2], 60, 20, 0)
+        kk = skr.skr_recycle_get(ctx1)
+        U = torch.empty((max(kk, 1), n), dtype=torch.float64, device="cuda:0")
+        skr.skr_recycle_get(ctx1, U)
+        skr.skr_recycle_set(ctx2, U, n, kk, 60, 20)
+        r2, x2 = _solve(torch, skr, ctx2, chain[2:], 60, 20, skr.SKR_FLAG_CONTINUE)
+        for pos, (r, x) in enumerate(zip(r1 + r2, x1 + x2)):
+            assert _same(r, ref[pos]), (pos, r, ref[pos])
+            assert np.array_equal(x, xref[pos]), pos
+    finally:
+        for c in (ctx, ctx1, ctx2):
+            skr.skr_ctx_destroy(c)
