@@ -110,6 +110,46 @@ def test_sort_darcy256_400sys_sampled(env):
         assert d2[t] == dd.min()
 
 
+def _check_sampled_walk(P, order, d2, samples):
+    """The permutation whole; every step distance bitwise against the oracle's exact distance; at
+    the sampled steps, the arg-min over the remaining systems re-derived by the oracle; at every
+    zero-distance step, the lowest remaining index among the exact duplicates of the current row."""
+    N = P.shape[0]
+    assert order[0] == 0 and np.array_equal(np.sort(order), np.arange(N))
+    for t in range(1, N):
+        assert d2[t] == oracle.sq_distance(P[order[t - 1]], P[order[t]]), t
+    visited = np.zeros(N, dtype=bool)
+    visited[order[0]] = True
+    for t in range(1, N):
+        cur = order[t - 1]
+        if t in samples:
+            left = np.flatnonzero(~visited)
+            dd = np.array([oracle.sq_distance(P[cur], P[j]) for j in left])
+            assert order[t] == left[np.flatnonzero(dd == dd.min())[0]], t
+        if d2[t] == 0.0:
+            left = np.flatnonzero(~visited)
+            dup = left[np.all(P[left] == P[cur], axis=1)]
+            assert order[t] == dup.min(), t
+        visited[order[t]] = True
+
+
+def test_sort_4096_clustered_sampled(env):
+    """N = 4096 (32,896 distance tiles, a 4,095-step walk): p = 24 vectors in 64 clusters of
+    different spread, with 40 exact duplicates (ties at distance 0 resolved to the lowest index)."""
+    torch, skr, ctx = env
+    log("[sort] N=4096 p=24 clustered, with duplicates")
+    rng = np.random.default_rng(4096)
+    centers = 10.0 * rng.standard_normal((64, 24))
+    lab = rng.integers(0, 64, 4096)
+    P = centers[lab] + np.exp(rng.uniform(-6, 0, (4096, 1))) * rng.standard_normal((4096, 24))
+    src = rng.integers(0, 4096, 40)
+    dst = rng.choice(4096, 40, replace=False)
+    P[dst] = P[src]
+    order, d2 = _sort_gpu(torch, skr, ctx, P)
+    assert np.count_nonzero(d2[1:] == 0.0) >= 10
+    _check_sampled_walk(P, order, d2, {1, 2, 3, 1000, 2047, 2048, 3071, 4093, 4094, 4095})
+
+
 # ------------------------------------------------------------------------------------------ solves
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
 def test_solve_darcy32_chain(env, kind):

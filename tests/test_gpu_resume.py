@@ -140,3 +140,42 @@ def test_split_chain_bench_size(env):
     finally:
         for c in (ctx, ctx1, ctx2):
             skr.skr_ctx_destroy(c)
+
+
+def test_rhs_in_recycled_range(env):
+    """The start-up's closed form (App. B.1) on the device: a right-hand side b = A U_k c lies in
+    range(C_k), so a continued chain solves it by the projection alone (no Arnoldi step,
+    x = U_k R^-1 C_k^T b), as the oracle does from the same read-back U_k. The residual left is at
+    rounding level; the solution is within the residual bound of both U_k c and the oracle's."""
+    import types
+    torch, skr = env
+    log("[resume] b in range(A U_k): zero Arnoldi steps")
+    s = darcy_sequence(32, 1, first_seed=33)[0]
+    n = s.n
+    ctx = make_ctx(torch)
+    try:
+        _solve(torch, skr, ctx, [s], 30, 10, 0)
+        kk = skr.skr_recycle_get(ctx)
+        assert kk == 10
+        U = torch.empty((kk, n), dtype=torch.float64, device="cuda:0")
+        skr.skr_recycle_get(ctx, U)
+        Uh = U.cpu().numpy().T.copy()
+        u = Uh @ np.random.default_rng(7).standard_normal(kk)
+        b1 = s.A @ u
+        sys1 = types.SimpleNamespace(A=s.A, b=b1, n=n, N_g=s.N_g)
+        res, xs = _solve(torch, skr, ctx, [sys1], 30, 10, skr.SKR_FLAG_CONTINUE)
+        g = res[0]
+        o = oracle.gcrodr(s.A, b1, Uh, 30, 10, 1e-8, 20000)
+        log(f"  gpu: status {g['status']} iters {g['iters']} k_start {g['k_start']} relres {g['relres_true']:.2e};"
+            f" oracle iters {o.iters} relres {o.relres_true:.2e}")
+        assert o.status == oracle.CONVERGED and o.iters == 0 and o.k_start == kk
+        assert g["status"] == skr.SKR_CONVERGED and g["iters"] == 0 and g["cycles"] == 0
+        assert g["k_start"] == kk and g["rank_dropped"] == 0
+        assert g["spmv"] == kk + 1            # A U_k at the start-up and the true residual
+        assert g["relres_true"] <= 1e-12
+        for ref, rr in ((u, np.linalg.norm(b1 - s.A @ u) / np.linalg.norm(b1)), (o.x, o.relres_true)):
+            bound, _ = solution_bound(s.A, b1, ref, g["relres_true"], rr)
+            assert np.linalg.norm(xs[0] - ref) / np.linalg.norm(ref) <= bound
+        assert skr.skr_recycle_get(ctx) == kk
+    finally:
+        skr.skr_ctx_destroy(ctx)
