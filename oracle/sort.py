@@ -1,20 +1,21 @@
-"""Greedy nearest-neighbour sort of the systems (Alg. 1, "The Sorting Algorithm", Sec. 4.1).
+"""Greedy nearest-neighbour ordering of the systems (Alg. 1, Sec. 4.1).
 
 Oracle (test infrastructure only).
 
-Alg. 1 starts at the first system, then repeatedly appends the not-yet-visited system whose
-parameter matrix is closest, in Frobenius norm, to that of the system appended last.
+What Alg. 1 computes: the order begins with a chosen first system; after that, each position is
+filled by the system, among those not placed yet, whose parameter matrix lies nearest in the
+Frobenius norm to the parameter matrix of the system placed just before it.
 
 Readings taken where the paper is loose:
-* The running minimum starts at +infinity (the paper's "a large number, e.g. 1000" would leave
-  the choice undefined once every distance exceeds 1000).
-* Candidates are scanned in ascending original index with a strict "<", so ties go to the
-  lowest index. If no candidate has a finite distance, the lowest remaining index is taken.
-* The comparison uses the squared distance (the square root is monotone, so the order is the
-  same). The squared distance is defined as the exact sum over all entries of the squares of the
-  FP64 differences fl(a_i[p] - a_j[p]), rounded once to FP64. Each square is split exactly into
-  two doubles (Dekker's product with Veltkamp splitting) and ``math.fsum`` returns the correctly
-  rounded sum, so the value does not depend on any summation order.
+* The paper seeds its running minimum with a finite constant; here nothing is compared against a
+  constant, so the choice is defined even when every distance is large.
+* Ties go to the lowest original index. NaN distances never win; when no candidate has a finite
+  distance, the lowest unplaced index is taken.
+* Squared distances are compared (the square root is monotone). The squared distance is defined
+  as the exact sum, over all entries, of the squares of the FP64 differences fl(a_i[p] - a_j[p]),
+  rounded once to FP64. Each square is split exactly into two doubles (Dekker's product with
+  Veltkamp splitting) and ``math.fsum`` returns the correctly rounded sum, so the value does not
+  depend on any summation order.
 """
 from __future__ import annotations
 
@@ -44,8 +45,24 @@ def sq_distance(pi: np.ndarray, pj: np.ndarray) -> float:
     return math.fsum(np.concatenate([hi, lo]).tolist())
 
 
+def _nearest_unplaced(row: list, placed: np.ndarray) -> int:
+    """Index of the smallest entry of ``row`` among the unplaced indices (lowest index on ties,
+    NaN never chosen; the lowest unplaced index when none is finite or below +inf)."""
+    best_i, best_d = -1, math.inf
+    for i, d in enumerate(row):
+        if placed[i]:
+            continue
+        if best_i < 0 and not (d < math.inf):
+            continue
+        if best_i < 0 or d < best_d:
+            best_i, best_d = i, d
+    if best_i < 0:
+        best_i = int(np.flatnonzero(~placed)[0])
+    return best_i
+
+
 def greedy_sort(params: np.ndarray, start: int = 0, return_dist: bool = False):
-    """Alg. 1 on an (N, p) array of flattened parameter matrices.
+    """Greedy nearest-neighbour order (Alg. 1) of an (N, p) array of flattened parameter matrices.
 
     Returns the visiting order (int64 array, first element ``start``) and, with ``return_dist``,
     the squared distance of every step (entry 0 is 0.0).
@@ -57,23 +74,17 @@ def greedy_sort(params: np.ndarray, start: int = 0, return_dist: bool = False):
         return (order, np.zeros(0)) if return_dist else order
     if not 0 <= start < N:
         raise ValueError("start out of range")
-    remaining = [j for j in range(N) if j != start]      # seq_0 with the start removed
-    order = [start]                                       # seq_mat
-    dists = [0.0]
-    cur = start
-    for _ in range(N - 1):
-        best = math.inf
-        jmin = None
-        for j in remaining:
-            dj = sq_distance(params[cur], params[j])
-            if dj < best:
-                best, jmin = dj, j
-        if jmin is None:
-            jmin = remaining[0]
-            best = sq_distance(params[cur], params[jmin])
-        remaining.remove(jmin)
-        order.append(jmin)
-        dists.append(best)
-        cur = jmin
-    order = np.asarray(order, dtype=np.int64)
-    return (order, np.asarray(dists)) if return_dist else order
+    placed = np.zeros(N, dtype=bool)
+    placed[start] = True
+    order = np.empty(N, dtype=np.int64)
+    step_d2 = np.zeros(N)
+    order[0] = start
+    for t in range(1, N):
+        prev = int(order[t - 1])
+        # distances from the system placed last to every system (placed ones are skipped)
+        row = [math.nan if placed[i] else sq_distance(params[prev], params[i]) for i in range(N)]
+        nxt = _nearest_unplaced(row, placed)
+        placed[nxt] = True
+        order[t] = nxt
+        step_d2[t] = row[nxt]
+    return (order, step_d2) if return_dist else order
