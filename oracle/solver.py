@@ -81,6 +81,8 @@ class SolveResult:
     Y_next: np.ndarray | None = None
     C_last: np.ndarray | None = None                   # C_k matching Y_next (A Y_next = C_last)
     res_history: list = field(default_factory=list)   # ||r|| after the start and after each cycle
+    restarts: int = 0          # cycles started from a true residual after a failed exit test
+    cycle_log: list = field(default_factory=list)     # keep_cycles: (||r|| at the cycle start, C after it)
 
 
 def qr_pos(M: np.ndarray):
@@ -232,14 +234,41 @@ def startup(A, Y: np.ndarray, r0: np.ndarray, store=_keep):
     return x1, r1, C, U, dropped
 
 
+def project_onto_c(x: np.ndarray, r: np.ndarray, C, U):
+    """x + U C^T r and r - C C^T r (App. B.1, the projection of a system start); identity without C."""
+    if C is None:
+        return x, r
+    c = C.T @ r
+    return x + U @ c, r - C @ c
+
+
+# ----------------------------------------------------------------------------------------------
+# Cycle-end matrices (Alg. 2, while body)
+# ----------------------------------------------------------------------------------------------
+def cycle_matrices(C: np.ndarray, U: np.ndarray, V: np.ndarray, Hbar: np.ndarray, B: np.ndarray):
+    """G, W^ and V^ of a GCRO-DR cycle of j steps: D_k scales U to unit columns, V^ = [U D_k, V_j],
+    W^ = [C, V_{j+1}] and G = [[D_k, B], [0, Hbar]], so that A V^ = W^ G (Eq. 6 with A U = C)."""
+    kc = C.shape[1]
+    j = Hbar.shape[1]
+    d = 1.0 / np.linalg.norm(U, axis=0)               # D_k: U D_k has unit columns
+    Vhat = np.hstack([U * d[None, :], V[:, :j]])
+    What = np.hstack([C, V])
+    G = np.zeros((kc + j + 1, kc + j))
+    G[:kc, :kc] = np.diag(d)
+    G[:kc, kc:] = B
+    G[kc:, kc:] = Hbar
+    return G, What, Vhat
+
+
 # ----------------------------------------------------------------------------------------------
 # One system
 # ----------------------------------------------------------------------------------------------
 def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 10,
            rtol: float = 1e-8, maxit: int = 10000, full_cycles: bool = False,
-           basis_fp32: bool = False) -> SolveResult:
+           basis_fp32: bool = False, keep_cycles: bool = False) -> SolveResult:
     """Solve A x = b from x0 = 0, recycling span(Y) (App. B.2, Alg. 2). Returns the next Y in Y_next.
-    ``basis_fp32`` selects the mixed-precision mode described in the module notes."""
+    ``basis_fp32`` selects the mixed-precision mode described in the module notes; ``keep_cycles``
+    records, per cycle, the residual norm it started from and the recycle space C it left."""
     if k < 0 or m <= k or rtol <= 0:
         raise ValueError("need 0 <= k < m and rtol > 0")
     b = np.asarray(b, dtype=np.float64)
@@ -253,15 +282,19 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
     tol_abs = rtol * bnorm
     store = fp32_store if basis_fp32 else _keep
     r = b.copy()
-    r_is_true = True                 # r equals b - A x computed directly (x = 0 here)
+    r_fresh = True                   # r is b - A x computed directly (x = 0 here) or just projected
     C = U = None
     spmv = iters = cycles = 0
     k_start = dropped = 0
+    restarts = 0
+    cycle_log = []
     if k > 0 and Y is not None and Y.shape[1] > 0:
         x, r, C, U, dropped = startup(A, Y, r, store)
         spmv += Y.shape[1]
         k_start = 0 if C is None else C.shape[1]
-        r_is_true = C is None
+        # r was just projected; with FP32-stored C and U the first cycle still refines from the
+        # true residual (A U equals C only to FP32 rounding)
+        r_fresh = C is None or not basis_fp32
     hist = [float(np.linalg.norm(r))]
     est = hist[0]
     status = None
@@ -274,22 +307,27 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
         if rt_norm <= tol_abs:
             status = CONVERGED
         else:
-            r = rt
-            r_is_true = True
+            x, r = project_onto_c(x, rt, C, U)
+            r_fresh = True
+            restarts += 1
     while status is None:
         if iters >= maxit:
             status = MAXIT
             break
-        if basis_fp32 and not r_is_true:
-            # refinement step: the cycle corrects the FP64 iterate from its true residual, first
-            # projected onto range(C) as at a system start (App. B.1): x += U C^T r, r -= C C^T r
-            r = b - A @ x
-            spmv += 1
-            if C is not None:
-                c = C.T @ r
-                x = x + U @ c
-                r = r - C @ c
-        r_is_true = False
+        if not r_fresh:
+            if basis_fp32:
+                # refinement step: the cycle corrects the FP64 iterate from its true residual,
+                # projected onto range(C) as at a system start (App. B.1)
+                spmv += 1
+                x, r = project_onto_c(x, b - A @ x, C, U)
+            else:
+                # the same projection of the current residual (x += U C^T r, r -= C C^T r): zero in
+                # exact arithmetic, where r stays orthogonal to C; in floating point it removes the
+                # rounding-level component along C that a cycle leaves in r, which would otherwise
+                # persist at a fixed absolute size and, relative to the shrinking residual, tilt
+                # v1 = r/||r|| (and with it the next C) out of orthogonality
+                x, r = project_onto_c(x, r, C, U)
+        r_fresh = False
         s = m if C is None else m - C.shape[1]
         s = min(s, maxit - iters)
         V, Hbar, B, est, breakdown = arnoldi_cycle(A, r, C, s, tol_abs, full_cycles, store)
@@ -314,15 +352,7 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
                     U = store(sla.solve_triangular(R, Yt.T, trans="T", lower=False).T)
         else:
             # GCRO-DR cycle (Alg. 2, while body)
-            kc = C.shape[1]
-            d = 1.0 / np.linalg.norm(U, axis=0)               # D_k: U D_k has unit columns
-            Ut = U * d[None, :]
-            Vhat = np.hstack([Ut, V[:, :j]])
-            What = np.hstack([C, V])
-            G = np.zeros((kc + j + 1, kc + j))
-            G[:kc, :kc] = np.diag(d)
-            G[:kc, kc:] = B
-            G[kc:, kc:] = Hbar
+            G, What, Vhat = cycle_matrices(C, U, V, Hbar, B)
             rhs = What.T @ r
             y = np.linalg.lstsq(G, rhs, rcond=None)[0]
             x = x + Vhat @ y
@@ -334,6 +364,8 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
                 C = store(What @ Q)
                 U = store(sla.solve_triangular(R, Yt.T, trans="T", lower=False).T)
         hist.append(float(np.linalg.norm(r)))
+        if keep_cycles:
+            cycle_log.append((beta, None if C is None else C.copy()))
         if est <= tol_abs or breakdown:
             rt = b - A @ x
             spmv += 1
@@ -341,14 +373,20 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
             if rt_norm <= tol_abs:
                 status = BREAKDOWN if breakdown else CONVERGED
                 break
-            r = rt
-            r_is_true = True
+            # the estimate met the tolerance but the true residual does not (rounding drift): go on
+            # from the true residual, projected onto range(C) as at a system start (App. B.1), so
+            # that the next cycle's v1 is orthogonal to C as the cycle's least-squares problem and
+            # the structure of W^T V^ assume
+            x, r = project_onto_c(x, rt, C, U)
+            r_fresh = True
+            restarts += 1
     if status == MAXIT:
         rt_norm = float(np.linalg.norm(b - A @ x))
         spmv += 1
     Y_next = U if (k > 0 and U is not None) else None
     return SolveResult(x, status, iters, cycles, spmv, rt_norm / bnorm, float(est / bnorm),
-                       k_start, dropped, Y_next, C if Y_next is not None else None, hist)
+                       k_start, dropped, Y_next, C if Y_next is not None else None, hist, restarts,
+                       cycle_log)
 
 
 def gmres(A, b, m: int = 30, rtol: float = 1e-8, maxit: int = 10000) -> SolveResult:

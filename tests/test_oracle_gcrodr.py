@@ -5,12 +5,13 @@ update, a transposed operand in the eigenproblem, a mis-applied D_k scaling) bre
 """
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from oracle import (BREAKDOWN, CONVERGED, MAXIT, NONFINITE, gcrodr, gmres,
                     harmonic_ritz_generalized, harmonic_ritz_standard, solve_sequence)
-from oracle.solver import arnoldi_cycle, qr_pos, startup
+from oracle.solver import arnoldi_cycle, cycle_matrices, qr_pos, select_smallest, startup
 from workloads import darcy_sequence
 
 
@@ -140,6 +141,77 @@ def test_harmonic_ritz_eigen_residual_and_bounds(darcy16):
     assert np.max(np.abs(th)) <= np.sort(np.abs(tall))[8] * (1 + 1e-12)
 
 
+# ------------------------------------------------- generalized harmonic Ritz, nonsymmetric, k > 0
+def _gcrodr_cycle(seed):
+    """One GCRO-DR cycle with a nonempty C on a nonsymmetric operator: C, U from the start-up with the
+    recycle space of a neighbouring system, 20 Arnoldi steps, and the cycle-end matrices."""
+    A0, A1 = convdiff(12, seed=2 * seed), convdiff(12, seed=2 * seed + 1)
+    b = np.ones(A0.shape[0])
+    Y = gcrodr(A0, b, None, 30, 8, 1e-10, 3000).Y_next
+    _, r1, C, U, _ = startup(A1, Y, b)
+    V, Hb, B, _, brk = arnoldi_cycle(A1, r1, C, 20, 0.0)
+    assert C.shape[1] >= 6 and not brk
+    G, What, Vhat = cycle_matrices(C, U, V, Hb, B)
+    return A1, G, What, Vhat
+
+
+def _harmonic_ritz_violation(A, Vhat, P, theta):
+    """Largest relative violation of the harmonic Ritz condition (A y - theta y) orthogonal to
+    range(A V^), y = V^ z, with A applied explicitly. A conjugate pair is the column pair (Re z, Im z)
+    listed with theta first."""
+    AVh = A @ Vhat
+    worst, c = 0.0, 0
+    while c < P.shape[1]:
+        t = theta[c]
+        if np.imag(t) != 0.0:
+            z, step = P[:, c] + 1j * P[:, c + 1], 2
+        else:
+            z, step, t = P[:, c], 1, np.real(t)
+        y = Vhat @ z
+        Ay = A @ y
+        worst = max(worst, np.linalg.norm(AVh.T @ (Ay - t * y)) / np.linalg.norm(AVh.T @ Ay))
+        c += step
+    return worst
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cycle_matrices_satisfy_the_cycle_relation(seed):
+    # A V^ = W^ G (Alg. 2 while body; Eq. 6 with A U = C), with A applied explicitly: pins D_k, B
+    # and Hbar in G and the column order of V^ and W^
+    A, G, What, Vhat = _gcrodr_cycle(seed)
+    assert np.linalg.norm(A @ Vhat - What @ G) <= 1e-12 * spla.norm(A) * np.linalg.norm(Vhat)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_generalized_harmonic_ritz_nonsymmetric(seed):
+    A, G, What, Vhat = _gcrodr_cycle(seed)
+    k = 8
+    P, th = harmonic_ritz_generalized(G, What.T @ Vhat, k)
+    assert P.shape[1] in (k - 1, k)
+    # each selected pair satisfies the harmonic Ritz condition with the explicit operator
+    assert _harmonic_ritz_violation(A, Vhat, P, th) <= 1e-9
+    # the selected values are the smallest-modulus eigenvalues of the pencil
+    # ((A V^)^T (A V^), (A V^)^T V^) formed from explicit products
+    AVh = A @ Vhat
+    ev = sla.eigvals(AVh.T @ AVh, AVh.T @ Vhat)
+    ev = ev[np.isfinite(ev)]
+    ev = ev[np.argsort(np.abs(ev), kind="stable")]
+    for t in th:
+        assert np.min(np.abs(ev[:P.shape[1] + 1] - t)) <= 1e-8 * abs(t)
+    assert np.max(np.abs(th)) <= np.abs(ev[P.shape[1] - 1]) * (1 + 1e-8)
+    if P.shape[1] == k - 1:          # only when the k-th is half of a conjugate pair
+        assert np.imag(ev[k - 1]) != 0.0 and abs(ev[k - 1] - np.conj(ev[k])) <= 1e-8 * abs(ev[k - 1])
+
+
+def test_generalized_harmonic_ritz_pin_detects_a_transposed_operand():
+    # the same selection from the pencil (G^T G, (W^T V)^T G), whose eigenvalues are the same but
+    # whose eigenvectors are not, must fail the harmonic Ritz condition above
+    A, G, What, Vhat = _gcrodr_cycle(0)
+    WtV = What.T @ Vhat
+    Pm, thm = select_smallest(*sla.eig(G.T @ G, WtV.T @ G), 8)
+    assert _harmonic_ritz_violation(A, Vhat, Pm, thm) > 1e-3
+
+
 def test_complex_pair_handling():
     # 2x2 rotation block has eigenvalues +-i (a conjugate pair of modulus 1), plus reals 0.5, 3.
     M = np.zeros((4, 4)); M[0, 1], M[1, 0] = -1.0, 1.0; M[2, 2] = 0.5; M[3, 3] = 3.0
@@ -187,10 +259,53 @@ def test_recycle_space_relations_after_solve(darcy16, m, k):
     r = gcrodr(A, b, None, m, k, 1e-10, 5000)
     U, C = r.Y_next, r.C_last
     assert U.shape == (A.shape[0], k) and C.shape == U.shape
-    # v1 = r/||r|| carries the rounding of r = r - W G y, of size eps*||b||, along C: relative to the
-    # shrinking residual it grows to ~eps/relres, so C's orthonormality is bounded through relres.
-    assert np.abs(C.T @ C - np.eye(k)).max() <= 1e-13 / r.relres_true
+    assert np.abs(C.T @ C - np.eye(k)).max() <= 1e-12
     assert np.linalg.norm(A @ U - C) <= 1e-10 * spla.norm(A) * np.linalg.norm(U)
+
+
+@pytest.mark.parametrize("kind", ["darcy", "convdiff"])
+def test_c_orthonormal_after_every_cycle(kind):
+    # C^T C = I to 1e-12 after every cycle end of a chain solved to 1e-12 (the projection of r at
+    # each cycle start keeps v1 orthogonal to C; without it the loss grows like eps / relres)
+    if kind == "darcy":
+        seq = darcy_sequence(32, 3)
+        As, bs = [s.A for s in seq], [s.b for s in seq]
+    else:
+        As, bs = [convdiff(14, seed=s) for s in range(3)], [np.ones(196)] * 3
+    Y, ncyc = None, 0
+    for A, b in zip(As, bs):
+        r = gcrodr(A, b, Y, 30, 10, 1e-12, 5000, keep_cycles=True)
+        assert r.status == CONVERGED and r.relres_true <= 1e-12
+        for _, C in r.cycle_log:
+            if C is not None:
+                assert np.abs(C.T @ C - np.eye(C.shape[1])).max() <= 1e-12
+                ncyc += 1
+        Y = r.Y_next
+    assert ncyc >= 8
+
+
+def test_restart_from_true_residual():
+    # rtol 1e-13 on 32^2 Darcy: the estimate meets the tolerance before the true residual does, so
+    # the solve goes on from the true residual projected onto range(C) (App. B.1), and still
+    # converges with C orthonormal
+    seq = darcy_sequence(32, 2)
+    Y, restarts = None, 0
+    for s in seq:
+        r = gcrodr(s.A, s.b, Y, 30, 10, 1e-13, 5000, keep_cycles=True)
+        assert r.status == CONVERGED and r.relres_true <= 1e-13
+        assert all(np.abs(C.T @ C - np.eye(C.shape[1])).max() <= 1e-12 for _, C in r.cycle_log if C is not None)
+        restarts += r.restarts
+        Y = r.Y_next
+    assert restarts >= 1
+
+
+def test_unattainable_tolerance_stagnates_without_diverging():
+    # rtol 1e-15 is below the attainable accuracy of FP64 on this system: the solve must stop at
+    # maxit near the attainable residual, not diverge
+    s = darcy_sequence(32, 1)[0]
+    r = gcrodr(s.A, s.b, None, 30, 10, 1e-15, 600)
+    assert r.status == MAXIT and np.isfinite(r.relres_true) and r.relres_true <= 1e-12
+    assert max(r.res_history[1:]) <= r.res_history[0]
 
 
 def test_span_invariance(darcy16):
