@@ -168,6 +168,14 @@ int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64
  *  x_dev:  host array of N device pointers, out, solutions (n FP64 each).
  *  order:  host array of N int64 (a permutation), or NULL for 0..N-1.
  *  results_host: out, N entries at the original indices.
+ * Every cycle that follows another starts from a residual projected onto the orthogonal complement
+ * of range(C_k) (x += U_k C_k^T r, r -= C_k C_k^T r, the start-up step of App. B.1): zero in exact
+ * arithmetic, it keeps the cycle's first Krylov vector orthogonal to C_k in floating point, and so
+ * C_k orthonormal and the solve stable down to the attainable accuracy. When the least-squares
+ * estimate meets rtol but the true residual does not, the solve goes on from the projected true
+ * residual. For the cycle-end eigenproblem the symmetric eigen stage is used only for an exactly
+ * symmetric operator (the stencil kinds, or a CSR matrix that passes an exact check at the system
+ * start); any other operator takes the general stage.
  * Returns SKR_OK, SKR_WARN_NOTCONVERGED if some system hit maxit, or an error
  * (SKR_EINVAL, SKR_ENOMEM, SKR_EHIP). A system with NaN/Inf in b or A gets status
  * SKR_NONFINITE and x = 0; the sequence goes on.
@@ -225,6 +233,12 @@ typedef struct {
     int64_t steps;        /* Arnoldi steps run by profiled solves                 */
     int64_t cycles;       /* Arnoldi cycles run by profiled solves                */
     double step_bytes;    /* algorithmic bytes of all those steps (A + B + C)     */
+    /* Cycle ends that formed a recycle space (Alg. 2, harmonic Ritz step), counted for every solve
+     * on the context (profiled or not), by the eigen stage that formed it: the symmetric stage
+     * (taken only when the operator is exactly symmetric: a stencil kind, or a CSR matrix that
+     * passes an exact check at the system start) or the general one. */
+    int64_t eig_symmetric;
+    int64_t eig_general;
 } skr_profile;
 
 /* Copy the statistics accumulated since the last reset into *out (host pointer). */

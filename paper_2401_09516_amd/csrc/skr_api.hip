@@ -18,6 +18,7 @@ struct ColList;
 void launch_init(hipStream_t, const Work&, const double*, double*, double);
 void launch_clear_nonfinite(hipStream_t, const Work&);
 void launch_check_finite(hipStream_t, const Work&, const double*, long);
+void launch_check_sym(hipStream_t, const Work&, const DevOp&);
 void launch_zero(hipStream_t, double*, int);
 void launch_copy_u(hipStream_t, const Work&, double*, long, int, int);
 void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int, hipEvent_t* ev);
@@ -228,6 +229,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     launch_init(s, w, b, x, rtol);
     if (op.kind == SKR_OP_CSR) {
         launch_check_finite(s, w, op.val, (long)nvals);
+        launch_check_sym(s, w, op);
     } else {
         const long nzl = op.kind == SKR_OP_STENCIL7 ? (long)op.nz : 1L;
         launch_check_finite(s, w, op.ax, nzl * op.ny * (op.nx + 1));
@@ -276,29 +278,49 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     }
     int status = -1;
     double est = hc.beta;
-    // r equals b - A x computed directly (at x = 0, or right after a true-residual product)
-    bool r_is_true = kc == 0;
+    // r is fresh: b - A x computed directly (at x = 0), or just projected onto range(C)'s
+    // complement. With FP32-stored C and U the first cycle still refines from the true residual
+    // (A U equals C only to FP32 rounding).
+    bool r_fresh = kc == 0 || !w.mixed;
     int prev_jd = 0, prev_scyc = 0;     // launch-length prediction (see the cycle loop)
     double prev_rate = 0.0;
+    // A failed exit test goes on from the true residual, projected onto range(C) as at a system
+    // start (App. B.1): the next cycle's v_0 must be orthogonal to C, which the cycle-end
+    // eigenproblem's block structure of W^T V assumes.
+    auto restart_from_true = [&]() -> int {
+        r_fresh = true;
+        if (kc > 0) {
+            launch_startup_project(s, w, x, kc, 1);
+            HIPLAUNCHCHK();
+            return read_ctrl(ctx);
+        }
+        return SKR_OK;
+    };
     if (hc.beta <= tol_abs) {
         launch_true_residual(s, w, op, b, x);
         HIPLAUNCHCHK();
         if ((rc = read_ctrl(ctx))) return rc;
         spmv += 1;
         if (std::sqrt(hc.res2) <= tol_abs) status = SKR_CONVERGED;
-        r_is_true = true;
+        else if ((rc = restart_from_true())) return rc;
     }
     // ---- Arnoldi cycles (Alg. 2)
     while (status < 0) {
         if (iters >= maxit) { status = SKR_MAXIT; break; }
-        if (w.mixed && !r_is_true) {
-            // refinement step: true FP64 residual, projected onto range(C) as at a system start
-            launch_true_residual(s, w, op, b, x);
-            spmv += 1;
+        if (!r_fresh) {
+            if (w.mixed) {
+                // refinement step: true FP64 residual, projected onto range(C) as at a system start
+                launch_true_residual(s, w, op, b, x);
+                spmv += 1;
+            }
+            // x += U C^T r, r -= C C^T r (App. B.1's projection): zero in exact arithmetic; it
+            // removes the rounding-level component along C that a cycle leaves in r, which would
+            // otherwise persist at a fixed absolute size and, relative to the shrinking residual,
+            // tilt v_0 = r/||r|| and the next C out of orthogonality
             if (kc > 0) launch_startup_project(s, w, x, kc, 1);
             HIPLAUNCHCHK();
         }
-        r_is_true = false;
+        r_fresh = false;
         int scyc = (kc == 0) ? m : m - kc;
         scyc = (int)std::min<int64_t>(scyc, maxit - iters);
         // Launch length. A step launched after the cycle has stopped exits at once, but still costs a
@@ -343,6 +365,8 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
         if ((rc = read_ctrl(ctx))) return rc;
         const int jd = hc.j_done;
         if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
+        if (hc.route == 1) ctx->prof.eig_symmetric++;
+        else if (hc.route == 2) ctx->prof.eig_general++;
         if (profile) {
             skr_profile& pr = ctx->prof;
             for (int q = 0; q < nsamp; ++q) {
@@ -389,7 +413,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
                 status = brk ? SKR_BREAKDOWN : SKR_CONVERGED;
                 break;
             }
-            r_is_true = true;
+            if ((rc = restart_from_true())) return rc;
         }
     }
     if (status == SKR_MAXIT) {

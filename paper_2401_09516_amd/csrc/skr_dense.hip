@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 
     const bool recycle = k_target > 0 && (kc > 0 || jd > k_target);
     if (!recycle) {
-        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; dw->mode = DW_NONE; }
+        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; ctrl->route = 0; dw->mode = DW_NONE; }
         return;
     }
     // hand over R_G (d x d, upper), X'' (d x d), rotations and D_k
@@ -224,9 +224,11 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 }
 
 // Stage 2, symmetric case (4 wavefronts). M = X'' R_G^{-1} is formed; for symmetric A it is
-// symmetric in exact arithmetic (G^T G and G^T W-hat^T V-hat = V-hat^T A V-hat are), and when the
-// computed M is symmetric to sym_tol relative (1e-10 with an FP64 basis, 1e-4 with an FP32 one),
-// the wanted eigenpairs of S = (M + M^T)/2 are found by
+// symmetric in exact arithmetic (G^T G and G^T W-hat^T V-hat = V-hat^T A V-hat are). The route is
+// taken only for an operator that is exactly symmetric (ctrl->nonsym clear: a stencil kind, or a
+// CSR matrix that passed the check at the system start), and only when the computed M is also
+// symmetric to sym_tol relative (1e-10 with an FP64 basis, 1e-4 with an FP32 one, far above the
+// rounding of the stored columns). Then the wanted eigenpairs of S = (M + M^T)/2 are found by
 // Householder reduction to tridiagonal form T, multisection with Sturm counts for the eigenvalues
 // of T, twisted factorizations of T - lambda I for their eigenvectors, back-transformation through
 // the reflectors and modified Gram-Schmidt (a second pass when a column lost more than 30 % of
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
     if (t == 0) {
         double ga = red[0], gd = red2[0];
         for (int q = 1; q < DT / 64; ++q) { ga = fmax(ga, red[q]); gd = fmax(gd, red2[q]); }
-        sym_s = (gd <= sym_tol * ga) ? 1 : 0;
+        sym_s = (!ctrl->nonsym && gd <= sym_tol * ga) ? 1 : 0;
     }
     __syncthreads();
     // M goes to the general stage's input in any case: that stage takes over if this one declines
@@ -763,7 +765,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
         }
     }
     __syncthreads();
-    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 1; dw->mode = DW_DONE; }
 }
 
 // Stage 2, general (nonsymmetric) case, one wavefront: M = X'' R_G^{-1} was formed by the
@@ -1006,7 +1008,7 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
                 coef->Qc[r + o * LDQC] = (r == o) ? 1.0 : 0.0;
                 if (r < d) coef->Qu[r + o * LDQU] = (r == o) ? 1.0 : 0.0;
             }
-        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; dw->mode = DW_DONE; }
+        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; ctrl->route = 2; dw->mode = DW_DONE; }
         return;
     }
 
@@ -1171,7 +1173,7 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
         if (kc < d || d == 0) coef->Qc[kc + t * LDQC] = carry;
         for (int c = 0; c < kc; ++c) coef->Qc[c + t * LDQC] = Wv[c + t * LDW];
     }
-    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 2; dw->mode = DW_DONE; }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1281,7 +1283,7 @@ __global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ 
 
     const bool recycle = k_target > 0 && (kc > 0 || jd > k_target);
     if (!recycle) {
-        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; dw->mode = DW_NONE; }
+        if (t == 0) { ctrl->k_new = 0; ctrl->eig_fail = 0; ctrl->route = 0; dw->mode = DW_NONE; }
         return;
     }
     // hand over R_G (d x d, upper), X'' (d x d), rotations and D_k
@@ -1350,7 +1352,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol
     if (t == 0) {
         double ga = red[0], gd = red2[0];
         for (int q = 1; q < DT / 64; ++q) { ga = fmax(ga, red[q]); gd = fmax(gd, red2[q]); }
-        sym_s = (gd <= sym_tol * ga) ? 1 : 0;
+        sym_s = (!ctrl->nonsym && gd <= sym_tol * ga) ? 1 : 0;
     }
     __syncthreads();
     if (!sym_s) {
@@ -1771,7 +1773,7 @@ __global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol
         }
     }
     __syncthreads();
-    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 1; dw->mode = DW_DONE; }
 }
 
 // General stage for d > DSM. LDS regions: XR (X'', then M, then the Schur form T, then the
@@ -2041,7 +2043,7 @@ __global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, De
                 coef->Qc[r + o * LDQC] = (r == o) ? 1.0 : 0.0;
                 if (r < d) coef->Qu[r + o * LDQU] = (r == o) ? 1.0 : 0.0;
             }
-        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; dw->mode = DW_DONE; }
+        if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 1; ctrl->route = 2; dw->mode = DW_DONE; }
         return;
     }
 
@@ -2213,7 +2215,7 @@ __global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, De
         if (kc < d || d == 0) coef->Qc[kc + t * LDQC] = carry;
         for (int c = 0; c < kc; ++c) coef->Qc[c + t * LDQC] = Wv[c + t * LDL];
     }
-    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; dw->mode = DW_DONE; }
+    if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 2; dw->mode = DW_DONE; }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -2269,10 +2271,10 @@ void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_
     hipLaunchKernelGGL(k_dense_prep, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
                        (const double*)w.gram, kc, jd_max, k_target, w.coef, w.dense, w.ctrl);
     if (k_target > 0) {
-        // For a symmetric operator M is symmetric in exact arithmetic; its computed asymmetry is the
-        // rounding of the stored columns (FP64 storage: ~1e-15 relative, FP32 storage: up to ~1e-6
-        // on the Darcy workloads). The tolerance sits far above that and far below the asymmetry of
-        // a nonsymmetric operator (1e-2 and more on advection-diffusion).
+        // The symmetric stage runs only for an exactly symmetric operator (ctrl->nonsym). For one,
+        // M is symmetric in exact arithmetic and its computed asymmetry is the rounding of the
+        // stored columns (FP64 storage: ~1e-15 relative, FP32 storage: up to ~1e-6 on the Darcy
+        // workloads); the tolerance is a guard far above that.
         const double sym_tol = w.mixed ? 1e-4 : 1e-10;
         hipLaunchKernelGGL(k_dense_sym, dim3(1), dim3(DT), 0, s, k_target, sym_tol, w.coef, w.dense, w.ctrl);
         hipLaunchKernelGGL(k_dense_gen, dim3(1), dim3(64), 0, s, k_target, w.coef, w.dense, w.ctrl);

@@ -131,6 +131,9 @@ struct Ctrl {
     int k_new;       // recycled columns produced by the last cycle end
     int nonfinite;   // NaN/Inf seen in b or A
     int eig_fail;    // the small eigen solve did not converge (recycle space kept from before)
+    int nonsym;      // the operator is not exactly symmetric (CSR check at the system start;
+                     // the stencil kinds are symmetric by construction)
+    int route;       // eigen stage that formed the last recycle space: 1 symmetric, 2 general, 0 none
     int pad0;
     double bnorm;    // ||b||
     double tol_abs;  // rtol * ||b||
@@ -145,7 +148,7 @@ struct Ctrl {
 
 // Snapshot read back by the host after a cycle.
 struct CtrlHost {
-    int stop, j_done, breakdown, kc, k_new, nonfinite, eig_fail, pad0;
+    int stop, j_done, breakdown, kc, k_new, nonfinite, eig_fail, nonsym, route, pad0;
     double bnorm, tol_abs, beta, inv_h, est, res2;
 };
 

@@ -74,7 +74,32 @@ __global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__
     }
 }
 
-__global__ void k_clear_nonfinite(Ctrl* ctrl) { ctrl->nonfinite = 0; }
+__global__ void k_clear_nonfinite(Ctrl* ctrl) {
+    ctrl->nonfinite = 0;
+    ctrl->nonsym = 0;
+}
+
+// Exact symmetry of a CSR operator: entry (i, c, v) with c != i needs an entry (c, i) of the same
+// value (duplicates are summed, as in the product). One row per thread; row c is scanned for
+// column i (rows need not be sorted). Any mismatch sets ctrl->nonsym.
+__global__ __launch_bounds__(ROWS) void k_check_sym_csr(DevOp op, Ctrl* ctrl) {
+    const int i = blockIdx.x * ROWS + threadIdx.x;
+    int bad = 0;
+    if (i < op.n) {
+        const int e1 = op.rowptr[i + 1];
+        for (int e = op.rowptr[i]; e < e1 && !bad; ++e) {
+            const int c = op.colind[e];
+            if (c == i) continue;
+            if (c < 0 || c >= op.n) { bad = 1; break; }
+            double vij = 0.0, vji = 0.0;
+            for (int f = op.rowptr[i]; f < e1; ++f) vij += (op.colind[f] == c) ? op.val[f] : 0.0;
+            const int f1 = op.rowptr[c + 1];
+            for (int f = op.rowptr[c]; f < f1; ++f) vji += (op.colind[f] == i) ? op.val[f] : 0.0;
+            bad = (vij == vji) ? 0 : 1;
+        }
+    }
+    if (__any(bad) && lane_id() == 0) atomicOr(&ctrl->nonsym, 1);
+}
 
 __global__ __launch_bounds__(ROWS) void k_check_finite(const double* __restrict__ v, long count, Ctrl* ctrl) {
     int bad = 0;
@@ -911,6 +936,10 @@ void launch_init(hipStream_t s, const Work& w, const double* b, double* x, doubl
 }
 void launch_clear_nonfinite(hipStream_t s, const Work& w) {
     hipLaunchKernelGGL(k_clear_nonfinite, dim3(1), dim3(1), 0, s, w.ctrl);
+}
+void launch_check_sym(hipStream_t s, const Work& w, const DevOp& op) {
+    if (op.kind == SKR_OP_CSR)
+        hipLaunchKernelGGL(k_check_sym_csr, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, w.ctrl);
 }
 void launch_check_finite(hipStream_t s, const Work& w, const double* v, long count) {
     if (count <= 0) return;

@@ -74,7 +74,8 @@ class skr_kernel_stat(ctypes.Structure):
 
 class skr_profile(ctypes.Structure):
     _fields_ = [("step_a", skr_kernel_stat), ("step_b", skr_kernel_stat), ("step_c", skr_kernel_stat),
-                ("steps", ctypes.c_int64), ("cycles", ctypes.c_int64), ("step_bytes", ctypes.c_double)]
+                ("steps", ctypes.c_int64), ("cycles", ctypes.c_int64), ("step_bytes", ctypes.c_double),
+                ("eig_symmetric", ctypes.c_int64), ("eig_general", ctypes.c_int64)]
 
 
 class skr_serve_opts(ctypes.Structure):
@@ -209,14 +210,17 @@ def skr_ctx_destroy(ctx: int) -> None:
     _check(load_library().skr_ctx_destroy(ctx))
 
 
-def skr_sort(ctx: int, params, N: int, p: int, start: int = 0, want_dist: bool = True):
-    """Alg. 1 on device parameters (N x p float64, row-major). Returns (order int64, step d2 or None)."""
+def _sort_call(fn, ctx, params, N, p, start, want_dist):
     order = np.zeros(max(N, 1), dtype=np.int64)
     dist = np.zeros(max(N, 1), dtype=np.float64) if want_dist else None
     dptr = dist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_dist else None
-    _check(load_library().skr_sort(ctx, _ptr(params), N, p, start,
-                                   order.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dptr))
+    _check(fn(ctx, _ptr(params), N, p, start, order.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dptr))
     return order[:N], (dist[:N] if want_dist else None)
+
+
+def skr_sort(ctx: int, params, N: int, p: int, start: int = 0, want_dist: bool = True):
+    """Alg. 1 on device parameters (N x p float64, row-major). Returns (order int64, step d2 or None)."""
+    return _sort_call(load_library().skr_sort, ctx, params, N, p, start, want_dist)
 
 
 def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
@@ -284,12 +288,14 @@ def skr_spmv_repeat(ctx: int, op: Operator, x, y, repeats: int) -> float:
 
 
 def skr_profile_get(ctx: int) -> dict:
-    """Kernel statistics of solves run with SKR_FLAG_PROFILE since the last reset."""
+    """Kernel statistics of solves run with SKR_FLAG_PROFILE since the last reset, and the cycle ends
+    of every solve by the eigen stage that formed their recycle space."""
     p = skr_profile()
     _check(load_library().skr_profile_get(ctx, ctypes.byref(p)))
     ks = {name: dict(launches=getattr(p, name).launches, ms=getattr(p, name).ms, bytes=getattr(p, name).bytes)
           for name in ("step_a", "step_b", "step_c")}
-    return dict(kernels=ks, steps=p.steps, cycles=p.cycles, step_bytes=p.step_bytes)
+    return dict(kernels=ks, steps=p.steps, cycles=p.cycles, step_bytes=p.step_bytes,
+                eig_symmetric=p.eig_symmetric, eig_general=p.eig_general)
 
 
 def skr_profile_reset(ctx: int) -> None:

@@ -53,7 +53,7 @@ int main(void) {
   printf("skr_kernel_stat %zu\nskr_profile %zu\n", sizeof(skr_kernel_stat), sizeof(skr_profile));
   F(skr_kernel_stat, launches); F(skr_kernel_stat, ms); F(skr_kernel_stat, bytes);
   F(skr_profile, step_a); F(skr_profile, step_b); F(skr_profile, step_c); F(skr_profile, steps);
-  F(skr_profile, cycles); F(skr_profile, step_bytes);
+  F(skr_profile, cycles); F(skr_profile, step_bytes); F(skr_profile, eig_symmetric); F(skr_profile, eig_general);
   printf("skr_serve_opts %zu\nskr_serve_stats %zu\n", sizeof(skr_serve_opts), sizeof(skr_serve_stats));
   F(skr_serve_opts, max_chains); F(skr_serve_opts, workers); F(skr_serve_opts, arena_bytes);
   F(skr_serve_opts, split_d2_rel); F(skr_serve_opts, max_chain_systems); F(skr_serve_opts, pad0);

@@ -1,0 +1,143 @@
+"""GPU parity of the branches that ordinary chains rarely reach, against the oracle.
+
+* Start-up rank drop (App. B.1: QR of A Y with dependent columns dropped): a recycle space seeded
+  with skr_recycle_set holding an exact duplicate column, and one holding a column perturbed at
+  1e-9 relative. Bars: k_start and rank_dropped equal to the oracle's gcrodr(Y = ...), Arnoldi steps
+  within one, solution within the residual bound.
+* The eigen route follows the operator: a weakly nonsymmetric advection-diffusion chain (relative
+  asymmetry ~1e-6) in the FP32-storage mode takes the general eigen stage at every cycle end (the
+  symmetric one would solve a different problem), and matches the oracle's mixed mode with the chain
+  bars; a symmetric Darcy CSR chain takes the symmetric stage.
+* Tight tolerances: rtol 1e-13 on 32^2 Darcy reaches the restart from the true residual, matches the
+  oracle, and leaves a recycle space U with C = A U orthonormal to 1e-12 (computed on the CPU from
+  the read-back U); rtol 1e-15, below FP64's attainable accuracy, ends at maxit with a finite
+  residual near the attainable one instead of diverging.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+from gpu_common import compare_chain, log, make_ctx, need_gpu, solution_bound
+from workloads import darcy_sequence
+from workloads.advdiff import advdiff_matrix, stream_velocity
+from workloads.device import upload_systems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = need_gpu()
+    from paper_2401_09516_amd import skr
+    ctx = make_ctx(torch)
+    yield torch, skr, ctx
+    skr.skr_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("perturb", [0.0, 1e-9])
+def test_startup_rank_drop(env, perturb):
+    torch, skr, ctx = env
+    log(f"[robust] start-up rank drop, duplicated column perturbed by {perturb}")
+    systems = darcy_sequence(32, 2, first_seed=90)
+    n = systems[0].n
+    m, k = 30, 8
+    # recycle space of the first system (oracle), then column 5 replaced by a copy of column 2
+    Y = oracle.gcrodr(systems[0].A, systems[0].b, None, m, k, 1e-8, 20000).Y_next.copy()
+    assert Y.shape[1] == k
+    rng = np.random.default_rng(5)
+    Y[:, 5] = Y[:, 2] * (1.0 + perturb * rng.standard_normal(n))
+    ref = oracle.gcrodr(systems[1].A, systems[1].b, Y, m, k, 1e-8, 20000)
+    assert ref.rank_dropped == 1 and ref.k_start == k - 1
+    Ud = torch.from_numpy(np.ascontiguousarray(Y.T)).to("cuda:0")
+    skr.skr_recycle_set(ctx, Ud, n, k, m, k)
+    ops, bs, xs = upload_systems(systems[1:], "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=m, k=k, rtol=1e-8, maxit=20000,
+                                     flags=skr.SKR_FLAG_CONTINUE)
+    assert rc == skr.SKR_OK
+    g = res[0]
+    log(f"  gpu k_start {g['k_start']} dropped {g['rank_dropped']} iters {g['iters']};"
+        f" oracle {ref.k_start} {ref.rank_dropped} {ref.iters}")
+    assert g["status"] == skr.SKR_CONVERGED and g["relres_true"] <= 1e-8
+    assert g["k_start"] == ref.k_start and g["rank_dropped"] == ref.rank_dropped
+    assert abs(g["iters"] - ref.iters) <= 1
+    x = xs[0].cpu().numpy()
+    bound, _ = solution_bound(systems[1].A, systems[1].b, ref.x, g["relres_true"], ref.relres_true)
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= bound
+
+
+class _Sys:
+    def __init__(self, A, b):
+        self.A, self.b, self.n = A, b, A.shape[0]
+
+
+def test_weakly_nonsymmetric_mixed_takes_general_route(env):
+    torch, skr, ctx = env
+    N, nu, dt = 32, 5e-3, 1.0
+    systems = []
+    for s in range(5):
+        bx, by = stream_velocity(N, 300 + s, amp=4e-6)
+        A = advdiff_matrix(N, nu, bx, by, dt)
+        systems.append(_Sys(A, np.ones(A.shape[0])))
+    D = systems[0].A - systems[0].A.T
+    asym = spla.norm(D) / spla.norm(systems[0].A)
+    log(f"[robust] weakly nonsymmetric advection-diffusion chain, relative asymmetry {asym:.1e}, mixed")
+    assert 1e-8 < asym < 1e-4
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    skr.skr_profile_reset(ctx)
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=20000,
+                                     flags=skr.SKR_FLAG_MIXED)
+    assert rc == skr.SKR_OK
+    pr = skr.skr_profile_get(ctx)
+    log(f"  eigen stages: symmetric {pr['eig_symmetric']} general {pr['eig_general']}")
+    assert pr["eig_symmetric"] == 0 and pr["eig_general"] > 0
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], None, 20, 6, 1e-8, 20000,
+                                basis_fp32=True)
+    compare_chain(systems, res, xs, ref, "weak-nonsym-mixed")
+
+
+def test_symmetric_csr_takes_symmetric_route(env):
+    torch, skr, ctx = env
+    log("[robust] Darcy CSR chain: symmetric eigen stage")
+    systems = darcy_sequence(24, 3, first_seed=95)
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    skr.skr_profile_reset(ctx)
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=20, k=6, rtol=1e-8, maxit=20000)
+    assert rc == skr.SKR_OK
+    pr = skr.skr_profile_get(ctx)
+    log(f"  eigen stages: symmetric {pr['eig_symmetric']} general {pr['eig_general']}")
+    assert pr["eig_symmetric"] > 0 and pr["eig_general"] == 0
+
+
+def test_tight_tolerance_restart_and_orthonormal_c(env):
+    torch, skr, ctx = env
+    log("[robust] 32x32 Darcy chain of 3 at rtol 1e-13, GCRO-DR(30,10)")
+    systems = darcy_sequence(32, 3)
+    n = systems[0].n
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=30, k=10, rtol=1e-13, maxit=20000)
+    assert rc == skr.SKR_OK
+    ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], None, 30, 10, 1e-13, 20000)
+    assert sum(r.restarts for r in ref) >= 1
+    compare_chain(systems, res, xs, ref, "rtol1e-13", rtol=1e-13)
+    kk = skr.skr_recycle_get(ctx)
+    assert kk == 10
+    U = torch.zeros((kk, n), dtype=torch.float64, device="cuda:0")
+    skr.skr_recycle_get(ctx, U)
+    C = systems[-1].A @ U.cpu().numpy().T
+    log(f"  ||C^T C - I||_max = {np.abs(C.T @ C - np.eye(kk)).max():.1e}")
+    assert np.abs(C.T @ C - np.eye(kk)).max() <= 1e-12
+
+
+def test_unattainable_tolerance(env):
+    torch, skr, ctx = env
+    log("[robust] 32x32 Darcy at rtol 1e-15 (below attainable accuracy), maxit 600")
+    systems = darcy_sequence(32, 1)
+    ops, bs, xs = upload_systems(systems, "cuda:0")
+    rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=30, k=10, rtol=1e-15, maxit=600)
+    assert rc == skr.SKR_WARN_NOTCONVERGED
+    g = res[0]
+    log(f"  status {g['status']} iters {g['iters']} relres {g['relres_true']:.2e}")
+    assert g["status"] == skr.SKR_MAXIT and np.isfinite(g["relres_true"]) and g["relres_true"] <= 1e-12
+    x = xs[0].cpu().numpy()
+    assert np.linalg.norm(systems[0].b - systems[0].A @ x) <= 1e-12 * np.linalg.norm(systems[0].b)
