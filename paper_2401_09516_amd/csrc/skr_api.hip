@@ -22,7 +22,8 @@ void launch_check_sym(hipStream_t, const Work&, const DevOp&);
 void launch_zero(hipStream_t, double*, int);
 void launch_copy_u(hipStream_t, const Work&, double*, long, int, int);
 void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int, hipEvent_t* ev);
-void launch_close_basis(hipStream_t, const Work&, int, int);
+void launch_close_basis(hipStream_t, const Work&, const DevOp&, int, int);
+void launch_apply_c(hipStream_t, const Work&, const DevOp&, int);
 void launch_cycle_gram(hipStream_t, const Work&, int, int);
 void launch_cycle_dense(hipStream_t, const Work&, int, int, int);
 void launch_cycle_update(hipStream_t, const Work&, double*, int, int);
@@ -66,17 +67,27 @@ static double op_bytes(const DevOp& op, int64_t nvals) {
     return 8.0 * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 8.0 * n;
 }
 // es: bytes per stored basis element (8, or 4 with an FP32 basis); w and the operand stay FP64.
-static void step_bytes(const DevOp& op, int64_t nvals, int ncol, double es, double& a, double& b, double& c) {
+// A step is passes A, B and C, or with two kernels (merged) pass A at step 0, the merged kernel after
+// it, which also reads the kc columns of Z = A C (FP32), and pass B; there is no pass C (c = 0).
+static void step_bytes(const DevOp& op, int64_t nvals, int kc, int j, bool mixed, bool merged, double& a, double& b,
+                       double& c) {
     const double n = op.n;
+    const int ncol = kc + j + 1;
+    const double es = mixed ? 4.0 : 8.0;
     a = op_bytes(op, nvals) + 8.0 * n /* w */ + es * n /* v_j */ + es * n * (ncol - 1);
     b = es * n * ncol + 16.0 * n;
-    c = es * n * ncol + 16.0 * n;
+    if (!merged) {
+        c = es * n * ncol + 16.0 * n;
+    } else {
+        if (j > 0) a += 4.0 * n * kc;
+        c = 0.0;
+    }
 }
 
 static void free_work(Work& w) {
-    double* bufs[] = {w.basis, w.U, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
+    double* bufs[] = {w.basis, w.U, w.Z, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
                       w.fold_a, w.fold_b, w.fold_n,
-                      w.red1, w.red2, w.H, w.Bm};
+                      w.red1, w.red2, w.gcorr, w.H, w.Bm};
     for (double* p : bufs)
         if (p) (void)hipFree(p);
     if (w.ctrl) (void)hipFree(w.ctrl);
@@ -109,6 +120,7 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     chk(dalloc(&w.basis, (size_t)(k + m + 1) * ld));
     chk(dalloc(&w.U, (size_t)std::max(k, 1) * ld));
+    chk(dalloc(&w.Z, (size_t)std::max(k, 1) * ld));
     chk(dalloc(&w.W[0], ld));
     chk(dalloc(&w.W[1], ld));
     chk(dalloc(&w.r, ld));
@@ -123,6 +135,7 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     chk(dalloc(&w.fold_n, (size_t)NFOLD));
     chk(dalloc(&w.red1, NC));
     chk(dalloc(&w.red2, NC));
+    chk(dalloc(&w.gcorr, 2 * NC));
     chk(dalloc(&w.H, (size_t)LDH * MMAX));
     chk(dalloc(&w.Bm, (size_t)KMAX * MMAX));
     chk(dalloc(&w.ctrl, 1));
@@ -153,8 +166,8 @@ size_t skr::work_bytes(int n, int m, int k) {
     const size_t nblk = (size_t)((n + ROWS - 1) / ROWS);
     const size_t ngblk = (size_t)std::min(256, std::max(1, (n + 255) / 256));
     const size_t gmax = (size_t)gram_cols_max(m, k);
-    size_t d = (size_t)(k + m + 1) * ld + (size_t)std::max(k, 1) * ld + 3 * ld;   // basis, U, W[2], r
-    d += 3 * nblk * NC + nblk + ngblk * gmax + gmax + 2 * (size_t)NFOLD * NC + NFOLD + 2 * NC;
+    size_t d = (size_t)(k + m + 1) * ld + 2 * (size_t)std::max(k, 1) * ld + 3 * ld;   // basis, U, Z, W[2], r
+    d += 3 * nblk * NC + nblk + ngblk * gmax + gmax + 2 * (size_t)NFOLD * NC + NFOLD + 4 * NC;
     d += (size_t)LDH * MMAX + (size_t)KMAX * MMAX;
     return d * sizeof(double) + sizeof(Ctrl) + sizeof(Coef) + sizeof(DenseWork) + 8 * sizeof(unsigned);
 }
@@ -217,7 +230,6 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     const double rtol = opts.rtol;
     const int64_t maxit = opts.maxit;
     const bool profile = (opts.flags & SKR_FLAG_PROFILE) && ctx->ev_ok;
-    const double es = w.mixed ? 4.0 : 8.0;
     int samp_j[PROF_MAXSAMP];
     int rc;
     DevOp op;
@@ -276,6 +288,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
         kc = hc.kc;
         res.k_start = kc;
     }
+    bool z_valid = false;      // Z = A C holds for the current C (two-kernel steps only)
     int status = -1;
     double est = hc.beta;
     // r is fresh: b - A x computed directly (at x = 0), or just projected onto range(C)'s
@@ -321,6 +334,11 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
             HIPLAUNCHCHK();
         }
         r_fresh = false;
+        if (w.merged && kc > 0 && !z_valid) {
+            launch_apply_c(s, w, op, kc);
+            HIPLAUNCHCHK();
+            z_valid = true;
+        }
         int scyc = (kc == 0) ? m : m - kc;
         scyc = (int)std::min<int64_t>(scyc, maxit - iters);
         // Launch length. A step launched after the cycle has stopped exits at once, but still costs a
@@ -355,7 +373,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
             if ((rc = read_ctrl(ctx))) return rc;
             if (!hc.stop) launch_steps(nfirst, scyc);
         }
-        launch_close_basis(s, w, kc, scyc);
+        launch_close_basis(s, w, op, kc, scyc);
         if (kc > 0) launch_cycle_gram(s, w, kc, scyc);
         launch_cycle_dense(s, w, kc, scyc, k);
         // the new recycle size is at most k (0 when no recycle space is formed this cycle)
@@ -371,18 +389,19 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
             skr_profile& pr = ctx->prof;
             for (int q = 0; q < nsamp; ++q) {
                 if (samp_j[q] >= jd) continue;   // steps after the stop are skipped launches
-                float t[3];
-                for (int e = 0; e < 3; ++e)
+                float t[3] = {0.f, 0.f, 0.f};
+                const int nk = w.merged ? 2 : 3;    // kernels per step
+                for (int e = 0; e < nk; ++e)
                     HIPCHK(hipEventElapsedTime(&t[e], ctx->ev[6 * q + 2 * e], ctx->ev[6 * q + 2 * e + 1]));
                 double ba, bb, bc;
-                step_bytes(op, nvals, kc + samp_j[q] + 1, es, ba, bb, bc);
+                step_bytes(op, nvals, kc, samp_j[q], w.mixed != 0, w.merged != 0, ba, bb, bc);
                 pr.step_a.launches++; pr.step_a.ms += t[0]; pr.step_a.bytes += ba;
                 pr.step_b.launches++; pr.step_b.ms += t[1]; pr.step_b.bytes += bb;
-                pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc;
+                if (nk == 3) { pr.step_c.launches++; pr.step_c.ms += t[2]; pr.step_c.bytes += bc; }
             }
             for (int j = 0; j < jd; ++j) {
                 double ba, bb, bc;
-                step_bytes(op, nvals, kc + j + 1, es, ba, bb, bc);
+                step_bytes(op, nvals, kc, j, w.mixed != 0, w.merged != 0, ba, bb, bc);
                 pr.step_bytes += ba + bb + bc;
             }
             pr.steps += jd;
@@ -396,6 +415,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
         spmv += jd;
         cycles += 1;
         est = hc.est;
+        if (hc.k_new > 0) z_valid = false;     // the cycle end rewrote C
         kc = hc.k_new;
         if (!std::isfinite(est)) {
             launch_zero(s, x, n);
@@ -460,6 +480,10 @@ int skr::prepare_solve(skr_ctx* ctx, int n, const skr_opts& opts) {
     Work& w = ctx->w;
     w.fold = (w.nblk > FOLD_MIN || (opts.flags & SKR_FLAG_FOLD)) ? 1 : 0;
     w.mixed = (opts.flags & SKR_FLAG_MIXED) ? 1 : 0;
+    // Two kernels per Arnoldi step where the step is bound by latency (at most 256 workgroups, no
+    // folding) and the basis is FP64. With an FP32 basis the product must be taken on the stored
+    // (rounded) vector, and on folded (HBM-streaming) grids the three-kernel step keeps more waves.
+    w.merged = (!w.mixed && !w.fold) ? 1 : 0;
     return SKR_OK;
 }
 

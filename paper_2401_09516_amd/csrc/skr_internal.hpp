@@ -385,13 +385,15 @@ __device__ __forceinline__ double sum_partials1(const double* part, int nblk, do
 // wave sums a contiguous quarter of the workgroups (up to 64 loads in flight per lane), then the
 // quarters are added in order. Columns 64.. (nr > 64) are a second pass of the same form. BATCH loads
 // are issued together (16 suffice for folded partials, 16 rows per wave, and keep registers free).
-// Called by all threads of a workgroup; sh holds NWAVE * 64 doubles.
+// Columns start at cfirst (a multiple of 64). Called by all threads of a workgroup; sh holds
+// NWAVE * 64 doubles.
 template <int BATCH = 64>
-__device__ __forceinline__ void sum_partials(const double* part, int nblk, int nr, double* sh, double* out) {
+__device__ __forceinline__ void sum_partials(const double* part, int nblk, int nr, double* sh, double* out,
+                                             int cfirst = 0) {
     const int lane = lane_id(), w = wave_id();
     const int per = (nblk + NWAVE - 1) / NWAVE;
     const int b0 = w * per, b1 = min(nblk, b0 + per);
-    for (int c0 = 0; c0 < nr; c0 += 64) {
+    for (int c0 = cfirst; c0 < nr; c0 += 64) {
         const int col = c0 + lane;
         double s = 0.0;
         if (col < nr) {
@@ -444,6 +446,8 @@ struct Work {
     // doubles, or floats when mixed (the buffers are sized for doubles either way)
     double* basis = nullptr;
     double* U = nullptr;
+    double* Z = nullptr;         // A C (k columns stored as FP32, FP64 basis only): the merged Arnoldi
+                                 // kernel's A C
     int mixed = 0;
     double* W[2] = {nullptr, nullptr};
     double* r = nullptr;
@@ -457,8 +461,10 @@ struct Work {
     double* fold_b = nullptr;    // NFOLD * NC folded partials of pass B
     double* fold_n = nullptr;    // NFOLD folded norm partials
     int fold = 0;                // nonzero: partials are folded before every re-sum
+    int merged = 0;              // nonzero: two kernels per Arnoldi step (FP64 basis, no folding)
     double* red1 = nullptr;      // NC
     double* red2 = nullptr;      // NC
+    double* gcorr = nullptr;     // 2 x NC: column corrections of the merged Arnoldi kernel (alternating)
     double* H = nullptr;         // LDH x MMAX
     double* Bm = nullptr;        // KMAX x MMAX
     Ctrl* ctrl = nullptr;

@@ -148,14 +148,16 @@ __device__ __forceinline__ void block_partials(double s, double* sh, double* par
 // Close step jj of the current cycle once tot = ||w||^2 is known (Eq. 6): column jj of B (rows of
 // C) and of Hbar (rows of V) are the sums of the two CGS passes h1 + h2, h_{jj+1,jj} = ||w|| (zero
 // at a happy breakdown, h <= 1e-14 ||A v_jj||), and the progressive Givens QR of Hbar gives the
-// least-squares residual estimate |g_{jj+1}|. Run by wave 0 of every calling workgroup on identical
+// least-squares residual estimate |g_{jj+1}|; g3, when given, is subtracted from the column (the
+// correction of the merged kernel below). Run by wave 0 of every calling workgroup on identical
 // inputs, so all get identical results; only the writer workgroup stores the column, the new
 // rotation and g_{jj+1}. Only the running entry of the rotated column is needed: after rotation q
 // it is a_{q+1} = -sn_q a_q + cs_q col[q+1], run by lane 0 from LDS copies (shc, 3 x 128 doubles;
 // lane t handles the column entries t and t + 64).
 __device__ __forceinline__ double close_step(int jj, int kc, double tot, const double* __restrict__ h1,
                                              const double* __restrict__ h2, double* H, double* Bm, Ctrl* ctrl,
-                                             bool writer, int& brk_out, double& hnorm_out, double* shc) {
+                                             bool writer, int& brk_out, double& hnorm_out, double* shc,
+                                             const double* __restrict__ g3 = nullptr) {
     const int t = threadIdx.x;
     const int ncol = kc + jj + 1;
     const double hnorm = sqrt(tot);
@@ -166,9 +168,9 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
     for (int half = 0; half < 2; ++half) {
         const int e = t + 64 * half;
         double colt = 0.0;
-        if (e <= jj) colt = h1[kc + e] + h2[kc + e];
+        if (e <= jj) colt = h1[kc + e] + h2[kc + e] - (g3 ? g3[kc + e] : 0.0);
         if (writer) {
-            if (e < kc) Bm[e + jj * KMAX] = h1[e] + h2[e];
+            if (e < kc) Bm[e + jj * KMAX] = h1[e] + h2[e] - (g3 ? g3[e] : 0.0);
             if (e <= jj) H[e + jj * LDH] = colt;
         }
         shc[e] = colt;
@@ -328,8 +330,9 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 }
 
 // Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
-// partials of Q^T w.
-template <int NL, typename BT, bool FOLDED>
+// partials of Q^T w; with NORM also of ||w||^2 (reduction column ncol), which the merged kernel
+// below needs in place of a pass C.
+template <int NL, typename BT, bool FOLDED, bool NORM = false>
 __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
@@ -354,17 +357,18 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
     for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
     if (valid) w_io[i] = w;
     else w = 0.0;
+    auto col_val = [&](int c) {
+        const double qw = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
+        return (NORM && c == ncol) ? w * w : qw;
+    };
     double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
+    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
     const double s = wave_reduce_scatter<NR>(acc);
     if constexpr (NR2 > 0) {
         double acc2[NR2];
 #pragma unroll
-        for (int c = 0; c < NR2; ++c) {
-            const int cc = 64 + c;
-            acc2[c] = (cc < NL && cc < ncol) ? q[cc < NL ? cc : 0] * w : 0.0;
-        }
+        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
         const double s2 = wave_reduce_scatter<NR2>(acc2);
         block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb);
     }
@@ -397,6 +401,179 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
     if (valid) w_io[i] = w;
     else w = 0.0;
     block_partial1(w * w, part_n, lb, sh);
+}
+
+// Merged pass C of step j-1 and pass A of step j (FP64 basis, 1 <= j). Pass B of step j-1 left
+// w_B = A v_{j-1} - Q h1 and the partials of h2 = Q^T w_B and ||w_B||^2, Q = [C, v_0..v_{j-1}]
+// (ncolp = kc + j columns). CGS2 then forms w_C = w_B - Q h2 and v_j = w_C / h with
+// h^2 = ||w_C||^2 = ||w_B||^2 - ||h2||^2 (Q orthonormal). The product A v_j cannot wait for v_j in
+// the other rows, so it is formed from the complete w_B by linearity: A v_j = (A w_B - A Q h2) / h.
+// With A C = Z (a product formed once per cycle) and the Arnoldi relation of the V columns (Eq. 6:
+// A v_l = C B(:, l) + V Hbar(:, l)), A Q h2 = Z h2_C + Q' g, Q' = [Q, v_j], g = [B h2_V; Hbar h2_V].
+// The term Q' g / h lies in the span the next projection removes, so the kernel continues with
+// w' = (A w_B - Z h2_C) / h, and CGS2 of w' against Q' gives the same vectors as CGS2 of A v_j, with
+// coefficients larger by exactly g / h: the closing of step j subtracts g / h from the column it
+// assembles. The writer workgroup forms g / h after its rows are done and leaves it in gnext for
+// the next kernel; gprev holds the one of step j-1 (none at j-1 = 0, which pass A formed directly).
+// Every quantity is as in CGS2 in exact arithmetic; the relation's rounding, like the FP32 rounding
+// of Z, enters multiplied by h2, a second-order term. LAST: the cycle's final closing (no product).
+//
+// The stop flag: a kernel of step j sets ctrl->stop = j + 1, so its own workgroups that read the flag
+// after the writer set it still see a stop of a later step than theirs; every other kernel treats
+// any nonzero value as stopped.
+template <int NL, int KIND, int KZ, bool LAST>
+__global__ __launch_bounds__(ROWS) void k_step_m(DevOp op, const double* __restrict__ wb, double* __restrict__ dst,
+                                                 double* __restrict__ basis, const float* __restrict__ Z, int ld,
+                                                 int kc, int vbase, int j, int nblk, int npb,
+                                                 const double* __restrict__ part_b, double* __restrict__ part_a,
+                                                 const double* __restrict__ red1, const double* __restrict__ gprev,
+                                                 double* __restrict__ gnext, double* H, double* Bm, Ctrl* ctrl) {
+    constexpr int NR = Width<NL>::NR, NR2 = Width<NL>::NR2;
+    __shared__ double sh[NWAVE * NC];
+    __shared__ double hs[NC];      // h2 (ncolp entries), ||w_B||^2 at ncolp
+    __shared__ double hc[NC];      // h2 padded with zeros past ncolp
+    __shared__ double hz[KZ > 0 ? KZ : 1];   // h2_C padded with zeros past kc
+    __shared__ double gp[NC];      // correction of the column closed here (zero at j - 1 = 0)
+    __shared__ double s_scale;
+    __shared__ int s_stop;
+    const bool writer = blockIdx.x == 0;
+    const int n = op.n;
+    const int lb = logical_block(blockIdx.x, nblk);
+    const int i = lb * ROWS + threadIdx.x;
+    const bool valid = i < n;
+    const int ii = valid ? i : n - 1;
+    const int jj = j - 1;               // the step closed here
+    const int ncolp = kc + j;           // columns of Q before v_j
+    const int ncol = ncolp + 1;         // with v_j
+    const int st = ctrl->stop;
+    // loads before the first wait: the basis row, the row of Z, w_B and its product with A
+    double q[NL];
+#pragma unroll
+    for (int c = 0; c < NL; ++c) q[c] = basis[qoff(c < ncolp ? c : ncolp - 1, kc, vbase, ld) + ii];
+    float z[KZ > 0 ? KZ : 1];
+#pragma unroll
+    for (int c = 0; c < (KZ > 0 ? KZ : 1); ++c) z[c] = KZ > 0 ? Z[(size_t)min(c, kc - 1) * ld + ii] : 0.0f;
+    const double wbi = wb[ii];
+    double aw = 0.0;
+    if constexpr (!LAST) aw = op_row_k<KIND>(op, wb, ii, 1.0);
+    if (threadIdx.x < NC) gp[threadIdx.x] = (jj > 0 && (int)threadIdx.x < ncolp) ? gprev[threadIdx.x] : 0.0;
+    if (st != 0 && st <= j) return;     // the cycle stopped at an earlier step
+    sum_partials<64>(part_b, npb, ncolp + 1, sh, hs);
+    if (threadIdx.x < NC) {
+        const int t = threadIdx.x;
+        const double v = hs[t];
+        hc[t] = t < ncolp ? v : 0.0;
+        if (KZ > 0 && t < (KZ > 0 ? KZ : 1)) hz[t < (KZ > 0 ? KZ : 1) ? t : 0] = t < kc ? v : 0.0;
+    }
+    if (threadIdx.x < 64) {
+        // ||w_C||^2 = ||w_B||^2 - ||h2||^2, summed in a fixed order (the same bits in every workgroup)
+        const int t = threadIdx.x;
+        const double a0 = hs[t], a1 = hs[t + 64];
+        double q2 = (t < ncolp) ? a0 * a0 : 0.0;
+        q2 += (t + 64 < ncolp) ? a1 * a1 : 0.0;
+        const double tot = fmax(hs[ncolp] - wave_sum(q2), 0.0);
+        int brk;
+        double hn;
+        const double est = close_step(jj, kc, tot, red1, hs, H, Bm, ctrl, writer, brk, hn, sh + 64, gp);
+        if (t == 0) {
+            const int stop = (brk || !(est > ctrl->tol_abs)) ? 1 : 0;
+            s_stop = stop;
+            s_scale = brk ? 0.0 : 1.0 / hn;
+            if (writer) {
+                ctrl->inv_h = s_scale;
+                if (stop || LAST) {
+                    ctrl->j_done = j;
+                    ctrl->breakdown = brk;
+                }
+                if (stop) ctrl->stop = j + 1;
+            }
+        }
+    }
+    __syncthreads();
+    const double scale = s_scale;
+    // The writer's loads of the earlier columns of B and Hbar (for g / h, below) go out now, so that
+    // their latency overlaps the row work. The four waves take interleaved columns l = w, w + 4, ...
+    // < jj, each lane one row (two past 64).
+    constexpr int LQ = (MMAX + NWAVE - 1) / NWAVE;
+    const int wv = wave_id(), lane = lane_id();
+    double gm[LAST ? 1 : 2][LAST ? 1 : LQ];
+    if (!LAST && writer && !s_stop) {
+#pragma unroll
+        for (int half = 0; half < (LAST ? 1 : 2); ++half) {
+            const int rr = min(lane + 64 * half, ncol - 1);
+#pragma unroll
+            for (int u = 0; u < (LAST ? 1 : LQ); ++u) {
+                const int l = min(wv + NWAVE * u, max(jj - 1, 0));
+                gm[half][u] = rr < kc ? Bm[rr + l * KMAX] : H[(rr - kc) + l * LDH];
+            }
+        }
+    }
+    // w_C = w_B - Q h2 and v_j = w_C / h
+    double wc = wbi;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) wc = fma(-q[c], hc[c], wc);
+    const double vj = wc * scale;
+    if (valid) basis[(size_t)(vbase + j) * ld + i] = vj;
+    if (s_stop || LAST) return;
+    // w' = (A w_B - Z h2_C) / h
+    double corr = 0.0;
+    if constexpr (KZ > 0) {
+#pragma unroll
+        for (int c = 0; c < KZ; ++c) corr = fma((double)z[c], hz[c], corr);
+    }
+    double w = (aw - corr) * scale;
+    if (valid) dst[i] = w;
+    else w = 0.0;
+    auto col_val = [&](int c) {
+        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
+        return (c < ncolp) ? qc * w : (c == ncolp ? vj * w : (c == ncol ? w * w : 0.0));
+    };
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
+    const double s = wave_reduce_scatter<NR>(acc);
+    if constexpr (NR2 > 0) {
+        double acc2[NR2];
+#pragma unroll
+        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
+        const double s2 = wave_reduce_scatter<NR2>(acc2);
+        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb);
+    }
+    block_partials<NR>(s, sh, part_a, lb);
+    if (!writer) return;
+    __syncthreads();
+    // g / h for the closing of step j: row t < kc is (B h2_V)_t, row kc + e is (Hbar h2_V)_e, e <= j.
+    // Columns l < jj of B and Hbar were loaded above from the stores of the steps they closed;
+    // column jj is the one closed here (h1 + h2 - correction, and h below the diagonal). The wave
+    // sums are added in wave order, then column jj.
+    if constexpr (LAST) return;
+    double part2[2];
+#pragma unroll
+    for (int half = 0; half < (LAST ? 1 : 2); ++half) {
+        const int rr = min(lane + 64 * half, ncol - 1);
+        double a = 0.0;
+#pragma unroll
+        for (int u = 0; u < (LAST ? 1 : LQ); ++u) {
+            const int l = wv + NWAVE * u;
+            const bool ok = l < jj && (rr < kc || l + 1 >= rr - kc);
+            a = fma(ok ? gm[half][u] : 0.0, hs[kc + min(l, max(jj - 1, 0))], a);
+        }
+        part2[half] = a;
+    }
+    __syncthreads();
+    sh[wv * 128 + lane] = part2[0];
+    sh[wv * 128 + 64 + lane] = part2[1];
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NC) {
+        double a = sh[t];
+#pragma unroll
+        for (int q2 = 1; q2 < NWAVE; ++q2) a += sh[q2 * 128 + t];
+        const int tt = min(t, ncolp);
+        const double colj = t < ncolp ? red1[tt] + hs[tt] - gp[tt] : 1.0 / scale;
+        a = fma(colj, hs[kc + jj], a);
+        gnext[t] = t < ncol ? a * scale : 0.0;
+    }
 }
 
 // Cycle end: closes the last step when no pass A did (the cycle ran all s_cycle steps), then stores
@@ -770,6 +947,99 @@ __global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const BT* __restrict__ 
         Z[(size_t)c * ld + i] = (BT)op_row_k<-1, BT, false>(op, Y + (size_t)c * ld, i, 1.0);
 }
 
+// Z = A C for the kc <= KB recycled columns C = basis columns 0..kc-1 (FP64), the product the merged
+// Arnoldi kernel takes A C from. Z is stored in FP32: the kernel only multiplies it by second-pass
+// Gram-Schmidt coefficients, which are of the order of the rounding of the first pass, so its
+// relative rounding 2^-24 changes that term far below FP64 rounding. One row per thread; the
+// operator row (CSR entries or stencil faces) is loaded once and applied to every column, each
+// column's terms added in the order of op_row_k.
+template <int KIND, int KB>
+__global__ __launch_bounds__(ROWS) void k_apply_c(DevOp op, const double* __restrict__ C, float* __restrict__ Z,
+                                                  int ld, int kc, int nblk) {
+    const int lb = logical_block(blockIdx.x, nblk);
+    const int i = lb * ROWS + threadIdx.x;
+    if (i >= op.n) return;
+    double acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    if constexpr (KIND == SKR_OP_CSR) {
+        const int e0 = op.rowptr[i], e1 = op.rowptr[i + 1];
+        for (int e = e0; e < e1; e += 8) {
+            int cl[8];
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = min(e + u, e1 - 1);
+                cl[u] = op.colind[q];
+                v[u] = op.val[q];
+            }
+#pragma unroll
+            for (int c = 0; c < KB; ++c) {
+                if (c < kc) {
+                    double xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) xv[u] = C[(size_t)c * ld + cl[u]];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (e + u < e1) acc[c] = fma(v[u], xv[u], acc[c]);
+                }
+            }
+        }
+    } else if constexpr (KIND == SKR_OP_STENCIL7) {
+        const int nx = op.nx, ny = op.ny, nz = op.nz, nxy = nx * ny;
+        const int gz = i / nxy, gyx = i - gz * nxy, gy = gyx / nx, gx = gyx - gy * nx;
+        const int fx = (gz * ny + gy) * (nx + 1) + gx, fy = (gz * (ny + 1) + gy) * nx + gx, fz = gz * nxy + gyx;
+        const double aw = op.ax[fx], ae = op.ax[fx + 1];
+        const double as = op.ay[fy], an = op.ay[fy + nx];
+        const double ad = op.az[fz], au = op.az[fz + nxy];
+        const bool hw = gx > 0, he = gx < nx - 1, hs = gy > 0, hn = gy < ny - 1, hd = gz > 0, hu = gz < nz - 1;
+        const double dg = (aw + ae) + (as + an) + (ad + au);
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < kc) {
+                const double* x = C + (size_t)c * ld;
+                const double xc = x[i];
+                const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
+                const double xs = x[hs ? i - nx : i], xn = x[hn ? i + nx : i];
+                const double xd = x[hd ? i - nxy : i], xu = x[hu ? i + nxy : i];
+                double t = dg * xc;
+                t = hw ? fma(-aw, xw, t) : t;
+                t = he ? fma(-ae, xe, t) : t;
+                t = hs ? fma(-as, xs, t) : t;
+                t = hn ? fma(-an, xn, t) : t;
+                t = hd ? fma(-ad, xd, t) : t;
+                t = hu ? fma(-au, xu, t) : t;
+                acc[c] = t * op.inv_h2;
+            }
+        }
+    } else {
+        const int nx = op.nx, ny = op.ny;
+        const int r = i / nx, cc = i - r * nx;
+        const double aw = op.ax[r * (nx + 1) + cc], ae = op.ax[r * (nx + 1) + cc + 1];
+        const double an = op.ay[r * nx + cc], as = op.ay[(r + 1) * nx + cc];
+        const bool hw = cc > 0, he = cc < nx - 1, hn = r > 0, hs = r < ny - 1;
+        const double dg = aw + ae + an + as;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < kc) {
+                const double* x = C + (size_t)c * ld;
+                const double xc = x[i];
+                const double xw = x[hw ? i - 1 : i], xe = x[he ? i + 1 : i];
+                const double xn = x[hn ? i - nx : i], xs = x[hs ? i + nx : i];
+                double t = dg * xc;
+                t = hw ? fma(-aw, xw, t) : t;
+                t = he ? fma(-ae, xe, t) : t;
+                t = hn ? fma(-an, xn, t) : t;
+                t = hs ? fma(-as, xs, t) : t;
+                acc[c] = t * op.inv_h2;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+        if (c < kc) Z[(size_t)c * ld + i] = (float)acc[c];
+}
+
 // Row-wise triangular solves z <- z R^{-1} (R upper, k x k, ld KMAX) on Z (kept columns gathered
 // through keep[]) and on U, compacting both to the first k_eff columns.
 template <typename BT>
@@ -975,16 +1245,46 @@ static void step_a(hipStream_t s, const Work& w, const DevOp& op, const double* 
         step_a_k<NL, SKR_OP_STENCIL5, BT>(s, w, op, src, dst, kc, j, e0, e1);
 }
 // Passes B and C re-sum NFOLD folded partial rows (w.fold) or one row per workgroup.
-template <int NL, typename BT>
+template <int NL, typename BT, bool NORM = false>
 static void step_b(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
     if (w.fold)
-        hipExtLaunchKernelGGL((k_step_b<NL, BT, true>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+        hipExtLaunchKernelGGL((k_step_b<NL, BT, true, NORM>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
                               (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, NFOLD, (const double*)w.fold_a,
                               w.part_b, w.red1, (const Ctrl*)w.ctrl);
     else
-        hipExtLaunchKernelGGL((k_step_b<NL, BT, false>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
+        hipExtLaunchKernelGGL((k_step_b<NL, BT, false, NORM>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, dst,
                               (const BT*)bas<BT>(w), w.n, w.ld, kc, w.k, j, w.nblk, w.nblk, (const double*)w.part_a,
                               w.part_b, w.red1, (const Ctrl*)w.ctrl);
+}
+// Merged kernel of step j (closes step j-1): reads pass B's partials (folded or not).
+template <int NL, int KIND, int KZ, bool LAST>
+static void step_m_k(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
+    const double* wb = w.W[(j - 1) & 1];
+    double* dst = w.W[j & 1];
+    hipExtLaunchKernelGGL((k_step_m<NL, KIND, KZ, LAST>), dim3(w.nblk), dim3(ROWS), 0, s, e0, e1, 0, op, wb, dst,
+                          bas<double>(w), (const float*)w.Z, w.ld, kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+                          (const double*)(w.fold ? w.fold_b : w.part_b), w.part_a, (const double*)w.red1,
+                          (const double*)(w.gcorr + ((j - 1) & 1) * NC), w.gcorr + (j & 1) * NC, w.H, w.Bm,
+                          w.ctrl);
+}
+template <int NL, int KZ, bool LAST>
+static void step_m_z(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
+    if (op.kind == SKR_OP_CSR)
+        step_m_k<NL, SKR_OP_CSR, KZ, LAST>(s, w, op, kc, j, e0, e1);
+    else if (op.kind == SKR_OP_STENCIL7)
+        step_m_k<NL, SKR_OP_STENCIL7, KZ, LAST>(s, w, op, kc, j, e0, e1);
+    else
+        step_m_k<NL, SKR_OP_STENCIL5, KZ, LAST>(s, w, op, kc, j, e0, e1);
+}
+template <int NL, bool LAST>
+static void step_m(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
+    // the closing form forms no product: one instance per NL
+    if constexpr (LAST) step_m_k<NL, SKR_OP_CSR, 0, true>(s, w, op, kc, j, e0, e1);
+    else if (kc == 0) step_m_z<NL, 0, LAST>(s, w, op, kc, j, e0, e1);
+    else if (kc <= 8) step_m_z<NL, 8, LAST>(s, w, op, kc, j, e0, e1);
+    else if (kc <= 16) step_m_z<NL, 16, LAST>(s, w, op, kc, j, e0, e1);
+    else if (kc <= 24) step_m_z<NL, 24, LAST>(s, w, op, kc, j, e0, e1);
+    else step_m_z<NL, 32, LAST>(s, w, op, kc, j, e0, e1);
 }
 template <int NL, typename BT>
 static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hipEvent_t e0, hipEvent_t e1) {
@@ -1037,15 +1337,71 @@ static void launch_step_t(hipStream_t s, const Work& w, const DevOp& op, int kc,
 #undef CALL_C
     launch_fold_n(s, w);
 }
+// One Arnoldi step with an FP64 basis, two kernels: step 0 is pass A (from r) and pass B; a later
+// step j is the merged kernel (pass C of step j-1 with pass A of step j) and pass B. Pass B leaves
+// ||w_B||^2 beside Q^T w_B. With ev != nullptr, ev[0..1] time the first kernel and ev[2..3] pass B.
+static void launch_step_2k(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, hipEvent_t* ev) {
+    const int ncol = kc + j + 1;
+    const int nla = bucket8(ncol + 1);
+    hipEvent_t e[4] = {};
+    if (ev)
+        for (int q = 0; q < 4; ++q) e[q] = ev[q];
+    if (j == 0) {
+#define CALL_A(NL) step_a<NL, double>(s, w, op, w.r, w.W[0], kc, 0, e[0], e[1])
+        SKR_DISPATCH8(nla, CALL_A)
+#undef CALL_A
+    } else {
+#define CALL_M(NL) step_m<NL, false>(s, w, op, kc, j, e[0], e[1])
+        SKR_DISPATCH8(nla, CALL_M)
+#undef CALL_M
+    }
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_a, w.nblk, ncol + 1, w.fold_a);
+#define CALL_B(NL) step_b<NL, double, true>(s, w, w.W[j & 1], kc, j, e[2], e[3])
+    SKR_DISPATCH8(nla, CALL_B)
+#undef CALL_B
+    if (w.fold) hipLaunchKernelGGL(k_fold, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_b, w.nblk, ncol + 1, w.fold_b);
+}
 void launch_step(hipStream_t s, const Work& w, const DevOp& op, int kc, int j, int s_cycle, hipEvent_t* ev) {
     (void)s_cycle;
-    if (w.mixed)
+    if (w.merged)
+        launch_step_2k(s, w, op, kc, j, ev);
+    else if (w.mixed)
         launch_step_t<float>(s, w, op, kc, j, ev);
     else
         launch_step_t<double>(s, w, op, kc, j, ev);
 }
-void launch_close_basis(hipStream_t s, const Work& w, int kc, int s_cycle) {
-    if (w.mixed)
+// Z = A C for the kc recycled columns (the merged Arnoldi kernel reads it).
+void launch_apply_c(hipStream_t s, const Work& w, const DevOp& op, int kc) {
+    if (!w.merged || kc <= 0) return;
+#define SKR_AC(KIND, KB)                                                                                  \
+    hipLaunchKernelGGL((k_apply_c<KIND, KB>), dim3(w.nblk), dim3(ROWS), 0, s, op, (const double*)w.basis, (float*)w.Z, \
+                       w.ld, kc, w.nblk)
+#define SKR_AC_K(KIND)                       \
+    if (kc <= 8) SKR_AC(KIND, 8);            \
+    else if (kc <= 16) SKR_AC(KIND, 16);     \
+    else if (kc <= 24) SKR_AC(KIND, 24);     \
+    else SKR_AC(KIND, 32);
+    if (op.kind == SKR_OP_CSR) {
+        SKR_AC_K(SKR_OP_CSR)
+    } else if (op.kind == SKR_OP_STENCIL7) {
+        SKR_AC_K(SKR_OP_STENCIL7)
+    } else {
+        SKR_AC_K(SKR_OP_STENCIL5)
+    }
+#undef SKR_AC_K
+#undef SKR_AC
+}
+// Cycle end: closes the last step when the cycle did not stop early and stores the last basis
+// vector v_{s_cycle}; with an FP64 basis this is the merged kernel in its closing form.
+void launch_close_basis(hipStream_t s, const Work& w, const DevOp& op, int kc, int s_cycle) {
+    if (w.merged) {
+        const int nla = bucket8(kc + s_cycle + 2);
+#define CALL_L(NL) step_m<NL, true>(s, w, op, kc, s_cycle, nullptr, nullptr)
+        SKR_DISPATCH8(nla, CALL_L)
+#undef CALL_L
+        return;
+    }
+    else if (w.mixed)
         hipLaunchKernelGGL(k_close_basis<float>, dim3(w.nblk), dim3(ROWS), 0, s, (const double*)w.W[0],
                            (const double*)w.W[1], bas<float>(w), w.n, w.ld, kc, w.k, s_cycle, pn_cnt(w), pn_src(w),
                            (const double*)w.red1, (const double*)w.red2, w.H, w.Bm, w.ctrl);
