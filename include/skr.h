@@ -160,6 +160,19 @@ int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64
              int64_t* order_host, double* step_d2_host);
 
 /*
+ * skr_sort without any device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments, results
+ * (bit for bit) and errors as skr_sort, for N <= 512 systems and any p. The distance matrix, slice
+ * partials and outputs live in one library-owned static device array of 16 MiB per GPU, held until
+ * the process ends; the caller passes only the inputs and outputs. Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (several host threads or streams) race: serialise
+ * them. Errors: those of skr_sort, SKR_EINVAL for N > 512, SKR_EHIP if the array could not be
+ * located on the device.
+ */
+int skr_sort_noalloc(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64_t start,
+                     int64_t* order_host, double* step_d2_host);
+
+/*
  * Solve A_i x_i = b_i for i = order[0], order[1], ... (Eq. 1) with GCRO-DR(m, k) (Alg. 2),
  * x0 = 0, carrying U_k from each solved system to the next (App. B.1).
  *  ops:    host array of N operators (device data), indexed by original system index;

@@ -36,6 +36,7 @@ void launch_startup_project(hipStream_t, const Work&, double*, int, int);
 void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
 void launch_spmv_repeat(hipStream_t, const DevOp&, const double*, double*, int);
 void launch_sort(hipStream_t, const double*, long, long, long, double*, double*, long long*, double*);
+hipError_t noalloc_setup(int);
 long sort_nmax();
 long sort_part_doubles(long, long);
 }  // namespace skr
@@ -517,7 +518,11 @@ int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(SKR_EINVAL, "device %d out of range (%d devices)", device, ndev);
-    return ctx_make(device, (hipStream_t)hip_stream, out);
+    const int rc = ctx_make(device, (hipStream_t)hip_stream, out);
+    // locate this device's copy of skr_sort_noalloc's scratch array once, with the device current; a
+    // failure is reported by that entry point, not here
+    if (rc == SKR_OK) (void)noalloc_setup(device);
+    return rc;
 }
 
 

@@ -16,7 +16,9 @@
 // 2. One workgroup walks the greedy path: N - 1 steps, each an arg-min over one row of d2 of the
 //    unvisited systems, ties to the lowest index, NaN/Inf never preferred (a row with no finite
 //    candidate takes the lowest unvisited index).
-#include "skr_internal.hpp"
+#include <mutex>
+
+#include "skr_host.hpp"
 
 namespace skr {
 
@@ -295,3 +297,105 @@ void launch_dd_dist(hipStream_t s, const double* a, const double* const* bs, int
 }
 
 }  // namespace skr
+
+namespace skr {
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free sort (skr_sort_noalloc): the distance matrix, the slice partials and the order
+// and step-distance outputs live in one file-scope device array instead of context buffers. Each
+// device holds its own copy; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------------------------
+constexpr long NOALLOC_NMAX = 512;
+constexpr size_t NOALLOC_BYTES = (size_t)16 << 20;     // covers every N <= 512 and every p
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAXDEV = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAXDEV] = {};
+static int g_scratch_state[NOALLOC_MAXDEV] = {};       // 0 not set up, 1 ready, -1 failed
+static hipError_t g_scratch_err[NOALLOC_MAXDEV] = {};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bytes of scratch a sort of N systems with p parameters uses, and the offsets of its parts.
+static size_t noalloc_layout(long N, long p, size_t& off_part, size_t& off_order, size_t& off_dist) {
+    off_part = align256((size_t)N * (size_t)N * sizeof(double));
+    off_order = off_part + align256((size_t)sort_part_doubles(N, p) * sizeof(double));
+    off_dist = off_order + align256((size_t)N * sizeof(long long));
+    return off_dist + align256((size_t)N * sizeof(double));
+}
+
+// Looks up this device's copy of the scratch array once, with the device current (called by
+// skr_ctx_create for the context's device). Returns the runtime's status of the lookup.
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_state[device] == 0) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void* ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+        g_scratch_err[device] = e;
+        if (e == hipSuccess && ptr) {
+            g_scratch_ptr[device] = ptr;
+            g_scratch_state[device] = 1;
+        } else {
+            g_scratch_state[device] = -1;
+        }
+    }
+    return g_scratch_err[device];
+}
+
+}  // namespace skr
+
+using namespace skr;
+
+extern "C" int skr_sort_noalloc(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64_t start,
+                                int64_t* order_host, double* step_d2_host) {
+    if (!ctx) return fail(SKR_EINVAL, "NULL context");
+    if (N < 0) return fail(SKR_EINVAL, "N must be >= 0");
+    if (N == 0) return SKR_OK;
+    if (!order_host) return fail(SKR_EINVAL, "order_host is NULL");
+    if (p < 1 || !params_dev) return fail(SKR_EINVAL, "need p >= 1 and params_dev");
+    if (start < 0 || start >= N) return fail(SKR_EINVAL, "start %lld out of range", (long long)start);
+    if (N > NOALLOC_NMAX)
+        return fail(SKR_EINVAL, "skr_sort_noalloc: N = %lld exceeds its limit of %ld systems", (long long)N,
+                    NOALLOC_NMAX);
+    size_t off_part, off_order, off_dist;
+    const size_t need = noalloc_layout((long)N, (long)p, off_part, off_order, off_dist);
+    if (need > NOALLOC_BYTES)
+        return fail(SKR_EINVAL, "skr_sort_noalloc: N = %lld, p = %lld needs %zu bytes of scratch (limit %zu)",
+                    (long long)N, (long long)p, need, NOALLOC_BYTES);
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= NOALLOC_MAXDEV) return fail(SKR_EINVAL, "device %d out of range", dev);
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_state[dev] == 1) base = g_scratch_ptr[dev];
+    }
+    if (!base) {
+        const hipError_t e = noalloc_setup(dev);
+        if (e != hipSuccess) return fail(SKR_EHIP, "scratch lookup on device %d failed: %s", dev, hipGetErrorString(e));
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[dev];
+    }
+    HIPCHK(hipSetDevice(dev));
+    unsigned char* b = (unsigned char*)base;
+    double* D = (double*)b;
+    double* part = (double*)(b + off_part);
+    long long* order_d = (long long*)(b + off_order);
+    double* dist_d = (double*)(b + off_dist);
+    // every entry the kernels read is written earlier in the same call (all N x N distances, the
+    // slice partials before they are combined, the whole order), so nothing needs clearing
+    launch_sort(ctx->stream, params_dev, (long)N, (long)p, (long)start, D, part, order_d, dist_d);
+    HIPLAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(order_host, order_d, N * sizeof(long long), hipMemcpyDeviceToHost, ctx->stream));
+    if (step_d2_host)
+        HIPCHK(hipMemcpyAsync(step_d2_host, dist_d, N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return SKR_OK;
+}
+

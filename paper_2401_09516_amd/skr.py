@@ -37,7 +37,7 @@ SKR_FLAG_FOLD = 2
 SKR_FLAG_MIXED = 4
 SKR_FLAG_CONTINUE = 8
 
-EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort",
+EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort", "skr_sort_noalloc",
             "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
             "skr_serve_start", "skr_submit", "skr_poll", "skr_wait", "skr_ticket_chain", "skr_serve_stats_get",
             "skr_serve_stop", "skr_recycle_get", "skr_recycle_set", "skr_workspace_bytes")
@@ -112,6 +112,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     lib.skr_version.restype = ctypes.c_char_p
     lib.skr_sort.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
     lib.skr_sort.restype = i32
+    lib.skr_sort_noalloc.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
+    lib.skr_sort_noalloc.restype = i32
     lib.skr_solve_sequence.argtypes = [vp, ctypes.POINTER(skr_op), ctypes.POINTER(vp), ctypes.POINTER(vp), i64,
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(skr_opts),
                                        ctypes.POINTER(skr_result)]
@@ -221,6 +223,11 @@ def _sort_call(fn, ctx, params, N, p, start, want_dist):
 def skr_sort(ctx: int, params, N: int, p: int, start: int = 0, want_dist: bool = True):
     """Alg. 1 on device parameters (N x p float64, row-major). Returns (order int64, step d2 or None)."""
     return _sort_call(load_library().skr_sort, ctx, params, N, p, start, want_dist)
+
+
+def skr_sort_noalloc(ctx: int, params, N: int, p: int, start: int = 0, want_dist: bool = True):
+    """skr_sort without device allocations (N <= 512; library-owned static scratch per GPU)."""
+    return _sort_call(load_library().skr_sort_noalloc, ctx, params, N, p, start, want_dist)
 
 
 def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
