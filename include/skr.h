@@ -89,14 +89,17 @@ typedef struct {
                                  before they are re-summed; done anyway above 256 workgroups
                                  (n > 65,536), where it keeps the reduction cost linear in n */
 #define SKR_FLAG_MIXED   4u   /* mixed precision: the Arnoldi vectors and the recycle pair C_k, U_k
-                                 are stored in FP32 (round to nearest even), halving the bytes the
-                                 Arnoldi steps stream; every product, sum, x, r, the operator and the
-                                 small dense problems stay FP64. Each cycle after the first starts
-                                 from the true residual r = b - A x (FP64), projected onto range(C)
-                                 (x += U C^T r, r -= C C^T r): iterative refinement with one cycle
-                                 as the inner correction. relres_true is the FP64 residual of the
-                                 FP64 solution, so rtol keeps its meaning. An extension of the
-                                 paper's method (Alg. 2 is stated in exact arithmetic). */
+                                 are stored in FP32 (round to nearest even), and the inner cycle's
+                                 products with A (the Arnoldi steps and the start-up A*Y) use the
+                                 operator's values (CSR values, stencil faces) rounded to FP32,
+                                 halving the bytes the Arnoldi steps stream; every sum and product is
+                                 formed in FP64, and x, r and the small dense problems stay FP64. Each
+                                 cycle after the first starts from the true residual r = b - A x with
+                                 the FP64 operator, projected onto range(C) (x += U C^T r,
+                                 r -= C C^T r): iterative refinement with one cycle as the inner
+                                 correction. relres_true is the FP64 residual of the FP64 solution,
+                                 so rtol keeps its meaning. An extension of the paper's method
+                                 (Alg. 2 is stated in exact arithmetic). */
 #define SKR_FLAG_CONTINUE 8u  /* skr_solve_sequence: the first system starts from the recycle space
                                  the context carries (left by the previous skr_solve_sequence on it,
                                  or set with skr_recycle_set) instead of none; it must belong to the
@@ -125,14 +128,25 @@ typedef struct {
 } skr_result;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t, NULL for
- * the default stream). Device workspace is allocated by the library on first use and owned by the
- * context. Returns SKR_EINVAL for a bad device, SKR_EHIP on runtime failure. */
-int skr_ctx_create(int device, void* hip_stream, skr_ctx** out);
+ * the default stream).
+ * arena_dev, arena_bytes: a caller-owned device buffer (e.g. a torch tensor) that the context
+ * sub-allocates for all its device memory: the workspace of each solve (one block of
+ * skr_workspace_bytes), the carried recycle space, the sort's distance matrix and outputs, the FP32
+ * operator copy of the mixed mode (4 bytes per CSR value or stencil face), and in serving every
+ * chain's workspace, resident recycle space and parameter tail (skr_workspace_bytes + 8p bytes,
+ * rounded up to 256). The buffer must stay valid until skr_ctx_destroy; the library never frees it.
+ * When a request does not fit, the call fails with SKR_ENOMEM (serving defers the admission
+ * instead, retiring idle chains first, Sec. 4.1 / App. E chains). Both NULL / 0: the library
+ * allocates its own memory. Only the serving runtime's small staging buffers (distance partials and
+ * deferred parameter copies) are allocated outside the arena.
+ * Returns SKR_EINVAL for a bad device or a half-given arena, SKR_EHIP on runtime failure. */
+int skr_ctx_create(int device, void* hip_stream, void* arena_dev, size_t arena_bytes, skr_ctx** out);
 
 /* Device bytes of the workspace a context allocates for solves of size n with GCRO-DR(m, k) (basis
- * [C V] and U, work vectors, reduction partials, small dense state); the same for both storage modes
- * (flags: SKR_FLAG_* of the solve). A serving chain adds p doubles for its parameter tail. Returns 0
- * for sizes a solve would reject (n < 1 or n >= 2^31, m outside [1, 86], k < 0, k >= m, k > 32). */
+ * [C V], U and A C, work vectors, reduction partials, small dense state), as one block; the same
+ * for both storage modes (flags: SKR_FLAG_* of the solve). A serving chain adds p doubles for its
+ * parameter tail, rounded up to 256 bytes. Returns 0 for sizes a solve would reject (n < 1 or
+ * n >= 2^31, m outside [1, 86], k < 0, k >= m, k > 32). */
 size_t skr_workspace_bytes(int64_t n, int32_t m, int32_t k, uint32_t flags);
 
 /* Free the context and its workspace (waits for its stream). NULL is accepted. */

@@ -31,9 +31,12 @@ Readings adopted where the paper is silent or loose (each is mirrored by the GPU
 Mixed-precision mode (``basis_fp32=True``; the FP32-inner / FP64-refinement variant of the method,
 an extension that the paper does not describe):
 * Every column kept in the subspace stores is rounded to FP32 when it is stored: the Arnoldi
-  vectors v_j and the recycle pair C_k, U_k (after the start-up QR and after each cycle). All
-  arithmetic, x, r, the operator, Hbar, G, the least-squares and eigen problems stay FP64; the
-  operator is applied to the stored (rounded) vector.
+  vectors v_j and the recycle pair C_k, U_k (after the start-up QR and after each cycle).
+* The inner cycle's operator is A with its stored values rounded to FP32 (``A_inner``; by default
+  the CSR values rounded, for a matrix-free stencil the matrix assembled from its rounded faces):
+  it is applied to the stored (rounded) vectors in the Arnoldi steps and in the start-up product
+  A Y. All arithmetic, x, r, Hbar, G, the least-squares and eigen problems stay FP64, and every true
+  residual b - A x uses the FP64 operator.
 * Iterative refinement at cycle granularity: every cycle starts from the true residual
   r = b - A x computed in FP64 (not at the very first cycle from x = 0, where r = b already),
   projected onto range(C) as at a system start (x += U C^T r, r -= C C^T r), so each cycle
@@ -263,12 +266,20 @@ def cycle_matrices(C: np.ndarray, U: np.ndarray, V: np.ndarray, Hbar: np.ndarray
 # ----------------------------------------------------------------------------------------------
 # One system
 # ----------------------------------------------------------------------------------------------
+def fp32_operator(A):
+    """A with its stored values rounded to FP32 (the mixed mode's inner operator of a CSR matrix)."""
+    Ai = A.copy()
+    Ai.data = fp32_store(Ai.data)
+    return Ai
+
+
 def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 10,
            rtol: float = 1e-8, maxit: int = 10000, full_cycles: bool = False,
-           basis_fp32: bool = False, keep_cycles: bool = False) -> SolveResult:
+           basis_fp32: bool = False, keep_cycles: bool = False, A_inner=None) -> SolveResult:
     """Solve A x = b from x0 = 0, recycling span(Y) (App. B.2, Alg. 2). Returns the next Y in Y_next.
-    ``basis_fp32`` selects the mixed-precision mode described in the module notes; ``keep_cycles``
-    records, per cycle, the residual norm it started from and the recycle space C it left."""
+    ``basis_fp32`` selects the mixed-precision mode described in the module notes, with inner operator
+    ``A_inner`` (default: fp32_operator(A)); ``keep_cycles`` records, per cycle, the residual norm it
+    started from and the recycle space C it left."""
     if k < 0 or m <= k or rtol <= 0:
         raise ValueError("need 0 <= k < m and rtol > 0")
     b = np.asarray(b, dtype=np.float64)
@@ -281,6 +292,7 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
         return SolveResult(x, CONVERGED, 0, 0, 0, 0.0, 0.0, Y_next=Y)
     tol_abs = rtol * bnorm
     store = fp32_store if basis_fp32 else _keep
+    Ai = (A_inner if A_inner is not None else fp32_operator(A)) if basis_fp32 else A
     r = b.copy()
     r_fresh = True                   # r is b - A x computed directly (x = 0 here) or just projected
     C = U = None
@@ -289,7 +301,7 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
     restarts = 0
     cycle_log = []
     if k > 0 and Y is not None and Y.shape[1] > 0:
-        x, r, C, U, dropped = startup(A, Y, r, store)
+        x, r, C, U, dropped = startup(Ai, Y, r, store)
         spmv += Y.shape[1]
         k_start = 0 if C is None else C.shape[1]
         # r was just projected; with FP32-stored C and U the first cycle still refines from the
@@ -330,7 +342,7 @@ def gcrodr(A, b: np.ndarray, Y: np.ndarray | None = None, m: int = 30, k: int = 
         r_fresh = False
         s = m if C is None else m - C.shape[1]
         s = min(s, maxit - iters)
-        V, Hbar, B, est, breakdown = arnoldi_cycle(A, r, C, s, tol_abs, full_cycles, store)
+        V, Hbar, B, est, breakdown = arnoldi_cycle(Ai, r, C, s, tol_abs, full_cycles, store)
         j = Hbar.shape[1]
         iters += j
         spmv += j
@@ -396,7 +408,7 @@ def gmres(A, b, m: int = 30, rtol: float = 1e-8, maxit: int = 10000) -> SolveRes
 
 def solve_sequence(As, bs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
                    maxit: int = 10000, full_cycles: bool = False, limit: int | None = None,
-                   basis_fp32: bool = False):
+                   basis_fp32: bool = False, A_inner=None):
     """Solve the systems in ``order`` (identity when None), carrying Y = U_k from each to the next.
 
     Returns a list of SolveResult indexed by original system index (None for systems not solved
@@ -409,7 +421,8 @@ def solve_sequence(As, bs, order=None, m: int = 30, k: int = 10, rtol: float = 1
     results = [None] * N
     Y = None
     for idx in order:
-        res = gcrodr(As[idx], bs[idx], Y, m, k, rtol, maxit, full_cycles, basis_fp32)
+        res = gcrodr(As[idx], bs[idx], Y, m, k, rtol, maxit, full_cycles, basis_fp32,
+                     A_inner=None if A_inner is None else A_inner[idx])
         results[idx] = res
         Y = res.Y_next
     return results

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "skr_host.hpp"
@@ -19,6 +20,7 @@ void launch_init(hipStream_t, const Work&, const double*, double*, double);
 void launch_clear_nonfinite(hipStream_t, const Work&);
 void launch_check_finite(hipStream_t, const Work&, const double*, long);
 void launch_check_sym(hipStream_t, const Work&, const DevOp&);
+void launch_to_f32(hipStream_t, const double*, float*, long);
 void launch_zero(hipStream_t, double*, int);
 void launch_copy_u(hipStream_t, const Work&, double*, long, int, int);
 void launch_step(hipStream_t, const Work&, const DevOp&, int, int, int, hipEvent_t* ev);
@@ -85,30 +87,121 @@ static void step_bytes(const DevOp& op, int64_t nvals, int kc, int j, bool mixed
     }
 }
 
-static void free_work(Work& w) {
-    double* bufs[] = {w.basis, w.U, w.Z, w.W[0], w.W[1], w.r, w.part_a, w.part_b, w.part_n, w.part, w.gpart, w.gram,
-                      w.fold_a, w.fold_b, w.fold_n,
-                      w.red1, w.red2, w.gcorr, w.H, w.Bm};
-    for (double* p : bufs)
-        if (p) (void)hipFree(p);
-    if (w.ctrl) (void)hipFree(w.ctrl);
-    if (w.coef) (void)hipFree(w.coef);
-    if (w.dense) (void)hipFree(w.dense);
-    if (w.counters) (void)hipFree(w.counters);
-    w = Work();
+// ---------------------------------------------------------------------------------------------
+// Device memory: the caller's arena or hipMalloc
+// ---------------------------------------------------------------------------------------------
+skr::Arena::Arena(void* b, size_t n) : base((char*)b), size(n / 256 * 256) {
+    // the first block starts at the first 256-byte boundary of the buffer
+    const size_t skew = (256 - ((uintptr_t)base & 255)) & 255;
+    if (size > skew) {
+        base += skew;
+        size = (n - skew) / 256 * 256;
+        if (size) free_blocks[0] = size;
+    } else {
+        size = 0;
+    }
+}
+void* skr::Arena::alloc(size_t bytes) {
+    const size_t need = round256(std::max<size_t>(bytes, 1));
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+        if (it->second < need) continue;
+        const size_t off = it->first, len = it->second;
+        free_blocks.erase(it);
+        if (len > need) free_blocks[off + need] = len - need;
+        live[off] = need;
+        in_use += need;
+        return base + off;
+    }
+    return nullptr;
+}
+void skr::Arena::release(void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = live.find((size_t)((char*)p - base));
+    if (it == live.end()) return;
+    size_t off = it->first, len = it->second;
+    live.erase(it);
+    in_use -= len;
+    auto nx = free_blocks.lower_bound(off);
+    if (nx != free_blocks.end() && nx->first == off + len) {
+        len += nx->second;
+        free_blocks.erase(nx);
+    }
+    auto pv = free_blocks.lower_bound(off);
+    if (pv != free_blocks.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            off = pv->first;
+            len += pv->second;
+            free_blocks.erase(pv);
+        }
+    }
+    free_blocks[off] = len;
+}
+bool skr::Arena::can_fit(const size_t* sizes, int count) {
+    std::lock_guard<std::mutex> lk(mu);
+    std::map<size_t, size_t> fb = free_blocks;
+    for (int q = 0; q < count; ++q) {
+        const size_t need = round256(std::max<size_t>(sizes[q], 1));
+        auto it = fb.begin();
+        while (it != fb.end() && it->second < need) ++it;
+        if (it == fb.end()) return false;
+        const size_t off = it->first, len = it->second;
+        fb.erase(it);
+        if (len > need) fb[off + need] = len - need;
+    }
+    return true;
+}
+hipError_t skr::dev_alloc(skr_ctx* ctx, void** p, size_t bytes) {
+    if (!ctx->arena) return hipMalloc(p, std::max<size_t>(bytes, 1));
+    *p = ctx->arena->alloc(bytes);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+void skr::dev_free(skr_ctx* ctx, void* p) {
+    if (!p) return;
+    if (ctx->arena) ctx->arena->release(p);
+    else (void)hipFree(p);
 }
 
-template <class T>
-static hipError_t dalloc(T** p, size_t count) {
-    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+// Places every workspace buffer for (w.n, w.m, w.k) in one block at base, each on a 256-byte
+// boundary (base == nullptr: measures only); returns the block's bytes.
+static size_t layout_work(Work& w, char* base) {
+    const size_t ld = (size_t)w.ld;
+    size_t off = 0;
+    auto take = [&](auto*& ptr, size_t count) {
+        using T = std::remove_reference_t<decltype(*ptr)>;
+        off = round256(off);
+        ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+    };
+    take(w.basis, (size_t)(w.k + w.m + 1) * ld);
+    take(w.U, (size_t)std::max(w.k, 1) * ld);
+    take(w.Z, (size_t)std::max(w.k, 1) * ld);
+    take(w.W[0], ld);
+    take(w.W[1], ld);
+    take(w.r, ld);
+    take(w.part_a, (size_t)w.nblk * NC);
+    take(w.part_b, (size_t)w.nblk * NC);
+    take(w.part_n, (size_t)w.nblk);
+    take(w.part, (size_t)w.nblk * NC);
+    take(w.gpart, (size_t)w.ngblk * w.gram_max);
+    take(w.gram, w.gram_max);
+    take(w.fold_a, (size_t)NFOLD * NC);
+    take(w.fold_b, (size_t)NFOLD * NC);
+    take(w.fold_n, (size_t)NFOLD);
+    take(w.red1, NC);
+    take(w.red2, NC);
+    take(w.gcorr, 2 * NC);
+    take(w.H, (size_t)LDH * MMAX);
+    take(w.Bm, (size_t)KMAX * MMAX);
+    take(w.ctrl, 1);
+    take(w.coef, 1);
+    take(w.dense, 1);
+    take(w.counters, 8);
+    return round256(off);
 }
 
-static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
-    Work& w = ctx->w;
-    if (w.basis && w.n == n && w.m == m && w.k == k) return SKR_OK;
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->carry_valid = false;      // the carried recycle space goes with the old workspace
-    free_work(w);
+static void set_shape(Work& w, int n, int m, int k) {
     w.n = n;
     w.m = m;
     w.k = k;
@@ -116,37 +209,35 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
     w.nblk = (n + ROWS - 1) / ROWS;
     w.ngblk = std::min(256, std::max(1, (n + 255) / 256));
     w.gram_max = (size_t)gram_cols_max(m, k);
+}
+
+static void free_work(skr_ctx* ctx) {
+    dev_free(ctx, ctx->w.block);
+    ctx->w = Work();
+}
+
+static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
+    Work& w = ctx->w;
+    if (w.block && w.n == n && w.m == m && w.k == k) return SKR_OK;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->carry_valid = false;      // the carried recycle space goes with the old workspace
+    free_work(ctx);
+    set_shape(w, n, m, k);
+    const size_t bytes = layout_work(w, nullptr);
+    void* blk = nullptr;
+    const hipError_t ea = dev_alloc(ctx, &blk, bytes);
+    if (ea != hipSuccess) {
+        w = Work();
+        if (ctx->arena)
+            return fail(SKR_ENOMEM, "the workspace for n = %d, m = %d, k = %d needs %zu bytes of the arena "
+                        "(%zu of %zu bytes in use)", n, m, k, bytes, ctx->arena->in_use, ctx->arena->size);
+        return fail(SKR_ENOMEM, "device workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(ea));
+    }
+    w.block = blk;
+    layout_work(w, (char*)blk);
     const size_t ld = (size_t)w.ld;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    chk(dalloc(&w.basis, (size_t)(k + m + 1) * ld));
-    chk(dalloc(&w.U, (size_t)std::max(k, 1) * ld));
-    chk(dalloc(&w.Z, (size_t)std::max(k, 1) * ld));
-    chk(dalloc(&w.W[0], ld));
-    chk(dalloc(&w.W[1], ld));
-    chk(dalloc(&w.r, ld));
-    chk(dalloc(&w.part_a, (size_t)w.nblk * NC));
-    chk(dalloc(&w.part_b, (size_t)w.nblk * NC));
-    chk(dalloc(&w.part_n, (size_t)w.nblk));
-    chk(dalloc(&w.part, (size_t)w.nblk * NC));
-    chk(dalloc(&w.gpart, (size_t)w.ngblk * w.gram_max));
-    chk(dalloc(&w.gram, w.gram_max));
-    chk(dalloc(&w.fold_a, (size_t)NFOLD * NC));
-    chk(dalloc(&w.fold_b, (size_t)NFOLD * NC));
-    chk(dalloc(&w.fold_n, (size_t)NFOLD));
-    chk(dalloc(&w.red1, NC));
-    chk(dalloc(&w.red2, NC));
-    chk(dalloc(&w.gcorr, 2 * NC));
-    chk(dalloc(&w.H, (size_t)LDH * MMAX));
-    chk(dalloc(&w.Bm, (size_t)KMAX * MMAX));
-    chk(dalloc(&w.ctrl, 1));
-    chk(dalloc(&w.coef, 1));
-    chk(dalloc(&w.dense, 1));
-    chk(dalloc(&w.counters, 8));
-    if (e != hipSuccess) {
-        free_work(w);
-        return fail(SKR_ENOMEM, "device workspace allocation failed: %s", hipGetErrorString(e));
-    }
     // zero everything once so that unused basis columns never hold NaN bit patterns
     chk(hipMemsetAsync(w.basis, 0, (size_t)(k + m + 1) * ld * sizeof(double), ctx->stream));
     chk(hipMemsetAsync(w.U, 0, (size_t)std::max(k, 1) * ld * sizeof(double), ctx->stream));
@@ -163,14 +254,9 @@ static int ensure_work(skr_ctx* ctx, int n, int m, int k) {
 }
 
 size_t skr::work_bytes(int n, int m, int k) {
-    const size_t ld = (size_t)((n + 63) / 64 * 64);
-    const size_t nblk = (size_t)((n + ROWS - 1) / ROWS);
-    const size_t ngblk = (size_t)std::min(256, std::max(1, (n + 255) / 256));
-    const size_t gmax = (size_t)gram_cols_max(m, k);
-    size_t d = (size_t)(k + m + 1) * ld + 2 * (size_t)std::max(k, 1) * ld + 3 * ld;   // basis, U, Z, W[2], r
-    d += 3 * nblk * NC + nblk + ngblk * gmax + gmax + 2 * (size_t)NFOLD * NC + NFOLD + 4 * NC;
-    d += (size_t)LDH * MMAX + (size_t)KMAX * MMAX;
-    return d * sizeof(double) + sizeof(Ctrl) + sizeof(Coef) + sizeof(DenseWork) + 8 * sizeof(unsigned);
+    Work w;
+    set_shape(w, n, m, k);
+    return layout_work(w, nullptr);
 }
 
 static int read_ctrl(skr_ctx* ctx) {
@@ -261,6 +347,46 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     if (hc.bnorm == 0.0) {
         res.status = SKR_CONVERGED;
         return SKR_OK;
+    }
+    if (w.mixed) {
+        // the inner cycle's operator: its values (CSR) or faces (stencils) rounded to FP32; true
+        // residuals keep the FP64 operator
+        long cnt[3] = {0, 0, 0};
+        const double* srcs[3] = {nullptr, nullptr, nullptr};
+        if (op.kind == SKR_OP_CSR) {
+            cnt[0] = (long)nvals;
+            srcs[0] = op.val;
+        } else {
+            const long nzl = op.kind == SKR_OP_STENCIL7 ? (long)op.nz : 1L;
+            cnt[0] = nzl * op.ny * (op.nx + 1);
+            cnt[1] = nzl * (op.ny + 1) * op.nx;
+            srcs[0] = op.ax;
+            srcs[1] = op.ay;
+            if (op.kind == SKR_OP_STENCIL7) {
+                cnt[2] = (nzl + 1) * op.ny * op.nx;
+                srcs[2] = op.az;
+            }
+        }
+        const size_t need = (size_t)(cnt[0] + cnt[1] + cnt[2]);
+        if (ctx->op32_cap < need) {
+            dev_free(ctx, ctx->op32);
+            ctx->op32 = nullptr;
+            ctx->op32_cap = 0;
+            if (dev_alloc(ctx, (void**)&ctx->op32, need * sizeof(float)) != hipSuccess)
+                return fail(SKR_ENOMEM, "FP32 operator copy (%zu bytes)", need * sizeof(float));
+            ctx->op32_cap = need;
+        }
+        float* dst32 = ctx->op32;
+        const float* parts[3] = {dst32, dst32 + cnt[0], dst32 + cnt[0] + cnt[1]};
+        for (int q = 0; q < 3; ++q) launch_to_f32(s, srcs[q], (float*)parts[q], cnt[q]);
+        HIPLAUNCHCHK();
+        if (op.kind == SKR_OP_CSR) {
+            op.val32 = parts[0];
+        } else {
+            op.ax32 = parts[0];
+            op.ay32 = parts[1];
+            op.az32 = cnt[2] ? parts[2] : nullptr;
+        }
     }
     const double bnorm = hc.bnorm, tol_abs = hc.tol_abs;
     int64_t iters = 0, spmv = 0;
@@ -488,11 +614,12 @@ int skr::prepare_solve(skr_ctx* ctx, int n, const skr_opts& opts) {
     return SKR_OK;
 }
 
-int skr::ctx_make(int device, hipStream_t stream, skr_ctx** out) {
+int skr::ctx_make(int device, hipStream_t stream, skr_ctx** out, Arena* arena) {
     HIPCHK(hipSetDevice(device));
     skr_ctx* c = new skr_ctx();
     c->device = device;
     c->stream = stream;
+    c->arena = arena;
     if (hipHostMalloc((void**)&c->hctrl, sizeof(CtrlHost), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->hkeff, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -512,13 +639,20 @@ const char* skr_version(void) { return "skr-gfx950 0.1"; }
 
 const char* skr_last_error(void) { return g_err.c_str(); }
 
-int skr_ctx_create(int device, void* hip_stream, skr_ctx** out) {
+int skr_ctx_create(int device, void* hip_stream, void* arena_dev, size_t arena_bytes, skr_ctx** out) {
     if (!out) return fail(SKR_EINVAL, "out is NULL");
     *out = nullptr;
+    if (!arena_dev != !arena_bytes) return fail(SKR_EINVAL, "arena_dev and arena_bytes must be both set or both 0");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(SKR_EINVAL, "device %d out of range (%d devices)", device, ndev);
-    const int rc = ctx_make(device, (hipStream_t)hip_stream, out);
+    Arena* ar = arena_dev ? new Arena(arena_dev, arena_bytes) : nullptr;
+    const int rc = ctx_make(device, (hipStream_t)hip_stream, out, ar);
+    if (rc != SKR_OK) {
+        delete ar;
+        return rc;
+    }
+    (*out)->owns_arena = ar != nullptr;
     // locate this device's copy of skr_sort_noalloc's scratch array once, with the device current; a
     // failure is reported by that entry point, not here
     if (rc == SKR_OK) (void)noalloc_setup(device);
@@ -531,15 +665,17 @@ int skr_ctx_destroy(skr_ctx* ctx) {
     serve_free(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    free_work(ctx->w);
-    if (ctx->sortD) (void)hipFree(ctx->sortD);
-    if (ctx->sortP) (void)hipFree(ctx->sortP);
-    if (ctx->order_d) (void)hipFree(ctx->order_d);
-    if (ctx->dist_d) (void)hipFree(ctx->dist_d);
+    free_work(ctx);
+    dev_free(ctx, ctx->sortD);
+    dev_free(ctx, ctx->sortP);
+    dev_free(ctx, ctx->order_d);
+    dev_free(ctx, ctx->dist_d);
+    dev_free(ctx, ctx->op32);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
     if (ctx->hkeff) (void)hipHostFree(ctx->hkeff);
     for (int q = 0; q < PROF_MAXSAMP * 6; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
+    if (ctx->owns_arena) delete ctx->arena;
     delete ctx;
     return SKR_OK;
 }
@@ -601,30 +737,30 @@ int skr_sort(skr_ctx* ctx, const double* params_dev, int64_t N, int64_t p, int64
     HIPCHK(hipSetDevice(ctx->device));
     const size_t need = (size_t)N * (size_t)N;
     if (ctx->sortD_cap < need) {
-        if (ctx->sortD) (void)hipFree(ctx->sortD);
+        dev_free(ctx, ctx->sortD);
         ctx->sortD = nullptr;
         ctx->sortD_cap = 0;
-        if (hipMalloc((void**)&ctx->sortD, need * sizeof(double)) != hipSuccess)
+        if (dev_alloc(ctx, (void**)&ctx->sortD, need * sizeof(double)) != hipSuccess)
             return fail(SKR_ENOMEM, "sort distance matrix (%zu bytes)", need * sizeof(double));
         ctx->sortD_cap = need;
     }
     if (ctx->sortN_cap < (size_t)N) {
-        if (ctx->order_d) (void)hipFree(ctx->order_d);
-        if (ctx->dist_d) (void)hipFree(ctx->dist_d);
+        dev_free(ctx, ctx->order_d);
+        dev_free(ctx, ctx->dist_d);
         ctx->order_d = nullptr;
         ctx->dist_d = nullptr;
         ctx->sortN_cap = 0;
-        if (hipMalloc((void**)&ctx->order_d, N * sizeof(long long)) != hipSuccess ||
-            hipMalloc((void**)&ctx->dist_d, N * sizeof(double)) != hipSuccess)
+        if (dev_alloc(ctx, (void**)&ctx->order_d, N * sizeof(long long)) != hipSuccess ||
+            dev_alloc(ctx, (void**)&ctx->dist_d, N * sizeof(double)) != hipSuccess)
             return fail(SKR_ENOMEM, "sort output buffers");
         ctx->sortN_cap = (size_t)N;
     }
     const size_t needp = (size_t)sort_part_doubles((long)N, (long)p);
     if (ctx->sortP_cap < needp) {
-        if (ctx->sortP) (void)hipFree(ctx->sortP);
+        dev_free(ctx, ctx->sortP);
         ctx->sortP = nullptr;
         ctx->sortP_cap = 0;
-        if (hipMalloc((void**)&ctx->sortP, needp * sizeof(double)) != hipSuccess)
+        if (dev_alloc(ctx, (void**)&ctx->sortP, needp * sizeof(double)) != hipSuccess)
             return fail(SKR_ENOMEM, "sort slice partials (%zu bytes)", needp * sizeof(double));
         ctx->sortP_cap = needp;
     }

@@ -40,6 +40,12 @@ struct DevOp {
     const double* ax;
     const double* ay;
     const double* az;
+    // FP32 copies of the values (CSR) or faces (stencils) for the products of the mixed mode's inner
+    // cycle (set only there)
+    const float* val32;
+    const float* ax32;
+    const float* ay32;
+    const float* az32;
 };
 
 // Round to the nearest FP32 value (ties to even), held in FP64.
@@ -49,14 +55,19 @@ __device__ __forceinline__ double rnd32(double v) { return (double)(float)v; }
 // operator kind when the caller knows it at compile time (each kind then gets its own register
 // allocation), or -1 to branch on op.kind. XT is the element type of x. With RND the row is that of
 // A v with v = rnd32(scale * x) (the FP32-stored vector the product is defined on), and no scaling
-// follows.
-template <int KIND, typename XT = double, bool RND = false>
+// follows. With OP32 the operator's values are its FP32 copies (op.val32, op.ax32, ...); the
+// arithmetic stays FP64.
+template <int KIND, typename XT = double, bool RND = false, bool OP32 = false>
 __device__ __forceinline__ double op_row_k(const DevOp& op, const XT* __restrict__ x, int i, double scale) {
     const int kind = KIND >= 0 ? KIND : op.kind;
     auto X = [&](int idx) -> double {
         const double v = (double)x[idx];
         return RND ? rnd32(v * scale) : v;
     };
+    auto VAL = [&](int q) -> double { return OP32 ? (double)op.val32[q] : op.val[q]; };
+    auto FX = [&](int q) -> double { return OP32 ? (double)op.ax32[q] : op.ax[q]; };
+    auto FY = [&](int q) -> double { return OP32 ? (double)op.ay32[q] : op.ay[q]; };
+    auto FZ = [&](int q) -> double { return OP32 ? (double)op.az32[q] : op.az[q]; };
     double s = 0.0;
     if (kind == SKR_OP_CSR) {
         // Entries in groups of 8: every index, value and gather load of a group is in flight before
@@ -69,7 +80,7 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const XT* __restrict
             for (int u = 0; u < 8; ++u) {
                 const int q = min(e + u, e1 - 1);
                 c[u] = op.colind[q];
-                v[u] = op.val[q];
+                v[u] = VAL(q);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) xv[u] = X(c[u]);
@@ -81,9 +92,9 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const XT* __restrict
         const int nx = op.nx, ny = op.ny, nz = op.nz, nxy = nx * ny;
         const int gz = i / nxy, gyx = i - gz * nxy, gy = gyx / nx, gx = gyx - gy * nx;
         const int fx = (gz * ny + gy) * (nx + 1) + gx, fy = (gz * (ny + 1) + gy) * nx + gx, fz = gz * nxy + gyx;
-        const double aw = op.ax[fx], ae = op.ax[fx + 1];
-        const double as = op.ay[fy], an = op.ay[fy + nx];
-        const double ad = op.az[fz], au = op.az[fz + nxy];
+        const double aw = FX(fx), ae = FX(fx + 1);
+        const double as = FY(fy), an = FY(fy + nx);
+        const double ad = FZ(fz), au = FZ(fz + nxy);
         // neighbour loads at clamped indices (a missing neighbour reads x[i]); its term is selected away
         const bool hw = gx > 0, he = gx < nx - 1, hs = gy > 0, hn = gy < ny - 1, hd = gz > 0, hu = gz < nz - 1;
         const double xc = X(i);
@@ -101,8 +112,8 @@ __device__ __forceinline__ double op_row_k(const DevOp& op, const XT* __restrict
     } else {
         const int nx = op.nx, ny = op.ny;
         const int r = i / nx, c = i - r * nx;
-        const double aw = op.ax[r * (nx + 1) + c], ae = op.ax[r * (nx + 1) + c + 1];
-        const double an = op.ay[r * nx + c], as = op.ay[(r + 1) * nx + c];
+        const double aw = FX(r * (nx + 1) + c), ae = FX(r * (nx + 1) + c + 1);
+        const double an = FY(r * nx + c), as = FY((r + 1) * nx + c);
         const bool hw = c > 0, he = c < nx - 1, hn = r > 0, hs = r < ny - 1;
         const double xc = X(i);
         const double xw = X(hw ? i - 1 : i), xe = X(he ? i + 1 : i);
@@ -442,6 +453,7 @@ __device__ __forceinline__ int logical_block(int b, int nblk) {
 // ---------------------------------------------------------------------------------------------
 struct Work {
     int n = 0, ld = 0, nblk = 0, m = 0, k = 0;
+    void* block = nullptr;       // the one device block every buffer below lives in
     // [C (k cols) | V (m+1 cols)] and U (k cols), column-major, leading dim ld; the elements are
     // doubles, or floats when mixed (the buffers are sized for doubles either way)
     double* basis = nullptr;

@@ -64,6 +64,7 @@ struct Chain {
     int64_t admitted = 0;
     size_t bytes = 0;
     uint64_t last_use = 0;
+    skr_ctx* owner = nullptr;     // the serving context (its allocator holds tail)
 };
 
 }  // namespace
@@ -97,7 +98,9 @@ struct Server {
 
 namespace {
 
-size_t chain_bytes(int n, int m, int k, int64_t p) { return work_bytes(n, m, k) + (size_t)p * sizeof(double); }
+size_t chain_bytes(int n, int m, int k, int64_t p) {
+    return work_bytes(n, m, k) + round256((size_t)p * sizeof(double));
+}
 
 bool same_shape(const Chain* c, const Job& j) {
     return c->n == j.op.n && c->p == j.p && c->m == j.opts.m && c->k == j.opts.k &&
@@ -109,7 +112,8 @@ void free_chain(Chain* c) {
         (void)hipStreamSynchronize(c->stream);
         skr_ctx_destroy(c->ctx);
     }
-    if (c->tail) (void)hipFree(c->tail);
+    if (c->tail) dev_free(c->owner, c->tail);
+    c->tail = nullptr;
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -153,14 +157,22 @@ int distances(Server* S, const double* params, int64_t p, const std::vector<Chai
     return SKR_OK;
 }
 
-bool can_add(Server* S, size_t bytes) {
+// Room for one more chain of `bytes` (its workspace block of `wbytes` and its parameter tail): under
+// the chain count and the byte budget of the serving options, and, on a context with a caller arena,
+// both blocks must fit the arena's free blocks now.
+bool can_add(Server* S, size_t bytes, size_t wbytes) {
     if ((int)S->chains.size() >= S->o.max_chains) return false;
-    return S->o.arena_bytes == 0 || S->bytes_in_use + bytes <= S->o.arena_bytes;
+    if (S->o.arena_bytes != 0 && S->bytes_in_use + bytes > S->o.arena_bytes) return false;
+    if (S->owner->arena) {
+        const size_t sz[2] = {wbytes, bytes - wbytes};
+        if (!S->owner->arena->can_fit(sz, 2)) return false;
+    }
+    return true;
 }
 
 // Retire idle chains, least recently used first, until a chain of `bytes` can be added.
-void make_room(Server* S, size_t bytes) {
-    while (!can_add(S, bytes)) {
+void make_room(Server* S, size_t bytes, size_t wbytes) {
+    while (!can_add(S, bytes, wbytes)) {
         Chain* victim = nullptr;
         for (auto& kv : S->chains) {
             Chain* c = kv.second;
@@ -185,12 +197,13 @@ int new_chain(Server* S, const Job& j, Chain** out) {
     c->mixed = j.opts.flags & SKR_FLAG_MIXED;
     c->p = j.p;
     c->bytes = chain_bytes(c->n, c->m, c->k, c->p);
+    c->owner = S->owner;
     int rc = SKR_OK;
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
         rc = fail(SKR_EHIP, "chain stream creation failed");
-    } else if ((rc = ctx_make(S->owner->device, c->stream, &c->ctx)) == SKR_OK) {
+    } else if ((rc = ctx_make(S->owner->device, c->stream, &c->ctx, S->owner->arena)) == SKR_OK) {
         if ((rc = prepare_solve(c->ctx, c->n, j.opts)) == SKR_OK &&
-            hipMalloc((void**)&c->tail, (size_t)c->p * sizeof(double)) != hipSuccess)
+            dev_alloc(S->owner, (void**)&c->tail, (size_t)c->p * sizeof(double)) != hipSuccess)
             rc = fail(SKR_ENOMEM, "chain parameter buffer (%lld doubles)", (long long)c->p);
     }
     if (rc) {
@@ -212,12 +225,13 @@ int assign(Server* S, uint64_t t, const double* params, bool& assigned) {
     // candidates: the chains of the job's shape that are not full (all of them when every one is
     // full and no chain can be added, so the job still joins the nearest)
     const size_t bytes = chain_bytes(j.op.n, j.opts.m, j.opts.k, j.p);
+    const size_t wbytes = work_bytes(j.op.n, j.opts.m, j.opts.k);
     const int cap = S->o.max_chain_systems;
     std::vector<Chain*> cand, full;
     for (auto& kv : S->chains)
         if (same_shape(kv.second, j)) (cap > 0 && kv.second->admitted >= cap ? full : cand).push_back(kv.second);
     bool all_full = cand.empty() && !full.empty();
-    if (all_full && !can_add(S, bytes)) {
+    if (all_full && !can_add(S, bytes, wbytes)) {
         cand.swap(full);
         all_full = false;
     }
@@ -240,10 +254,10 @@ int assign(Server* S, uint64_t t, const double* params, bool& assigned) {
     if (all_full) {
         if ((rc = new_chain(S, j, &target))) return rc;
     } else if (!best) {
-        make_room(S, bytes);
-        if (!can_add(S, bytes)) return SKR_OK;       // deferred
+        make_room(S, bytes, wbytes);
+        if (!can_add(S, bytes, wbytes)) return SKR_OK;       // deferred
         if ((rc = new_chain(S, j, &target))) return rc;
-    } else if (bd > S->o.split_d2_rel * j.pnorm2 && can_add(S, bytes)) {
+    } else if (bd > S->o.split_d2_rel * j.pnorm2 && can_add(S, bytes, wbytes)) {
         if ((rc = new_chain(S, j, &target))) return rc;
     }
     HIPCHK(hipMemcpyAsync(target->tail, params, (size_t)j.p * sizeof(double), hipMemcpyDeviceToDevice,
@@ -388,6 +402,9 @@ int skr_submit(skr_ctx* ctx, const skr_op* op, const double* params_dev, int64_t
     if (S->o.arena_bytes && bytes > S->o.arena_bytes)
         return fail(SKR_ENOMEM, "a chain of this shape needs %zu bytes, more than the arena (%llu)", bytes,
                     (unsigned long long)S->o.arena_bytes);
+    if (ctx->arena && bytes > ctx->arena->size)
+        return fail(SKR_ENOMEM, "a chain of this shape needs %zu bytes, more than the context's arena (%zu)",
+                    bytes, ctx->arena->size);
     HIPCHK(hipSetDevice(ctx->device));
     std::unique_lock<std::mutex> lk(S->mu);
     if (S->stopping) return fail(SKR_EINVAL, "serving is stopping");

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     double vj, w;
     if constexpr (MIX) {
         vj = rnd32(xi * scale);
-        w = op_row_k<KIND, double, true>(op, src, ii, scale);
+        w = op_row_k<KIND, double, true, true>(op, src, ii, scale);
     } else {
         vj = xi * scale;
         w = wraw * scale;
@@ -944,7 +944,12 @@ __global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const BT* __restrict__ 
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i >= op.n) return;
     for (int c = 0; c < kin; ++c)
-        Z[(size_t)c * ld + i] = (BT)op_row_k<-1, BT, false>(op, Y + (size_t)c * ld, i, 1.0);
+        Z[(size_t)c * ld + i] = (BT)op_row_k<-1, BT, false, sizeof(BT) == 4>(op, Y + (size_t)c * ld, i, 1.0);
+}
+
+// FP32 copy of an operator array (round to nearest even): the mixed mode's inner operator.
+__global__ __launch_bounds__(ROWS) void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long count) {
+    for (long e = blockIdx.x * (long)ROWS + threadIdx.x; e < count; e += (long)gridDim.x * ROWS) dst[e] = (float)src[e];
 }
 
 // Z = A C for the kc <= KB recycled columns C = basis columns 0..kc-1 (FP64), the product the merged
@@ -1210,6 +1215,11 @@ void launch_clear_nonfinite(hipStream_t s, const Work& w) {
 void launch_check_sym(hipStream_t s, const Work& w, const DevOp& op) {
     if (op.kind == SKR_OP_CSR)
         hipLaunchKernelGGL(k_check_sym_csr, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, w.ctrl);
+}
+void launch_to_f32(hipStream_t s, const double* src, float* dst, long count) {
+    if (count <= 0) return;
+    const int g = (int)std::min<long>(2048, (count + ROWS - 1) / ROWS);
+    hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(ROWS), 0, s, src, dst, count);
 }
 void launch_check_finite(hipStream_t s, const Work& w, const double* v, long count) {
     if (count <= 0) return;

@@ -102,7 +102,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         raise ImportError(f"{p} is missing: build it with __graft_entry__.build()")
     lib = ctypes.CDLL(p)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
-    lib.skr_ctx_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+    lib.skr_ctx_create.argtypes = [i32, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     lib.skr_ctx_create.restype = i32
     lib.skr_ctx_destroy.argtypes = [vp]
     lib.skr_ctx_destroy.restype = i32
@@ -200,11 +200,18 @@ def skr_version() -> str:
     return load_library().skr_version().decode()
 
 
-def skr_ctx_create(device: int = 0, stream=None) -> int:
-    """Create a context on ``device`` enqueuing on ``stream`` (a hipStream_t address, or None)."""
+def skr_ctx_create(device: int = 0, stream=None, arena=None, arena_bytes: int = 0) -> int:
+    """Create a context on ``device`` enqueuing on ``stream`` (a hipStream_t address, or None). ``arena``:
+    optional caller-owned device buffer (a tensor or an address) the context sub-allocates all its device
+    memory from; ``arena_bytes`` defaults to the tensor's size in bytes. The caller keeps it alive."""
     out = ctypes.c_void_p()
     s = stream if isinstance(stream, int) or stream is None else int(stream)
-    _check(load_library().skr_ctx_create(device, s, ctypes.byref(out)))
+    ap = None
+    if arena is not None:
+        ap = _ptr(arena)
+        if not arena_bytes and hasattr(arena, "numel"):
+            arena_bytes = arena.numel() * arena.element_size()
+    _check(load_library().skr_ctx_create(device, s, ap, int(arena_bytes), ctypes.byref(out)))
     return out.value
 
 

@@ -3,6 +3,7 @@ C_k, U_k) with FP64 arithmetic, and one refinement step (a cycle from the true F
 cycle. The paper fixes the method in exact arithmetic; these pins check what that mode must
 preserve and what it must change:
 * the stored columns are exactly FP32 values, rounded to nearest (IEEE 754 binary32);
+* the inner cycle's operator is A with its values rounded to FP32, while true residuals use A;
 * the Arnoldi and recycle relations still hold, to FP32 storage accuracy;
 * because x and r stay FP64 and each cycle restarts from the true residual, the solve reaches
   residuals far below what any FP32 iterate can represent, and the solutions match a direct solve;
@@ -15,8 +16,9 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import CONVERGED, gcrodr, solve_sequence
-from oracle.solver import arnoldi_cycle, fp32_store, qr_pos
+from oracle.solver import arnoldi_cycle, fp32_operator, fp32_store, qr_pos
 from workloads import darcy_sequence
+from workloads.darcy import assemble_csr
 
 
 @pytest.fixture(scope="module")
@@ -115,3 +117,51 @@ def test_one_refinement_product_per_cycle(darcy16):
     # FP64: Arnoldi products + the final true residual; mixed: + one residual per later cycle
     assert r64.spmv == r64.iters + 1
     assert r32.spmv == r32.iters + (r32.cycles - 1) + 1
+
+
+def test_fp32_operator_rounds_every_value():
+    A = darcy_sequence(8, 1)[0].A
+    Ai = fp32_operator(A)
+    assert (Ai.indptr == A.indptr).all() and (Ai.indices == A.indices).all()
+    assert is_fp32(Ai.data) and not is_fp32(A.data)
+    assert np.all(np.abs(Ai.data - A.data) <= 2.0 ** -24 * np.abs(A.data))
+    assert A.data.dtype == np.float64 and not np.shares_memory(Ai.data, A.data)
+
+
+def test_inner_operator_is_the_fp32_one(monkeypatch):
+    # the operator a mixed-mode solve hands to its Arnoldi cycles and its start-up product is A with
+    # its values rounded to FP32 (or the given inner operator: a stencil's is assembled from its
+    # rounded faces, which differs from the rounded CSR values); an FP64 solve hands A itself
+    import oracle.solver as S
+    s = darcy_sequence(24, 2, first_seed=3)
+    A = s[1].A
+    Ai_csr = fp32_operator(A)
+    Ai_st = assemble_csr(fp32_store(s[1].ax), fp32_store(s[1].ay), s[1].inv_h2)
+    assert np.abs(Ai_st - Ai_csr).max() > 0.0
+    Y = gcrodr(s[0].A, s[0].b, None, 20, 6, 1e-8, 5000).Y_next
+    seen = []
+    orig_cycle, orig_start = S.arnoldi_cycle, S.startup
+    monkeypatch.setattr(S, "arnoldi_cycle", lambda Aop, *a, **kw: (seen.append(Aop), orig_cycle(Aop, *a, **kw))[1])
+    monkeypatch.setattr(S, "startup", lambda Aop, *a, **kw: (seen.append(Aop), orig_start(Aop, *a, **kw))[1])
+    for inner, want, fp32 in ((None, Ai_csr, True), (Ai_st, Ai_st, True), (None, A, False)):
+        seen.clear()
+        r = S.gcrodr(A, s[1].b, Y, 20, 6, 1e-8, 5000, basis_fp32=fp32, A_inner=inner)
+        assert r.status == CONVERGED and len(seen) >= 2
+        for Aop in seen:
+            assert (abs(Aop - want)).max() == 0.0
+    # the FP32 operator changes the Arnoldi relation at its rounding level only
+    V, Hbar, B, est, brk = arnoldi_cycle(Ai_csr, s[1].b, None, 20, 0.0)
+    j = Hbar.shape[1]
+    ref = np.linalg.norm(Ai_csr @ V[:, :j])
+    assert np.linalg.norm(Ai_csr @ V[:, :j] - V @ Hbar) / ref < 1e-13
+    assert 1e-10 < np.linalg.norm(A @ V[:, :j] - V @ Hbar) / ref < 1e-6
+
+
+def test_mixed_solutions_use_fp64_residuals(darcy16):
+    # the refinement's true residuals use the FP64 operator: a solve at rtol 1e-11 reaches it with A,
+    # which the FP32-rounded operator alone could not certify
+    s = darcy16[1]
+    r = gcrodr(s.A, s.b, None, 30, 10, 1e-11, 20000, basis_fp32=True)
+    assert r.status == CONVERGED
+    assert np.linalg.norm(s.b - s.A @ r.x) <= 1e-11 * np.linalg.norm(s.b) * (1 + 1e-9)
+    assert np.linalg.norm(s.b - fp32_operator(s.A) @ r.x) > 1e-9 * np.linalg.norm(s.b)
