@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--chains", type=int, default=1,
                     help="split the sorted order into this many contiguous chains, solved concurrently on "
                          "their own contexts and streams (the sorted-partition parallel scheme, App. E)")
+    ap.add_argument("--chains-form", choices=["batched", "streams"], default="batched",
+                    help="--chains C > 1: all chains in lockstep through skr_solve_chains, one call per round "
+                         "of systems (default), or one host thread and stream per chain")
     ap.add_argument("--gmres-systems", type=int, default=40, help="prefix of the sorted chain solved by GMRES(m)")
     ap.add_argument("--cpu-systems", type=int, default=8, help="oracle sample: first systems of the sorted chain")
     ap.add_argument("--no-cpu", action="store_true")
@@ -106,6 +109,9 @@ def parse():
                     help="time-stepping mode: unsteady advection-diffusion, --chains chains of --steps-per-chain "
                          "backward-Euler steps on a --grid^2 mesh, each chain solved as a chain of the serving runtime")
     ap.add_argument("--steps-per-chain", type=int, default=32)
+    ap.add_argument("--advdiff-form", choices=["both", "batched", "serve"], default="both",
+                    help="--advdiff: all chains in lockstep (skr_solve_chains, one call per time step), the "
+                         "serving runtime (one submission per step and chain), or both")
     a = ap.parse_args()
     if a.grid is None:
         a.grid = 256 if a.dim == 2 else 128
@@ -232,9 +238,11 @@ def serve_bench(a):
 
 
 def advdiff_bench(a):
-    """Backward-Euler chains A x^{t+1} = x^t / dt: one host thread per chain submits each step when
-    the previous one is done; the serving runtime keeps each chain's recycle space resident and runs
-    up to --serve-workers chains at once on their own streams."""
+    """Backward-Euler chains A x^{t+1} = x^t / dt in two forms. Batched: one skr_solve_chains call
+    per time step advances every chain by one step in lockstep (each launch covers all chains; the
+    recycle spaces stay on the context between calls). Serving: one host thread per chain submits
+    each step when the previous one is done; the serving runtime keeps each chain's recycle space
+    resident and runs up to --serve-workers chains at once on their own streams."""
     import threading
 
     import numpy as np
@@ -299,26 +307,66 @@ def advdiff_bench(a):
                     iters_later=float(np.mean([r["iters"] for rc in res for r in rc[1:]])) if nsteps > 1 else None,
                     max_relres=max(r["relres_true"] for r in flat), chains=stats["chains_created"])
 
-    log("warm-up")
-    run(min(C, 4), 2, a.k)
-    log(f"timed run: {C} chains x {T} steps")
-    main = run(C, T, a.k)
+    def run_batched(nch, nsteps, k):
+        ctx = skr.skr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+        bufs = [[torch.empty_like(x0[c]) for _ in range(3)] for c in range(nch)]   # b, x (two, alternating)
+        prev = [x0[c] for c in range(nch)]
+        starts = list(range(nch + 1))
+        res = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(nsteps):
+            bs, xs = [], []
+            for c in range(nch):
+                torch.div(prev[c], chains[c].dt, out=bufs[c][0])
+                bs.append(bufs[c][0])
+                xs.append(bufs[c][1 + q % 2])
+            rc, r = skr.skr_solve_chains(ctx, starts, ops[:nch], bs, xs, None, m=a.m, k=k, rtol=a.rtol,
+                                         maxit=a.maxit, flags=mode | (skr.SKR_FLAG_CONTINUE if q else 0))
+            res.append(r)
+            prev = xs
+            log(f"  batched time step {q} of {nch} chains done")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        skr.skr_ctx_destroy(ctx)
+        flat = [x for r in res for x in r]
+        conv = sum(r_["status"] in (skr.SKR_CONVERGED, skr.SKR_BREAKDOWN) for r_ in flat)
+        return dict(wall=wall, value=conv / wall, converged=conv, solves=len(flat),
+                    iters_mean=float(np.mean([r_["iters"] for r_ in flat])),
+                    iters_first=float(np.mean([r_["iters"] for r_ in res[0]])),
+                    iters_later=float(np.mean([r_["iters"] for r in res[1:] for r_ in r])) if nsteps > 1 else None,
+                    max_relres=max(r_["relres_true"] for r_ in flat), chains=nch)
+
+    forms = ["batched", "serve"] if a.advdiff_form == "both" else [a.advdiff_form]
+    runner = {"batched": run_batched, "serve": run}
     sub_c, sub_t = min(C, 8), min(T, 8)
-    log(f"GMRES(m) and GCRO-DR on {sub_c} chains x {sub_t} steps")
-    g = run(sub_c, sub_t, 0)
-    s_ = run(sub_c, sub_t, a.k)
+    results = {}
+    for f in forms:
+        log(f"[{f}] warm-up")
+        runner[f](min(C, 4), 2, a.k)
+        log(f"[{f}] timed run: {C} chains x {T} steps")
+        main = runner[f](C, T, a.k)
+        log(f"[{f}] {main['value']:.1f} systems/s; GMRES(m) and GCRO-DR on {sub_c} chains x {sub_t} steps")
+        g = runner[f](sub_c, sub_t, 0)
+        s_ = runner[f](sub_c, sub_t, a.k)
+        results[f] = dict(run=main, subset={"chains": sub_c, "steps": sub_t, "gmres": g, "gcrodr": s_,
+                                            "speedup_vs_gmres": round(s_["value"] / g["value"], 2)
+                                            if g["value"] > 0 else None})
+    head = forms[0]
     out = {
         "metric": "systems/s of backward-Euler advection-diffusion chains (GCRO-DR recycling along each chain)",
-        "value": round(main["value"], 3), "unit": "systems/s", "n_gpus": 1, "higher_is_better": True,
-        "dtype": "f64", "data": "synthetic",
+        "value": round(results[head]["run"]["value"], 3), "unit": "systems/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"advdiff2d-{N}x{N}-{C}chains-x{T}steps-gcrodr({a.m},{a.k})"
                                + ("-fp32basis" if a.mixed else ""),
                    "grid": N, "n": N * N, "chains": C, "steps": T, "dt": chains[0].dt, "m": a.m, "k": a.k,
-                   "rtol": a.rtol, "workers": a.serve_workers},
-        "run": main,
-        "subset": {"chains": sub_c, "steps": sub_t, "gmres": g, "gcrodr": s_,
-                   "speedup_vs_gmres": round(s_["value"] / g["value"], 2) if g["value"] > 0 else None},
+                   "rtol": a.rtol, "form": head, "workers": a.serve_workers},
+        "run": results[head]["run"], "subset": results[head]["subset"],
     }
+    if len(forms) > 1:
+        other = forms[1]
+        out[other] = results[other]
+        out[f"{head}_over_{other}"] = round(results[head]["run"]["value"] / results[other]["run"]["value"], 3)
     print(json.dumps(out), flush=True)
 
 
@@ -397,8 +445,25 @@ def main():
         if C == 1:
             return skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=a.m, k=a.k, rtol=a.rtol, maxit=a.maxit,
                                           flags=flags | mode)
-        import threading
         slices = [[int(i) for i in sl] for sl in np.array_split(np.asarray(order), C)]
+        if a.chains_form == "batched":
+            # round t gives every chain its t-th system; the chains carry their recycle spaces from
+            # round to round (SKR_FLAG_CONTINUE), which solves each chain as one uninterrupted call would
+            res = [None] * N
+            rc = 0
+            for t_ in range(max(len(sl) for sl in slices)):
+                idx = [sl[t_] for sl in slices if t_ < len(sl)]
+                starts = np.concatenate([[0], np.cumsum([1 if t_ < len(sl) else 0 for sl in slices])])
+                rc_, r = skr.skr_solve_chains(ctx, starts, [ops[i] for i in idx], [bs[i] for i in idx],
+                                              [xs[i] for i in idx], None, m=a.m, k=a.k, rtol=a.rtol,
+                                              maxit=a.maxit, flags=flags | mode | (skr.SKR_FLAG_CONTINUE if t_ else 0))
+                rc = max(rc, rc_)
+                for i, r_ in zip(idx, r):
+                    res[i] = r_
+                if a.dim == 3:
+                    log(f"  round {t_}: {len(idx)} systems done")
+            return rc, res
+        import threading
         out = [None] * C
 
         def run(c):
@@ -625,8 +690,10 @@ def main():
                    "dim": a.dim, "grid": a.grid, "n": systems[0].n, "nnz": nnz, "systems": a.systems, "m": a.m, "k": a.k,
                    "rtol": a.rtol, "matrix": a.matrix, "chains": C,
                    "basis_storage": "fp32 (FP64 arithmetic and refinement)" if a.mixed else "fp64",
-                   "parallelism": "single chain" if C == 1 else f"{C} contiguous chains of the sorted order, "
-                                                                 "one stream each"},
+                   "parallelism": "single chain" if C == 1 else (
+                       f"{C} contiguous chains of the sorted order advanced in lockstep (skr_solve_chains: one "
+                       "launch per kernel covers every chain)" if a.chains_form == "batched" else
+                       f"{C} contiguous chains of the sorted order, one host thread and stream each")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "converged": converged,

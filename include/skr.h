@@ -212,6 +212,32 @@ int skr_solve_sequence(skr_ctx* ctx, const skr_op* ops, const double* const* b_d
                        const skr_opts* opts, skr_result* results_host);
 
 /*
+ * Several chains of one sorted order advanced together (the data-parallel split of App. E: the
+ * sorted sequence cut into contiguous chains, one per worker, each recycling along its own part).
+ * Chain c solves order[chain_start[c]] .. order[chain_start[c+1] - 1] exactly as
+ * skr_solve_sequence would on a context of its own (x0 = 0; no recycle space at its first system,
+ * or with SKR_FLAG_CONTINUE the one chain c left at the end of the previous skr_solve_chains call
+ * on this context), and the results and solutions equal that call's bit for bit. All chains share the context's stream:
+ * every kernel launch covers the chains that take part in that phase (one grid row per chain), so
+ * C chains cost about the launches of one, which is what raises the throughput of small systems.
+ *  C:            number of chains, >= 1.
+ *  chain_start:  host array of C + 1 int64, chain_start[0] = 0, chain_start[C] = N, non-decreasing
+ *                (an empty chain is allowed).
+ *  ops, b_dev, x_dev, N, order, opts, results_host: as for skr_solve_sequence; all operators of
+ *                one kind and size. With SKR_FLAG_CONTINUE, C and (n, m, k, precision) must be
+ *                those of the previous call on this context (else SKR_EINVAL); a chain may then be
+ *                given one system per call, e.g. one time step of C time-stepping chains whose
+ *                right-hand sides depend on the previous solutions.
+ * Memory: one workspace per chain (C times skr_workspace_bytes) plus small tables, taken from the
+ * context's arena when it has one, else allocated; they stay with the context (holding each
+ * chain's recycle space) until a call with fewer chains or skr_ctx_destroy. The context's own
+ * recycle space (skr_recycle_get) is not touched. Returns as skr_solve_sequence.
+ */
+int skr_solve_chains(skr_ctx* ctx, int32_t C, const int64_t* chain_start, const skr_op* ops,
+                     const double* const* b_dev, double* const* x_dev, int64_t N, const int64_t* order,
+                     const skr_opts* opts, skr_result* results_host);
+
+/*
  * Checkpoint and resume of a chain. After skr_solve_sequence the context carries the recycle space
  * U_k that the next system of the chain would start from (the Y~_k handed from system to system,
  * App. B.1; Alg. 2 start-up). With the order and the index of the next system it is the whole

@@ -11,7 +11,17 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["skr_solver.hip", "skr_dense.hip", "skr_sort.hip", "skr_api.hip", "skr_serve.hip", "skr_state.hip"]
+# (source, object, extra flags): skr_solver.hip is compiled twice, its single-chain kernels and its
+# batched (one grid row per chain) kernels, which share the device bodies
+UNITS = [("skr_solver.hip", "skr_solver.o", []),
+         ("skr_solver.hip", "skr_solver_chains.o", ["-DSKR_CHAINS_UNIT"]),
+         ("skr_dense.hip", "skr_dense.o", []),
+         ("skr_sort.hip", "skr_sort.o", []),
+         ("skr_api.hip", "skr_api.o", []),
+         ("skr_serve.hip", "skr_serve.o", []),
+         ("skr_state.hip", "skr_state.o", []),
+         ("skr_batch.hip", "skr_batch.o", [])]
+SOURCES = sorted({u[0] for u in UNITS})
 OUTPUT = os.path.join(HERE, "libskr.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,9 +40,9 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into libskr.so; returns the library path. Raises on failure."""
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = []
-    for src in SOURCES:
-        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
-        jobs.append((obj, [HIPCC, *FLAGS, "-c", os.path.join(HERE, "csrc", src), "-o", obj]))
+    for src, o, extra in UNITS:
+        obj = os.path.join(OBJDIR, o)
+        jobs.append((obj, [HIPCC, *FLAGS, *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]))
     with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
         results = list(ex.map(lambda j: _run(j[1]), jobs))
     msgs = []

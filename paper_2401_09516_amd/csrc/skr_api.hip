@@ -61,23 +61,27 @@ const std::string& last_error() { return g_err; }
 }  // namespace skr
 
 // Algorithmic bytes of the three step kernels at step j with ncol = kc + j + 1 basis columns.
-static double op_bytes(const DevOp& op, int64_t nvals) {
-    const double n = op.n;
-    if (op.kind == SKR_OP_CSR) return 12.0 * (double)nvals + 4.0 * (n + 1) + 8.0 * n;
+// Bytes of one product with the operator: its values (FP64, or FP32 for the inner products of the
+// mixed mode) with the CSR column indices and row pointers, the FP64 operand and result.
+static double op_bytes(const DevOp& op, int64_t nvals, bool fp32_values) {
+    const double n = op.n, vb = fp32_values ? 4.0 : 8.0;
+    if (op.kind == SKR_OP_CSR) return (vb + 4.0) * (double)nvals + 4.0 * (n + 1) + 16.0 * n;
     if (op.kind == SKR_OP_STENCIL7)
-        return 8.0 * (double)op.nz * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) +
-               8.0 * (double)(op.nz + 1) * op.ny * op.nx + 8.0 * n;
-    return 8.0 * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 8.0 * n;
+        return vb * (double)op.nz * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) +
+               vb * (double)(op.nz + 1) * op.ny * op.nx + 16.0 * n;
+    return vb * ((double)op.ny * (op.nx + 1) + (double)(op.ny + 1) * op.nx) + 16.0 * n;
 }
-// es: bytes per stored basis element (8, or 4 with an FP32 basis); w and the operand stay FP64.
-// A step is passes A, B and C, or with two kernels (merged) pass A at step 0, the merged kernel after
-// it, which also reads the kc columns of Z = A C (FP32), and pass B; there is no pass C (c = 0).
-static void step_bytes(const DevOp& op, int64_t nvals, int kc, int j, bool mixed, bool merged, double& a, double& b,
-                       double& c) {
+// Algorithmic bytes of the kernels of Arnoldi step j. es: bytes per stored basis element (8, or 4
+// with an FP32 basis, whose mode also takes the operator values in FP32); w stays FP64. A step is
+// passes A, B and C, or with two kernels (merged) pass A at step 0, the merged kernel after it,
+// which also reads the kc columns of Z = A C (FP32), and pass B; there is no pass C (c = 0).
+void skr::step_bytes(const DevOp& op, int64_t nvals, int kc, int j, bool mixed, bool merged, double& a, double& b,
+                     double& c) {
     const double n = op.n;
     const int ncol = kc + j + 1;
     const double es = mixed ? 4.0 : 8.0;
-    a = op_bytes(op, nvals) + 8.0 * n /* w */ + es * n /* v_j */ + es * n * (ncol - 1);
+    // pass A: the product (operand and result counted in op_bytes), v_j stored, the other columns
+    a = op_bytes(op, nvals, mixed) + es * n /* v_j */ + es * n * (ncol - 1);
     b = es * n * ncol + 16.0 * n;
     if (!merged) {
         c = es * n * ncol + 16.0 * n;
@@ -663,6 +667,7 @@ int skr_ctx_create(int device, void* hip_stream, void* arena_dev, size_t arena_b
 int skr_ctx_destroy(skr_ctx* ctx) {
     if (!ctx) return SKR_OK;
     serve_free(ctx);
+    chains_free(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     free_work(ctx);

@@ -83,7 +83,7 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 // Stage 1 of a cycle end (one wavefront): G, X = W-hat^T V-hat, Givens QR of G, least-squares
 // solution and the coefficients of the x and r updates. When a recycle space is to be formed, R_G,
 // the top d rows of Q_G^T X, the rotations and D_k are handed to the eigen stage through dw.
-__global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H, const double* __restrict__ Bm,
+__device__ __forceinline__ void k_dense_prep_body(const double* __restrict__ H, const double* __restrict__ Bm,
                                                    const double* __restrict__ gram, int kc, int jd_max, int k_target,
                                                    Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     __shared__ double G[LDG * DS];
@@ -222,6 +222,12 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
     if (t < kc) dw->Dk[t] = Dk[t];
     if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_PENDING; }
 }
+__global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H, const double* __restrict__ Bm,
+                                                   const double* __restrict__ gram, int kc, int jd_max, int k_target,
+                                                   Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    k_dense_prep_body(H, Bm, gram, kc, jd_max, k_target, coef, dw, ctrl);
+}
+
 
 // Stage 2, symmetric case (4 wavefronts). M = X'' R_G^{-1} is formed; for symmetric A it is
 // symmetric in exact arithmetic (G^T G and G^T W-hat^T V-hat = V-hat^T A V-hat are). The route is
@@ -238,7 +244,7 @@ constexpr int DT = 256;         // threads of the symmetric stage
 constexpr int LDS_ = DS + 1;  // leading dimension of S and V in LDS
 constexpr int NSHIFT = 8;       // multisection: shifts per eigenvalue interval and round
 
-__global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
+__device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
                                                   Ctrl* ctrl) {
     if (dw->mode != DW_PENDING) return;
     __shared__ double S[LDS_ * DS];
@@ -767,12 +773,17 @@ __global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, 
     __syncthreads();
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 1; dw->mode = DW_DONE; }
 }
+__global__ __launch_bounds__(DT) void k_dense_sym(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
+                                                  Ctrl* ctrl) {
+    k_dense_sym_body(k_target, sym_tol, coef, dw, ctrl);
+}
+
 
 // Stage 2, general (nonsymmetric) case, one wavefront: M = X'' R_G^{-1} was formed by the
 // symmetric stage, which found it nonsymmetric. Householder reduction to Hessenberg form, Francis
 // double-shift QR, eigenvectors of the selected eigenvalues by back-substitution, an orthonormal
 // basis Q_w of them, and the recycle-space coefficients Qu = R_G^{-1} Q_w, Qc = Q_G [Q_w; 0].
-__global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+__device__ __forceinline__ void k_dense_gen_body(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     if (dw->mode != DW_GEN) return;
     __shared__ double G[LDG * DS];
     __shared__ double X[LDG * DS];
@@ -1175,6 +1186,10 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
     }
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 2; dw->mode = DW_DONE; }
 }
+__global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    k_dense_gen_body(k_target, coef, dw, ctrl);
+}
+
 
 // ---------------------------------------------------------------------------------------------
 // Cycle end for DSM < d <= MMAX: the same three stages with their thread mappings stretched to
@@ -1185,7 +1200,7 @@ __global__ __launch_bounds__(64) void k_dense_gen(int k_target, Coef* coef, Dens
 constexpr int LDP = MMAX + 2;   // leading dimension of G and X ((d + 1) x d) in the first stage
 constexpr int LDL = MMAX + 1;   // leading dimension of the d x d arrays of the general stage
 
-__global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ H, const double* __restrict__ Bm,
+__device__ __forceinline__ void k_dense_prep_L_body(const double* __restrict__ H, const double* __restrict__ Bm,
                                                      const double* __restrict__ gram, int kc, int jd_max,
                                                      int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     __shared__ double G[LDP * MMAX];
@@ -1296,6 +1311,12 @@ __global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ 
     if (t < kc) dw->Dk[t] = Dk[t];
     if (t == 0) { dw->d = d; dw->kc = kc; dw->mode = DW_PENDING_L; }
 }
+__global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ H, const double* __restrict__ Bm,
+                                                     const double* __restrict__ gram, int kc, int jd_max,
+                                                     int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    k_dense_prep_L_body(H, Bm, gram, kc, jd_max, k_target, coef, dw, ctrl);
+}
+
 
 // Symmetric stage for d > DSM (DT threads): the route of k_dense_sym (M, symmetry test,
 // Householder tridiagonalization, multisection, twisted factorizations, back-transformation and
@@ -1305,7 +1326,7 @@ __global__ __launch_bounds__(64) void k_dense_prep_L(const double* __restrict__ 
 // factorizations and the eigenvectors). dw->X keeps X'' for the general stage if this one declines.
 constexpr int RPL = (MMAX + 7) / 8;   // rows per lane when eight lanes share a column
 
-__global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
+__device__ __forceinline__ void k_dense_sym_L_body(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
                                                     Ctrl* ctrl) {
     if (dw->mode != DW_PENDING_L) return;
     __shared__ double S[LDL * MMAX];
@@ -1775,11 +1796,16 @@ __global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol
     __syncthreads();
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 1; dw->mode = DW_DONE; }
 }
+__global__ __launch_bounds__(DT) void k_dense_sym_L(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
+                                                    Ctrl* ctrl) {
+    k_dense_sym_L_body(k_target, sym_tol, coef, dw, ctrl);
+}
+
 
 // General stage for d > DSM. LDS regions: XR (X'', then M, then the Schur form T, then the
 // back-transformed vectors and the back-substitution scratch), ZR (R_G, then the Schur vectors,
 // then R_G again), WV (the selected eigenvectors in the Schur basis, then Q_w).
-__global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+__device__ __forceinline__ void k_dense_gen_L_body(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
     if (dw->mode != DW_GEN_L) return;
     __shared__ double XR[LDL * MMAX];
     __shared__ double ZR[LDL * MMAX];
@@ -2217,12 +2243,16 @@ __global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, De
     }
     if (t == 0) { ctrl->k_new = kn; ctrl->eig_fail = 0; ctrl->route = 2; dw->mode = DW_DONE; }
 }
+__global__ __launch_bounds__(64) void k_dense_gen_L(int k_target, Coef* coef, DenseWork* dw, Ctrl* ctrl) {
+    k_dense_gen_L_body(k_target, coef, dw, ctrl);
+}
+
 
 // ---------------------------------------------------------------------------------------------
 // Start-up CholQR: Cholesky of the Gram matrix Z^T Z (kin x kin, row-major in gram). With drops,
 // a column whose pivot falls to <= 1e-14 ||z_j||^2 (R_jj <= 1e-7 ||z_j||) is left out.
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_chol(const double* __restrict__ gram, int kin, int with_drop, Coef* coef) {
+__device__ __forceinline__ void k_chol_body(const double* __restrict__ gram, int kin, int with_drop, Coef* coef) {
     __shared__ double A[KMAX * KMAX];
     __shared__ double Rf[KMAX * KMAX];
     __shared__ double d0[KMAX];
@@ -2266,6 +2296,10 @@ __global__ __launch_bounds__(64) void k_chol(const double* __restrict__ gram, in
         if (t == 0) coef->k_eff = ke;
     }
 }
+__global__ __launch_bounds__(64) void k_chol(const double* __restrict__ gram, int kin, int with_drop, Coef* coef) {
+    k_chol_body(gram, kin, with_drop, coef);
+}
+
 
 void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_target) {
     hipLaunchKernelGGL(k_dense_prep, dim3(1), dim3(64), 0, s, (const double*)w.H, (const double*)w.Bm,
@@ -2294,6 +2328,57 @@ void launch_cycle_dense(hipStream_t s, const Work& w, int kc, int jd_max, int k_
 }
 void launch_chol(hipStream_t s, const Work& w, int kin, int with_drop) {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(64), 0, s, (const double*)w.gram, kin, with_drop, w.coef);
+}
+
+// Batched forms (skr_solve_chains): one workgroup per chain, chain blockIdx.y, the same bodies.
+#define SKR_CD const ChainDesc& cd = tab[blockIdx.y]; if (!cd.on) return; const Work& w = cd.w
+__global__ __launch_bounds__(64) void kb_dense_prep(const ChainDesc* tab, int k_target) {
+    SKR_CD;
+    k_dense_prep_body(w.H, w.Bm, w.gram, cd.kc, cd.scyc, k_target, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(DT) void kb_dense_sym(const ChainDesc* tab, int k_target, double sym_tol) {
+    SKR_CD;
+    k_dense_sym_body(k_target, sym_tol, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(64) void kb_dense_gen(const ChainDesc* tab, int k_target) {
+    SKR_CD;
+    k_dense_gen_body(k_target, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(64) void kb_dense_prep_L(const ChainDesc* tab, int k_target) {
+    SKR_CD;
+    k_dense_prep_L_body(w.H, w.Bm, w.gram, cd.kc, cd.scyc, k_target, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(DT) void kb_dense_sym_L(const ChainDesc* tab, int k_target, double sym_tol) {
+    SKR_CD;
+    k_dense_sym_L_body(k_target, sym_tol, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(64) void kb_dense_gen_L(const ChainDesc* tab, int k_target) {
+    SKR_CD;
+    k_dense_gen_L_body(k_target, w.coef, w.dense, w.ctrl);
+}
+__global__ __launch_bounds__(64) void kb_chol(const ChainDesc* tab, int with_drop) {
+    SKR_CD;
+    k_chol_body(w.gram, with_drop ? cd.kin : cd.ke, with_drop, w.coef);
+}
+#undef SKR_CD
+void blaunch_cycle_dense(const Batch& B, int k_target) {
+    const dim3 g(1, (unsigned)B.C);
+    const double sym_tol = B.w0.mixed ? 1e-4 : 1e-10;
+    hipLaunchKernelGGL(kb_dense_prep, g, dim3(64), 0, B.s, B.cd, k_target);
+    if (k_target > 0) {
+        hipLaunchKernelGGL(kb_dense_sym, g, dim3(DT), 0, B.s, B.cd, k_target, sym_tol);
+        hipLaunchKernelGGL(kb_dense_gen, g, dim3(64), 0, B.s, B.cd, k_target);
+    }
+    if (B.w0.m > DSM) {
+        hipLaunchKernelGGL(kb_dense_prep_L, g, dim3(64), 0, B.s, B.cd, k_target);
+        if (k_target > 0) {
+            hipLaunchKernelGGL(kb_dense_sym_L, g, dim3(DT), 0, B.s, B.cd, k_target, sym_tol);
+            hipLaunchKernelGGL(kb_dense_gen_L, g, dim3(64), 0, B.s, B.cd, k_target);
+        }
+    }
+}
+void blaunch_chol(const Batch& B, int with_drop) {
+    hipLaunchKernelGGL(kb_chol, dim3(1, (unsigned)B.C), dim3(64), 0, B.s, B.cd, with_drop);
 }
 
 }  // namespace skr

@@ -9,6 +9,7 @@
 
 namespace skr {
 struct Server;
+struct ChainSet;
 
 // Sub-allocator over a caller-owned device buffer (the arena of skr_ctx_create): first fit over the
 // free blocks in address order, every block a multiple of 256 bytes at a 256-byte offset, freed
@@ -63,6 +64,8 @@ struct skr_ctx {
     int carry_k = 0, carry_n = 0, carry_m = 0, carry_kmax = 0, carry_mixed = 0;
     // serving (skr_serve_start .. skr_serve_stop)
     skr::Server* server = nullptr;
+    // the chain contexts and tables of skr_solve_chains, kept for the next call on this context
+    skr::ChainSet* chains = nullptr;
 };
 
 namespace skr {
@@ -87,6 +90,11 @@ void dev_free(skr_ctx* ctx, void* p);
 inline size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 // Serving state of a context (skr_serve.hip).
 void serve_free(skr_ctx* ctx);
+// Algorithmic bytes of the kernels of Arnoldi step j (passes A, B, C; c = 0 with two kernels).
+void step_bytes(const DevOp& op, int64_t nvals, int kc, int j, bool mixed, bool merged, double& a, double& b,
+                double& c);
+// Releases the chain contexts and tables skr_solve_chains keeps on ctx.
+void chains_free(skr_ctx* ctx);
 }  // namespace skr
 
 #define HIPCHK(call)                                                                            \

@@ -489,4 +489,45 @@ struct Work {
 
 int gram_cols_max(int m, int k);
 
+// Up to four column segments for the tall-skinny Gram products; segment s has cnt[s] columns at
+// seg[s] (stride ld), all of the element type the kernel takes for the list.
+struct ColList {
+    const void* seg[4];
+    int cnt[4];
+};
+
+// ---------------------------------------------------------------------------------------------
+// Batched launches (skr_solve_chains): several chains of one shape advance in one launch, chain c
+// in grid row blockIdx.y. Each chain keeps its own workspace; its descriptor holds the device
+// pointers and the values that differ between chains. A launch's template parameters are uniform
+// over the chains it covers; `on` masks the chains a launch leaves alone.
+// ---------------------------------------------------------------------------------------------
+struct ChainDesc {
+    Work w;                 // the chain's workspace (device pointers) and sizes
+    DevOp op;               // operator of the chain's current system
+    const double* b;
+    double* x;
+    ColList Lg, Rg;         // cycle-end Gram lists ([C V U] and [U r]) of the current cycle
+    ColList Ls;             // start-up columns (kin or ke)
+    ColList Lp;             // C columns for C^T r (projection)
+    int on;                 // the launch touches this chain
+    int kc;                 // recycled columns (C, U) of the current cycle / projection
+    int kin;                // carried columns at the start-up
+    int ke;                 // columns kept by the start-up drop
+    int scyc;               // steps of the current cycle
+    int part;               // which operator array a check / conversion launch touches (0..2)
+    long cnt[3];            // operator array lengths: CSR values, or faces ax, ay, az
+    const double* arr[3];   // the operator arrays
+    float* arr32[3];        // their FP32 copies (mixed mode)
+};
+
+// A batched launch: the device table of C chain descriptors and the sizes shared by every chain
+// (a representative workspace: n, ld, nblk, m, k, fold, mixed, merged).
+struct Batch {
+    hipStream_t s;
+    const ChainDesc* cd;
+    int C;
+    Work w0;
+};
+
 }  // namespace skr

@@ -25,7 +25,7 @@ __device__ __forceinline__ const double* qcol(const double* basis, int ld, int k
 // ---------------------------------------------------------------------------------------------
 // Solve set-up: x = 0, r = b, partials of ||b||^2 (closed by k_norm_finish).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(ROWS) void k_init(const double* __restrict__ b, double* __restrict__ x,
+__device__ __forceinline__ void k_init_body(const double* __restrict__ b, double* __restrict__ x,
                                                double* __restrict__ r, int n, int nblk, double* part_n) {
     __shared__ double sh[NWAVE];
     const int lb = logical_block(blockIdx.x, nblk);
@@ -39,13 +39,20 @@ __global__ __launch_bounds__(ROWS) void k_init(const double* __restrict__ b, dou
     }
     block_partial1(v, part_n, lb, sh);
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_init(const double* __restrict__ b, double* __restrict__ x,
+                                               double* __restrict__ r, int n, int nblk, double* part_n) {
+    k_init_body(b, x, r, n, nblk, part_n);
+}
+#endif
+
 
 // Close of a squared-norm reduction whose per-workgroup partials (folded or not) the previous
 // kernel left: one workgroup sums them in the fixed order every Arnoldi pass A uses for the same
 // partials, so the host and the next cycle see bitwise the same value, and sets the control-block
 // fields that follow from it. No fences or atomics: the kernel boundary orders it after the writer.
 enum { FIN_INIT = 0, FIN_TRUE_RES = 1, FIN_PROJECT = 2 };
-__global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__ pn, int npn, int mode, double rtol,
+__device__ __forceinline__ void k_norm_finish_body(const double* __restrict__ pn, int npn, int mode, double rtol,
                                                       int ke, Ctrl* ctrl) {
     __shared__ double sh[NWAVE * NC];
     const double tot = sum_partials1(pn, npn, sh);
@@ -73,16 +80,29 @@ __global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__
         ctrl->kc = ke;
     }
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__ pn, int npn, int mode, double rtol,
+                                                      int ke, Ctrl* ctrl) {
+    k_norm_finish_body(pn, npn, mode, rtol, ke, ctrl);
+}
+#endif
 
-__global__ void k_clear_nonfinite(Ctrl* ctrl) {
+
+__device__ __forceinline__ void k_clear_nonfinite_body(Ctrl* ctrl) {
     ctrl->nonfinite = 0;
     ctrl->nonsym = 0;
 }
+#ifndef SKR_CHAINS_UNIT
+__global__  void k_clear_nonfinite(Ctrl* ctrl) {
+    k_clear_nonfinite_body(ctrl);
+}
+#endif
+
 
 // Exact symmetry of a CSR operator: entry (i, c, v) with c != i needs an entry (c, i) of the same
 // value (duplicates are summed, as in the product). One row per thread; row c is scanned for
 // column i (rows need not be sorted). Any mismatch sets ctrl->nonsym.
-__global__ __launch_bounds__(ROWS) void k_check_sym_csr(DevOp op, Ctrl* ctrl) {
+__device__ __forceinline__ void k_check_sym_csr_body(DevOp op, Ctrl* ctrl) {
     const int i = blockIdx.x * ROWS + threadIdx.x;
     int bad = 0;
     if (i < op.n) {
@@ -100,18 +120,36 @@ __global__ __launch_bounds__(ROWS) void k_check_sym_csr(DevOp op, Ctrl* ctrl) {
     }
     if (__any(bad) && lane_id() == 0) atomicOr(&ctrl->nonsym, 1);
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_check_sym_csr(DevOp op, Ctrl* ctrl) {
+    k_check_sym_csr_body(op, ctrl);
+}
+#endif
 
-__global__ __launch_bounds__(ROWS) void k_check_finite(const double* __restrict__ v, long count, Ctrl* ctrl) {
+
+__device__ __forceinline__ void k_check_finite_body(const double* __restrict__ v, long count, Ctrl* ctrl) {
     int bad = 0;
     for (long e = blockIdx.x * (long)ROWS + threadIdx.x; e < count; e += (long)gridDim.x * ROWS)
         bad |= !isfinite(v[e]);
     if (__any(bad) && lane_id() == 0) atomicOr(&ctrl->nonfinite, 1);
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_check_finite(const double* __restrict__ v, long count, Ctrl* ctrl) {
+    k_check_finite_body(v, count, ctrl);
+}
+#endif
 
-__global__ __launch_bounds__(ROWS) void k_zero(double* __restrict__ x, int n) {
+
+__device__ __forceinline__ void k_zero_body(double* __restrict__ x, int n) {
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i < n) x[i] = 0.0;
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_zero(double* __restrict__ x, int n) {
+    k_zero_body(x, n);
+}
+#endif
+
 
 // ---------------------------------------------------------------------------------------------
 // Arnoldi step kernels. NL (a multiple of 8, >= the columns used) is the number of basis loads per
@@ -207,7 +245,7 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
 // column), w = A v_j, and partials of Q^T w (Q = [C, V_0..V_j], ncol = kc + j + 1 columns) and of
 // ||w||^2 (reduction column ncol).
 template <int NL, int KIND, typename BT>
-__global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
+__device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict__ src,
                                                  double* __restrict__ dst, BT* __restrict__ basis,
                                                  int ld, int kc, int vbase, int j, int nblk, int npn,
                                                  const double* __restrict__ part_n, double* __restrict__ part_a,
@@ -328,12 +366,22 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
     }
     block_partials<NR>(s, sh, part_a, lb);
 }
+template <int NL, int KIND, typename BT>
+__global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
+                                                 double* __restrict__ dst, BT* __restrict__ basis,
+                                                 int ld, int kc, int vbase, int j, int nblk, int npn,
+                                                 const double* __restrict__ part_n, double* __restrict__ part_a,
+                                                 const double* __restrict__ red1, const double* __restrict__ red2,
+                                                 double* H, double* Bm, Ctrl* ctrl) {
+    k_step_a_body<NL, KIND, BT>(op, src, dst, basis, ld, kc, vbase, j, nblk, npn, part_n, part_a, red1, red2, H, Bm, ctrl);
+}
+
 
 // Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
 // partials of Q^T w; with NORM also of ||w||^2 (reduction column ncol), which the merged kernel
 // below needs in place of a pass C.
 template <int NL, typename BT, bool FOLDED, bool NORM = false>
-__global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
+__device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
                                                  const double* __restrict__ part_a, double* __restrict__ part_b,
                                                  double* __restrict__ red1, const Ctrl* ctrl) {
@@ -374,10 +422,18 @@ __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, cons
     }
     block_partials<NR>(s, sh, part_b, lb);
 }
+template <int NL, typename BT, bool FOLDED, bool NORM = false>
+__global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
+                                                 int n, int ld, int kc, int vbase, int j, int nblk, int npa,
+                                                 const double* __restrict__ part_a, double* __restrict__ part_b,
+                                                 double* __restrict__ red1, const Ctrl* ctrl) {
+    k_step_b_body<NL, BT, FOLDED, NORM>(w_io, basis, n, ld, kc, vbase, j, nblk, npa, part_a, part_b, red1, ctrl);
+}
+
 
 // Pass C: h2 = Q^T w (sum of pass B's partials, stored), w -= Q h2, partials of ||w||^2.
 template <int NL, typename BT, bool FOLDED>
-__global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const BT* __restrict__ basis,
+__device__ __forceinline__ void k_step_c_body(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npb,
                                                  const double* __restrict__ part_b, double* __restrict__ part_n,
                                                  double* __restrict__ red2, const Ctrl* ctrl) {
@@ -402,6 +458,14 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
     else w = 0.0;
     block_partial1(w * w, part_n, lb, sh);
 }
+template <int NL, typename BT, bool FOLDED>
+__global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, const BT* __restrict__ basis,
+                                                 int n, int ld, int kc, int vbase, int j, int nblk, int npb,
+                                                 const double* __restrict__ part_b, double* __restrict__ part_n,
+                                                 double* __restrict__ red2, const Ctrl* ctrl) {
+    k_step_c_body<NL, BT, FOLDED>(w_io, basis, n, ld, kc, vbase, j, nblk, npb, part_b, part_n, red2, ctrl);
+}
+
 
 // Merged pass C of step j-1 and pass A of step j (FP64 basis, 1 <= j). Pass B of step j-1 left
 // w_B = A v_{j-1} - Q h1 and the partials of h2 = Q^T w_B and ||w_B||^2, Q = [C, v_0..v_{j-1}]
@@ -422,7 +486,7 @@ __global__ __launch_bounds__(ROWS) void k_step_c(double* __restrict__ w_io, cons
 // after the writer set it still see a stop of a later step than theirs; every other kernel treats
 // any nonzero value as stopped.
 template <int NL, int KIND, int KZ, bool LAST>
-__global__ __launch_bounds__(ROWS) void k_step_m(DevOp op, const double* __restrict__ wb, double* __restrict__ dst,
+__device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict__ wb, double* __restrict__ dst,
                                                  double* __restrict__ basis, const float* __restrict__ Z, int ld,
                                                  int kc, int vbase, int j, int nblk, int npb,
                                                  const double* __restrict__ part_b, double* __restrict__ part_a,
@@ -575,11 +639,21 @@ __global__ __launch_bounds__(ROWS) void k_step_m(DevOp op, const double* __restr
         gnext[t] = t < ncol ? a * scale : 0.0;
     }
 }
+template <int NL, int KIND, int KZ, bool LAST>
+__global__ __launch_bounds__(ROWS) void k_step_m(DevOp op, const double* __restrict__ wb, double* __restrict__ dst,
+                                                 double* __restrict__ basis, const float* __restrict__ Z, int ld,
+                                                 int kc, int vbase, int j, int nblk, int npb,
+                                                 const double* __restrict__ part_b, double* __restrict__ part_a,
+                                                 const double* __restrict__ red1, const double* __restrict__ gprev,
+                                                 double* __restrict__ gnext, double* H, double* Bm, Ctrl* ctrl) {
+    k_step_m_body<NL, KIND, KZ, LAST>(op, wb, dst, basis, Z, ld, kc, vbase, j, nblk, npb, part_b, part_a, red1, gprev, gnext, H, Bm, ctrl);
+}
+
 
 // Cycle end: closes the last step when no pass A did (the cycle ran all s_cycle steps), then stores
 // v_{j_done} = w_last * inv_h (zero after a breakdown), the last column of the cycle's basis.
 template <typename BT>
-__global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__ w0, const double* __restrict__ w1,
+__device__ __forceinline__ void k_close_basis_body(const double* __restrict__ w0, const double* __restrict__ w1,
                                                       BT* __restrict__ basis, int n, int ld, int kc, int vbase,
                                                       int s_cycle, int npn, const double* __restrict__ part_n,
                                                       const double* __restrict__ red1, const double* __restrict__ red2,
@@ -616,17 +690,20 @@ __global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__
     const double* wl = ((s_jd - 1) & 1) ? w1 : w0;
     basis[(size_t)(vbase + s_jd) * ld + i] = (BT)(s_brk ? 0.0 : wl[i] * s_scale);
 }
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_close_basis(const double* __restrict__ w0, const double* __restrict__ w1,
+                                                      BT* __restrict__ basis, int n, int ld, int kc, int vbase,
+                                                      int s_cycle, int npn, const double* __restrict__ part_n,
+                                                      const double* __restrict__ red1, const double* __restrict__ red2,
+                                                      double* H, double* Bm, Ctrl* ctrl) {
+    k_close_basis_body<BT>(w0, w1, basis, n, ld, kc, vbase, s_cycle, npn, part_n, red1, red2, H, Bm, ctrl);
+}
+
 
 // ---------------------------------------------------------------------------------------------
 // Tall-skinny Gram products out = L^T R over all rows (L, R: lists of columns), used for
 // [C V]^T U, C^T r, U^T U at a cycle end and for the start-up CholQR.
 // ---------------------------------------------------------------------------------------------
-// Up to four column segments; segment s has cnt[s] columns at seg[s] (stride ld), all of the
-// element type the kernel takes for the list.
-struct ColList {
-    const void* seg[4];
-    int cnt[4];
-};
 constexpr int GCHUNK = 32;               // rows staged per LDS chunk
 constexpr int GL_MAX = 2 * KMAX + MMAX + 2;   // max columns on the left
 constexpr int GR_MAX = KMAX + 1;              // max columns on the right
@@ -652,7 +729,7 @@ __device__ __forceinline__ const T* col_of(const ColList& L, int a, int ld) {
 // in a fixed order at the end.
 typedef double skr_d4 __attribute__((ext_vector_type(4)));
 template <int TA, int TB, typename LT, typename RT>
-__global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColList R, int nr, int n, int ld,
+__device__ __forceinline__ void k_gram_partial_body(ColList L, int nl, ColList R, int nr, int n, int ld,
                                                        int rows_per_block, double* __restrict__ gpart) {
     constexpr int NT = TA * TB, KS = NT > 12 ? 2 : 4;   // row steps (of 4 rows) per operand batch
     __shared__ double red[(NWAVE - 1) * NT * 4 * 64];
@@ -731,11 +808,17 @@ __global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColLis
                 }
     }
 }
+template <int TA, int TB, typename LT, typename RT>
+__global__ __launch_bounds__(ROWS) void k_gram_partial(ColList L, int nl, ColList R, int nr, int n, int ld,
+                                                       int rows_per_block, double* __restrict__ gpart) {
+    k_gram_partial_body<TA, TB, LT, RT>(L, nl, R, nr, n, ld, rows_per_block, gpart);
+}
+
 
 // out[(e / nr) * ostride + e % nr] = sum_b gpart[b][e]: one workgroup per 64 outputs; wave w sums a
 // contiguous quarter of the partials (loads issued 16 at a time), then the quarters are added in
 // order.
-__global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__ gpart, int nb, int E, int nr,
+__device__ __forceinline__ void k_gram_reduce_body(const double* __restrict__ gpart, int nb, int E, int nr,
                                                       int ostride, double* __restrict__ out) {
     __shared__ double sh[NWAVE * 64];
     const int lane = lane_id(), w = wave_id();
@@ -763,6 +846,13 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
         out[(e / nr) * ostride + e % nr] = t;
     }
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__ gpart, int nb, int E, int nr,
+                                                      int ostride, double* __restrict__ out) {
+    k_gram_reduce_body(gpart, nb, E, nr, ostride, out);
+}
+#endif
+
 
 // ---------------------------------------------------------------------------------------------
 // Cycle end (Alg. 2): x += V-hat y, r -= W-hat G y, C <- W-hat Qc, U <- V-hat P_k R^{-1} (all
@@ -783,7 +873,7 @@ __global__ __launch_bounds__(ROWS) void k_gram_reduce(const double* __restrict__
 // column steps load while the current four multiply.
 typedef double skr_d4u __attribute__((ext_vector_type(4)));
 template <int KB, typename BT>
-__global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
+__device__ __forceinline__ void k_cycle_update_body(double* __restrict__ x, double* __restrict__ r,
                                                        BT* __restrict__ basis, BT* __restrict__ U,
                                                        int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
                                                        double* part_n, Ctrl* ctrl) {
@@ -914,11 +1004,19 @@ __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, d
     block_partial1(rn2, part_n, lb, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->stop = 0;
 }
+template <int KB, typename BT>
+__global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
+                                                       BT* __restrict__ basis, BT* __restrict__ U,
+                                                       int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
+                                                       double* part_n, Ctrl* ctrl) {
+    k_cycle_update_body<KB, BT>(x, r, basis, U, n, ld, vbase, kc, nblk, coef, part_n, ctrl);
+}
+
 
 // ---------------------------------------------------------------------------------------------
 // True residual r = b - A x (overwrites r) and the partials of ||r||^2 (closed by k_norm_finish).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* __restrict__ b,
+__device__ __forceinline__ void k_true_residual_body(DevOp op, const double* __restrict__ b,
                                                         const double* __restrict__ x, double* __restrict__ r,
                                                         int nblk, double* part_n) {
     __shared__ double sh[NWAVE];
@@ -932,6 +1030,14 @@ __global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* 
     }
     block_partial1(v, part_n, lb, sh);
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* __restrict__ b,
+                                                        const double* __restrict__ x, double* __restrict__ r,
+                                                        int nblk, double* part_n) {
+    k_true_residual_body(op, b, x, r, nblk, part_n);
+}
+#endif
+
 
 // ---------------------------------------------------------------------------------------------
 // Start-up with a carried recycle space (App. B.1): Z = A Y, CholQR2 of Z with column drops,
@@ -939,18 +1045,30 @@ __global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* 
 // refinement step of the mixed-precision mode (x += U C^T r, r -= C C^T r).
 // ---------------------------------------------------------------------------------------------
 template <typename BT>
-__global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const BT* __restrict__ Y, BT* __restrict__ Z,
+__device__ __forceinline__ void k_spmm_body(DevOp op, const BT* __restrict__ Y, BT* __restrict__ Z,
                                                int ld, int kin) {
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i >= op.n) return;
     for (int c = 0; c < kin; ++c)
         Z[(size_t)c * ld + i] = (BT)op_row_k<-1, BT, false, sizeof(BT) == 4>(op, Y + (size_t)c * ld, i, 1.0);
 }
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_spmm(DevOp op, const BT* __restrict__ Y, BT* __restrict__ Z,
+                                               int ld, int kin) {
+    k_spmm_body<BT>(op, Y, Z, ld, kin);
+}
+
 
 // FP32 copy of an operator array (round to nearest even): the mixed mode's inner operator.
-__global__ __launch_bounds__(ROWS) void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long count) {
+__device__ __forceinline__ void k_to_f32_body(const double* __restrict__ src, float* __restrict__ dst, long count) {
     for (long e = blockIdx.x * (long)ROWS + threadIdx.x; e < count; e += (long)gridDim.x * ROWS) dst[e] = (float)src[e];
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long count) {
+    k_to_f32_body(src, dst, count);
+}
+#endif
+
 
 // Z = A C for the kc <= KB recycled columns C = basis columns 0..kc-1 (FP64), the product the merged
 // Arnoldi kernel takes A C from. Z is stored in FP32: the kernel only multiplies it by second-pass
@@ -959,7 +1077,7 @@ __global__ __launch_bounds__(ROWS) void k_to_f32(const double* __restrict__ src,
 // operator row (CSR entries or stencil faces) is loaded once and applied to every column, each
 // column's terms added in the order of op_row_k.
 template <int KIND, int KB>
-__global__ __launch_bounds__(ROWS) void k_apply_c(DevOp op, const double* __restrict__ C, float* __restrict__ Z,
+__device__ __forceinline__ void k_apply_c_body(DevOp op, const double* __restrict__ C, float* __restrict__ Z,
                                                   int ld, int kc, int nblk) {
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
@@ -1044,11 +1162,17 @@ __global__ __launch_bounds__(ROWS) void k_apply_c(DevOp op, const double* __rest
     for (int c = 0; c < KB; ++c)
         if (c < kc) Z[(size_t)c * ld + i] = (float)acc[c];
 }
+template <int KIND, int KB>
+__global__ __launch_bounds__(ROWS) void k_apply_c(DevOp op, const double* __restrict__ C, float* __restrict__ Z,
+                                                  int ld, int kc, int nblk) {
+    k_apply_c_body<KIND, KB>(op, C, Z, ld, kc, nblk);
+}
+
 
 // Row-wise triangular solves z <- z R^{-1} (R upper, k x k, ld KMAX) on Z (kept columns gathered
 // through keep[]) and on U, compacting both to the first k_eff columns.
 template <typename BT>
-__global__ __launch_bounds__(ROWS) void k_startup_apply(BT* __restrict__ Z, BT* __restrict__ U, int n,
+__device__ __forceinline__ void k_startup_apply_body(BT* __restrict__ Z, BT* __restrict__ U, int n,
                                                         int ld, const Coef* coef, int use_keep, int second) {
     __shared__ double Rs[KMAX * KMAX];
     __shared__ int ks[KMAX];
@@ -1086,13 +1210,19 @@ __global__ __launch_bounds__(ROWS) void k_startup_apply(BT* __restrict__ Z, BT* 
             U[(size_t)c * ld + i] = (BT)u[c];
         }
 }
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_startup_apply(BT* __restrict__ Z, BT* __restrict__ U, int n,
+                                                        int ld, const Coef* coef, int use_keep, int second) {
+    k_startup_apply_body<BT>(Z, U, n, ld, coef, use_keep, second);
+}
+
 
 // x = x0 + U c, r -= C c with c = C^T r (ke entries, from a Gram product), and the partials of
 // ||r||^2 (closed by k_norm_finish). x0 = 0 at a system start, the current iterate at a refinement
 // step. The columns are taken eight at a time, every load of a group in flight together at clamped
 // column indices (a coefficient of zero past ke), products added in column order.
 template <typename BT>
-__global__ __launch_bounds__(ROWS) void k_startup_project(double* __restrict__ x, double* __restrict__ r,
+__device__ __forceinline__ void k_startup_project_body(double* __restrict__ x, double* __restrict__ r,
                                                           const BT* __restrict__ C, const BT* __restrict__ U,
                                                           int n, int ld, int nblk, int ke, int add_x,
                                                           const double* __restrict__ cvec, double* part_n) {
@@ -1126,14 +1256,24 @@ __global__ __launch_bounds__(ROWS) void k_startup_project(double* __restrict__ x
     }
     block_partial1(v, part_n, lb, sh);
 }
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void k_startup_project(double* __restrict__ x, double* __restrict__ r,
+                                                          const BT* __restrict__ C, const BT* __restrict__ U,
+                                                          int n, int ld, int nblk, int ke, int add_x,
+                                                          const double* __restrict__ cvec, double* part_n) {
+    k_startup_project_body<BT>(x, r, C, U, n, ld, nblk, ke, add_x, cvec, part_n);
+}
+
 
 // ---------------------------------------------------------------------------------------------
 // Plain y = A x (the sparse product alone, for the SpMV entry point).
 // ---------------------------------------------------------------------------------------------
+#ifndef SKR_CHAINS_UNIT
 __global__ __launch_bounds__(ROWS) void k_spmv(DevOp op, const double* __restrict__ x, double* __restrict__ y) {
     const int i = blockIdx.x * ROWS + threadIdx.x;
     if (i < op.n) y[i] = op_row(op, x, i, 1.0);
 }
+#endif
 
 // ---------------------------------------------------------------------------------------------
 // Partial folding for large grids. Every workgroup of a step kernel re-sums the partials of the
@@ -1143,7 +1283,7 @@ __global__ __launch_bounds__(ROWS) void k_spmv(DevOp op, const double* __restric
 // added in wave order), and the consumer re-sums the NFOLD rows.
 // ---------------------------------------------------------------------------------------------
 // Columns [0, width) (width <= NC), 64 per pass.
-__global__ __launch_bounds__(ROWS) void k_fold(const double* __restrict__ part, int nblk, int width,
+__device__ __forceinline__ void k_fold_body(const double* __restrict__ part, int nblk, int width,
                                                double* __restrict__ out) {
     __shared__ double sh[NWAVE * 64];
     const int lane = lane_id(), w = wave_id();
@@ -1174,7 +1314,14 @@ __global__ __launch_bounds__(ROWS) void k_fold(const double* __restrict__ part, 
         __syncthreads();
     }
 }
-__global__ __launch_bounds__(ROWS) void k_fold1(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_fold(const double* __restrict__ part, int nblk, int width,
+                                               double* __restrict__ out) {
+    k_fold_body(part, nblk, width, out);
+}
+#endif
+
+__device__ __forceinline__ void k_fold1_body(const double* __restrict__ part, int nblk, double* __restrict__ out) {
     __shared__ double sh[NWAVE];
     const int per = (nblk + NFOLD - 1) / NFOLD;
     const int g0 = blockIdx.x * per, g1 = min(nblk, g0 + per);
@@ -1190,16 +1337,42 @@ __global__ __launch_bounds__(ROWS) void k_fold1(const double* __restrict__ part,
         out[blockIdx.x] = t;
     }
 }
+#ifndef SKR_CHAINS_UNIT
+__global__ __launch_bounds__(ROWS) void k_fold1(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    k_fold1_body(part, nblk, out);
+}
+#endif
+
+// Host helpers of both launcher sets.
+static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
+static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
+#define SKR_DISPATCH8(NLV, CALL)                        \
+    switch (NLV) {                                      \
+        case 8: CALL(8); break;                         \
+        case 16: CALL(16); break;                       \
+        case 24: CALL(24); break;                       \
+        case 32: CALL(32); break;                       \
+        case 40: CALL(40); break;                       \
+        case 48: CALL(48); break;                       \
+        case 56: CALL(56); break;                       \
+        case 64: CALL(64); break;                       \
+        case 72: CALL(72); break;                       \
+        case 80: CALL(80); break;                       \
+        default: CALL(88); break;                       \
+    }
+
+// This file is compiled twice. Without SKR_CHAINS_UNIT it gives the single-chain kernels and their
+// launchers; with it, the batched kernels of skr_solve_chains (one grid row per chain) and theirs.
+// Both wrap the same device bodies above, so the arithmetic of a chain is the same either way.
+#ifndef SKR_CHAINS_UNIT
+// ---------------------------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------------------------
 static inline const double* pn_src(const Work& w) { return w.fold ? w.fold_n : w.part_n; }
 static inline int pn_cnt(const Work& w) { return w.fold ? NFOLD : w.nblk; }
 void launch_fold_n(hipStream_t s, const Work& w) {
     if (w.fold) hipLaunchKernelGGL(k_fold1, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_n, w.nblk, w.fold_n);
 }
-
-// ---------------------------------------------------------------------------------------------
-// Launch wrappers
-// ---------------------------------------------------------------------------------------------
-static inline int blocks_for(long n) { return (int)((n + ROWS - 1) / ROWS); }
 
 static void launch_norm_finish(hipStream_t s, const Work& w, int mode, double rtol, int ke) {
     hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(ROWS), 0, s, pn_src(w), pn_cnt(w), mode, rtol, ke, w.ctrl);
@@ -1229,7 +1402,6 @@ void launch_check_finite(hipStream_t s, const Work& w, const double* v, long cou
 void launch_zero(hipStream_t s, double* x, int n) {
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(n)), dim3(ROWS), 0, s, x, n);
 }
-static inline int bucket8(int c) { return c <= 8 ? 8 : ((c + 7) / 8) * 8; }
 template <typename BT>
 static inline BT* bas(const Work& w) { return reinterpret_cast<BT*>(w.basis); }
 template <typename BT>
@@ -1308,20 +1480,6 @@ static void step_c(hipStream_t s, const Work& w, double* dst, int kc, int j, hip
                               w.part_n, w.red2, (const Ctrl*)w.ctrl);
 }
 
-#define SKR_DISPATCH8(NLV, CALL)                        \
-    switch (NLV) {                                      \
-        case 8: CALL(8); break;                         \
-        case 16: CALL(16); break;                       \
-        case 24: CALL(24); break;                       \
-        case 32: CALL(32); break;                       \
-        case 40: CALL(40); break;                       \
-        case 48: CALL(48); break;                       \
-        case 56: CALL(56); break;                       \
-        case 64: CALL(64); break;                       \
-        case 72: CALL(72); break;                       \
-        case 80: CALL(80); break;                       \
-        default: CALL(88); break;                       \
-    }
 
 // One Arnoldi step (three kernels). With ev != nullptr, ev[2q], ev[2q+1] take the start and end of
 // kernel q (A, B, C).
@@ -1554,5 +1712,431 @@ void launch_spmv_repeat(hipStream_t s, const DevOp& op, const double* x, double*
 }
 
 int gram_cols_max(int m, int k) { return (2 * k + m + 2) * (k + 1); }
+
+#endif  // !SKR_CHAINS_UNIT
+
+#ifdef SKR_CHAINS_UNIT
+// ---------------------------------------------------------------------------------------------
+// Batched launches: chain blockIdx.y of the table, the same bodies as the single-chain kernels, so
+// that every chain's arithmetic is that of the chain solved alone. A chain with `on` clear, or past
+// the steps of its cycle, returns at once.
+// ---------------------------------------------------------------------------------------------
+#define SKR_CD const ChainDesc& cd = tab[blockIdx.y]; if (!cd.on) return; const Work& w = cd.w
+__device__ __forceinline__ const double* pn_src_d(const Work& w) { return w.fold ? w.fold_n : w.part_n; }
+__device__ __forceinline__ int pn_cnt_d(const Work& w) { return w.fold ? NFOLD : w.nblk; }
+
+__global__ void kb_clear_nonfinite(const ChainDesc* tab) {
+    SKR_CD;
+    if (threadIdx.x == 0) k_clear_nonfinite_body(w.ctrl);
+}
+__global__ __launch_bounds__(ROWS) void kb_init(const ChainDesc* tab) {
+    SKR_CD;
+    k_init_body(cd.b, cd.x, w.r, w.n, w.nblk, w.part_n);
+}
+__global__ __launch_bounds__(ROWS) void kb_fold1(const ChainDesc* tab, int j) {
+    SKR_CD;
+    if (j >= 0 && j >= cd.scyc) return;
+    k_fold1_body(w.part_n, w.nblk, w.fold_n);
+}
+__global__ __launch_bounds__(ROWS) void kb_norm_finish(const ChainDesc* tab, int mode, double rtol) {
+    SKR_CD;
+    k_norm_finish_body(pn_src_d(w), pn_cnt_d(w), mode, rtol, cd.kc, w.ctrl);
+}
+__global__ __launch_bounds__(ROWS) void kb_check_finite(const ChainDesc* tab) {
+    SKR_CD;
+    k_check_finite_body(cd.arr[cd.part], cd.cnt[cd.part], w.ctrl);
+}
+__global__ __launch_bounds__(ROWS) void kb_to_f32(const ChainDesc* tab) {
+    SKR_CD;
+    k_to_f32_body(cd.arr[cd.part], cd.arr32[cd.part], cd.cnt[cd.part]);
+}
+__global__ __launch_bounds__(ROWS) void kb_check_sym(const ChainDesc* tab) {
+    SKR_CD;
+    if (cd.op.kind == SKR_OP_CSR) k_check_sym_csr_body(cd.op, w.ctrl);
+}
+__global__ __launch_bounds__(ROWS) void kb_zero(const ChainDesc* tab) {
+    SKR_CD;
+    k_zero_body(cd.x, w.n);
+}
+__global__ __launch_bounds__(ROWS) void kb_true_residual(const ChainDesc* tab) {
+    SKR_CD;
+    k_true_residual_body(cd.op, cd.b, cd.x, w.r, w.nblk, w.part_n);
+}
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void kb_spmm(const ChainDesc* tab) {
+    SKR_CD;
+    k_spmm_body<BT>(cd.op, (const BT*)w.U, (BT*)w.basis, w.ld, cd.kin);
+}
+// which: 0 the cycle end (Lg, Rg), 1 the start-up (Ls, Ls), 2 the projection (Lp, r), 3 (Lg, r)
+template <int TA, int TB, typename LT, typename RT>
+__global__ __launch_bounds__(ROWS) void kb_gram_partial(const ChainDesc* tab, int which, int nl, int nr, int rpb) {
+    SKR_CD;
+    const ColList Rr = {{w.r, nullptr, nullptr, nullptr}, {1, 0, 0, 0}};
+    const ColList& L = which == 0 || which == 3 ? cd.Lg : (which == 1 ? cd.Ls : cd.Lp);
+    const ColList& R = which == 0 ? cd.Rg : (which == 1 ? cd.Ls : Rr);
+    k_gram_partial_body<TA, TB, LT, RT>(L, nl, R, nr, w.n, w.ld, rpb, w.gpart);
+}
+// out: the Gram block (+ offset) or, with to_red1, red1 (the projection's C^T r)
+__global__ __launch_bounds__(ROWS) void kb_gram_reduce(const ChainDesc* tab, int nb, int E, int nr, int ostride,
+                                                       int to_red1, int off) {
+    SKR_CD;
+    k_gram_reduce_body(w.gpart, nb, E, nr, ostride, to_red1 ? w.red1 : w.gram + off);
+}
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void kb_startup_apply(const ChainDesc* tab, int use_keep, int second) {
+    SKR_CD;
+    k_startup_apply_body<BT>((BT*)w.basis, (BT*)w.U, w.n, w.ld, w.coef, use_keep, second);
+}
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void kb_startup_project(const ChainDesc* tab, int add_x) {
+    SKR_CD;
+    k_startup_project_body<BT>(cd.x, w.r, (const BT*)w.basis, (const BT*)w.U, w.n, w.ld, w.nblk, cd.kc, add_x,
+                               w.red1, w.part_n);
+}
+template <int KIND, int KB>
+__global__ __launch_bounds__(ROWS) void kb_apply_c(const ChainDesc* tab) {
+    SKR_CD;
+    k_apply_c_body<KIND, KB>(cd.op, (const double*)w.basis, (float*)w.Z, w.ld, cd.kc, w.nblk);
+}
+template <int NL, int KIND, typename BT>
+__global__ __launch_bounds__(ROWS) void kb_step_a(const ChainDesc* tab, int j) {
+    SKR_CD;
+    if (j >= cd.scyc) return;
+    const double* src = (j == 0) ? w.r : w.W[(j - 1) & 1];
+    k_step_a_body<NL, KIND, BT>(cd.op, src, w.W[j & 1], (BT*)w.basis, w.ld, cd.kc, w.k, j, w.nblk, pn_cnt_d(w),
+                                pn_src_d(w), w.part_a, w.red1, w.red2, w.H, w.Bm, w.ctrl);
+}
+template <int NL, typename BT, bool FOLDED, bool NORM>
+__global__ __launch_bounds__(ROWS) void kb_step_b(const ChainDesc* tab, int j) {
+    SKR_CD;
+    if (j >= cd.scyc) return;
+    k_step_b_body<NL, BT, FOLDED, NORM>(w.W[j & 1], (const BT*)w.basis, w.n, w.ld, cd.kc, w.k, j, w.nblk,
+                                        FOLDED ? NFOLD : w.nblk, FOLDED ? w.fold_a : w.part_a, w.part_b, w.red1,
+                                        w.ctrl);
+}
+template <int NL, typename BT, bool FOLDED>
+__global__ __launch_bounds__(ROWS) void kb_step_c(const ChainDesc* tab, int j) {
+    SKR_CD;
+    if (j >= cd.scyc) return;
+    k_step_c_body<NL, BT, FOLDED>(w.W[j & 1], (const BT*)w.basis, w.n, w.ld, cd.kc, w.k, j, w.nblk,
+                                  FOLDED ? NFOLD : w.nblk, FOLDED ? w.fold_b : w.part_b, w.part_n, w.red2, w.ctrl);
+}
+// which 0: part_a -> fold_a, 1: part_b -> fold_b
+__global__ __launch_bounds__(ROWS) void kb_fold(const ChainDesc* tab, int j, int which, int width) {
+    SKR_CD;
+    if (j >= cd.scyc) return;
+    k_fold_body(which ? w.part_b : w.part_a, w.nblk, width, which ? w.fold_b : w.fold_a);
+}
+// LAST: the cycle's final closing at j = scyc of each chain (j is ignored)
+template <int NL, int KIND, int KZ, bool LAST>
+__global__ __launch_bounds__(ROWS) void kb_step_m(const ChainDesc* tab, int j) {
+    SKR_CD;
+    if (LAST) j = cd.scyc;
+    else if (j >= cd.scyc) return;
+    k_step_m_body<NL, KIND, KZ, LAST>(cd.op, w.W[(j - 1) & 1], w.W[j & 1], (double*)w.basis, (const float*)w.Z,
+                                      w.ld, cd.kc, w.k, j, w.nblk, w.fold ? NFOLD : w.nblk,
+                                      w.fold ? w.fold_b : w.part_b, w.part_a, w.red1,
+                                      w.gcorr + ((j - 1) & 1) * NC, w.gcorr + (j & 1) * NC, w.H, w.Bm, w.ctrl);
+}
+template <typename BT>
+__global__ __launch_bounds__(ROWS) void kb_close_basis(const ChainDesc* tab) {
+    SKR_CD;
+    k_close_basis_body<BT>(w.W[0], w.W[1], (BT*)w.basis, w.n, w.ld, cd.kc, w.k, cd.scyc, pn_cnt_d(w), pn_src_d(w),
+                           w.red1, w.red2, w.H, w.Bm, w.ctrl);
+}
+template <int KB, typename BT>
+__global__ __launch_bounds__(ROWS) void kb_cycle_update(const ChainDesc* tab) {
+    SKR_CD;
+    k_cycle_update_body<KB, BT>(cd.x, w.r, (BT*)w.basis, (BT*)w.U, w.n, w.ld, w.k, cd.kc, w.nblk, w.coef,
+                                w.part_n, w.ctrl);
+}
+// The control snapshot of every chain (and the start-up's k_eff) into one host-readable array.
+__global__ void kb_gather(const ChainDesc* tab, CtrlHost* out, int* keff) {
+    const ChainDesc& cd = tab[blockIdx.y];
+    constexpr int NW = sizeof(CtrlHost) / sizeof(int);
+    const int t = threadIdx.x;
+    if (t < NW) ((int*)&out[blockIdx.y])[t] = ((const int*)cd.w.ctrl)[t];
+    if (t == 0) keff[blockIdx.y] = cd.w.coef->k_eff;
+}
+#undef SKR_CD
+
+// Launchers of the batched kernels, mirroring the single-chain launchers above.
+static inline dim3 grid_b(int x, const Batch& B) { return dim3((unsigned)x, (unsigned)B.C); }
+void blaunch_gather(const Batch& B, CtrlHost* out, int* keff) {
+    hipLaunchKernelGGL(kb_gather, grid_b(1, B), dim3(64), 0, B.s, B.cd, out, keff);
+}
+void blaunch_fold_n(const Batch& B, int j) {
+    if (B.w0.fold) hipLaunchKernelGGL(kb_fold1, grid_b(NFOLD, B), dim3(ROWS), 0, B.s, B.cd, j);
+}
+void blaunch_norm_finish(const Batch& B, int mode, double rtol) {
+    hipLaunchKernelGGL(kb_norm_finish, grid_b(1, B), dim3(ROWS), 0, B.s, B.cd, mode, rtol);
+}
+void blaunch_clear_nonfinite(const Batch& B) {
+    hipLaunchKernelGGL(kb_clear_nonfinite, grid_b(1, B), dim3(1), 0, B.s, B.cd);
+}
+void blaunch_init(const Batch& B, double rtol) {
+    hipLaunchKernelGGL(kb_init, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd);
+    blaunch_fold_n(B, -1);
+    blaunch_norm_finish(B, FIN_INIT, rtol);
+}
+// checks (finite, and symmetric for CSR) of operator array `part` of every chain; grid as the single path
+void blaunch_check_finite(const Batch& B, long count_max) {
+    if (count_max <= 0) return;
+    const int g = (int)std::min<long>(1024, (count_max + ROWS - 1) / ROWS);
+    hipLaunchKernelGGL(kb_check_finite, grid_b(g, B), dim3(ROWS), 0, B.s, B.cd);
+}
+void blaunch_to_f32(const Batch& B, long count_max) {
+    if (count_max <= 0) return;
+    const int g = (int)std::min<long>(2048, (count_max + ROWS - 1) / ROWS);
+    hipLaunchKernelGGL(kb_to_f32, grid_b(g, B), dim3(ROWS), 0, B.s, B.cd);
+}
+void blaunch_check_sym(const Batch& B) {
+    hipLaunchKernelGGL(kb_check_sym, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd);
+}
+void blaunch_zero(const Batch& B) {
+    hipLaunchKernelGGL(kb_zero, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd);
+}
+void blaunch_true_residual(const Batch& B) {
+    hipLaunchKernelGGL(kb_true_residual, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd);
+    blaunch_fold_n(B, -1);
+    blaunch_norm_finish(B, FIN_TRUE_RES, 0.0);
+}
+void blaunch_spmm(const Batch& B) {
+    if (B.w0.mixed)
+        hipLaunchKernelGGL(kb_spmm<float>, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd);
+    else
+        hipLaunchKernelGGL(kb_spmm<double>, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd);
+}
+template <typename LT, typename RT>
+static void blaunch_gram_t(const Batch& B, int which, int nl, int nr, int ostride, int to_red1, int off) {
+    const Work& w = B.w0;
+    const int E = nl * nr;
+    const int rpb = ((w.n + w.ngblk - 1) / w.ngblk + GCHUNK - 1) / GCHUNK * GCHUNK;
+    const int nb = (w.n + rpb - 1) / rpb;
+    const int la = nl <= 32 ? 2 : (nl <= 64 ? 4 : (nl <= 96 ? 6 : 8));
+    const int lbk = nr <= 16 ? 1 : (nr <= 32 ? 2 : 3);
+#define SKR_BGP(LA, LB)                                                                                     \
+    hipLaunchKernelGGL((kb_gram_partial<LA, LB, LT, RT>), grid_b(nb, B), dim3(ROWS), 0, B.s, B.cd, which, nl, nr, rpb)
+#define SKR_BGP_B(LA)                           \
+    switch (lbk) {                              \
+        case 1: SKR_BGP(LA, 1); break;          \
+        case 2: SKR_BGP(LA, 2); break;          \
+        default: SKR_BGP(LA, 3); break;         \
+    }
+    switch (la) {
+        case 2: SKR_BGP_B(2); break;
+        case 4: SKR_BGP_B(4); break;
+        case 6: SKR_BGP_B(6); break;
+        default: SKR_BGP_B(8); break;
+    }
+#undef SKR_BGP_B
+#undef SKR_BGP
+    hipLaunchKernelGGL(kb_gram_reduce, grid_b((E + 63) / 64, B), dim3(ROWS), 0, B.s, B.cd, nb, E, nr, ostride,
+                       to_red1, off);
+}
+// start-up Gram of kcols columns (uniform over the chains launched)
+void blaunch_startup_gram(const Batch& B, int kcols) {
+    if (B.w0.mixed) blaunch_gram_t<float, float>(B, 1, kcols, kcols, kcols, 0, 0);
+    else blaunch_gram_t<double, double>(B, 1, kcols, kcols, kcols, 0, 0);
+}
+void blaunch_startup_apply(const Batch& B, int use_keep, int second) {
+    if (B.w0.mixed)
+        hipLaunchKernelGGL(kb_startup_apply<float>, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd,
+                           use_keep, second);
+    else
+        hipLaunchKernelGGL(kb_startup_apply<double>, grid_b(blocks_for(B.w0.n), B), dim3(ROWS), 0, B.s, B.cd,
+                           use_keep, second);
+}
+// c = C^T r over cd.kc = ke columns (uniform), then x (+)= U c, r -= C c and ||r||
+void blaunch_startup_project(const Batch& B, int ke, int add_x) {
+    if (B.w0.mixed) {
+        blaunch_gram_t<float, double>(B, 2, ke, 1, 1, 1, 0);
+        hipLaunchKernelGGL(kb_startup_project<float>, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, add_x);
+    } else {
+        blaunch_gram_t<double, double>(B, 2, ke, 1, 1, 1, 0);
+        hipLaunchKernelGGL(kb_startup_project<double>, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, add_x);
+    }
+    blaunch_fold_n(B, -1);
+    blaunch_norm_finish(B, FIN_PROJECT, 0.0);
+}
+void blaunch_apply_c(const Batch& B, int kind, int kc) {
+    if (!B.w0.merged || kc <= 0) return;
+#define SKR_BAC(KIND, KB) hipLaunchKernelGGL((kb_apply_c<KIND, KB>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd)
+#define SKR_BAC_K(KIND)                      \
+    if (kc <= 8) SKR_BAC(KIND, 8);           \
+    else if (kc <= 16) SKR_BAC(KIND, 16);    \
+    else if (kc <= 24) SKR_BAC(KIND, 24);    \
+    else SKR_BAC(KIND, 32);
+    if (kind == SKR_OP_CSR) {
+        SKR_BAC_K(SKR_OP_CSR)
+    } else if (kind == SKR_OP_STENCIL7) {
+        SKR_BAC_K(SKR_OP_STENCIL7)
+    } else {
+        SKR_BAC_K(SKR_OP_STENCIL5)
+    }
+#undef SKR_BAC_K
+#undef SKR_BAC
+}
+// one Arnoldi step of every chain launched (uniform kc and operator kind): the single path's kernels
+template <int NL, int KIND, typename BT>
+static void bstep_a(const Batch& B, int j) {
+    hipLaunchKernelGGL((kb_step_a<NL, KIND, BT>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, j);
+}
+template <int NL, typename BT>
+static void bstep_a_k(const Batch& B, int kind, int j) {
+    if (kind == SKR_OP_CSR) bstep_a<NL, SKR_OP_CSR, BT>(B, j);
+    else if (kind == SKR_OP_STENCIL7) bstep_a<NL, SKR_OP_STENCIL7, BT>(B, j);
+    else bstep_a<NL, SKR_OP_STENCIL5, BT>(B, j);
+}
+template <int NL, typename BT, bool NORM>
+static void bstep_b(const Batch& B, int j) {
+    if (B.w0.fold)
+        hipLaunchKernelGGL((kb_step_b<NL, BT, true, NORM>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, j);
+    else
+        hipLaunchKernelGGL((kb_step_b<NL, BT, false, NORM>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, j);
+}
+template <int NL, typename BT>
+static void bstep_c(const Batch& B, int j) {
+    if (B.w0.fold)
+        hipLaunchKernelGGL((kb_step_c<NL, BT, true>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, j);
+    else
+        hipLaunchKernelGGL((kb_step_c<NL, BT, false>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd, j);
+}
+static void bfold(const Batch& B, int j, int which, int width) {
+    if (B.w0.fold) hipLaunchKernelGGL(kb_fold, grid_b(NFOLD, B), dim3(ROWS), 0, B.s, B.cd, j, which, width);
+}
+template <int NL, int KZ, bool LAST>
+static void bstep_m_z(const Batch& B, int kind, int j) {
+    if (LAST || kind == SKR_OP_CSR)
+        hipLaunchKernelGGL((kb_step_m<NL, SKR_OP_CSR, LAST ? 0 : KZ, LAST>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s,
+                           B.cd, j);
+    else if (kind == SKR_OP_STENCIL7)
+        hipLaunchKernelGGL((kb_step_m<NL, SKR_OP_STENCIL7, KZ, LAST>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s,
+                           B.cd, j);
+    else
+        hipLaunchKernelGGL((kb_step_m<NL, SKR_OP_STENCIL5, KZ, LAST>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s,
+                           B.cd, j);
+}
+template <int NL, bool LAST>
+static void bstep_m(const Batch& B, int kind, int kc, int j) {
+    if (LAST) bstep_m_z<NL, 0, true>(B, kind, j);
+    else if (kc == 0) bstep_m_z<NL, 0, false>(B, kind, j);
+    else if (kc <= 8) bstep_m_z<NL, 8, false>(B, kind, j);
+    else if (kc <= 16) bstep_m_z<NL, 16, false>(B, kind, j);
+    else if (kc <= 24) bstep_m_z<NL, 24, false>(B, kind, j);
+    else bstep_m_z<NL, 32, false>(B, kind, j);
+}
+// With ev != nullptr, ev[2q], ev[2q+1] take the start and end of kernel q of the step (A or the
+// merged kernel, B, C), as in the single-chain launcher.
+void blaunch_step(const Batch& B, int kind, int kc, int j, hipEvent_t* ev) {
+    const int ncol = kc + j + 1;
+    auto rec = [&](int e) {
+        if (ev) (void)hipEventRecord(ev[e], B.s);
+    };
+    if (B.w0.merged) {
+        const int nla = bucket8(ncol + 1);
+        rec(0);
+        if (j == 0) {
+#define CALL_A(NL) bstep_a_k<NL, double>(B, kind, 0)
+            SKR_DISPATCH8(nla, CALL_A)
+#undef CALL_A
+        } else {
+#define CALL_M(NL) bstep_m<NL, false>(B, kind, kc, j)
+            SKR_DISPATCH8(nla, CALL_M)
+#undef CALL_M
+        }
+        rec(1);
+        bfold(B, j, 0, ncol + 1);
+        rec(2);
+#define CALL_B(NL) bstep_b<NL, double, true>(B, j)
+        SKR_DISPATCH8(nla, CALL_B)
+#undef CALL_B
+        rec(3);
+        bfold(B, j, 1, ncol + 1);
+        return;
+    }
+    const int nla = bucket8(ncol + 1), nlb = bucket8(ncol);
+    if (B.w0.mixed) {
+        rec(0);
+#define CALL_A(NL) bstep_a_k<NL, float>(B, kind, j)
+        SKR_DISPATCH8(nla, CALL_A)
+#undef CALL_A
+        rec(1);
+        bfold(B, j, 0, ncol + 1);
+        rec(2);
+#define CALL_B(NL) bstep_b<NL, float, false>(B, j)
+        SKR_DISPATCH8(nlb, CALL_B)
+#undef CALL_B
+        rec(3);
+        bfold(B, j, 1, ncol);
+        rec(4);
+#define CALL_C(NL) bstep_c<NL, float>(B, j)
+        SKR_DISPATCH8(nlb, CALL_C)
+#undef CALL_C
+        rec(5);
+    } else {
+        rec(0);
+#define CALL_A(NL) bstep_a_k<NL, double>(B, kind, j)
+        SKR_DISPATCH8(nla, CALL_A)
+#undef CALL_A
+        rec(1);
+        bfold(B, j, 0, ncol + 1);
+        rec(2);
+#define CALL_B(NL) bstep_b<NL, double, false>(B, j)
+        SKR_DISPATCH8(nlb, CALL_B)
+#undef CALL_B
+        rec(3);
+        bfold(B, j, 1, ncol);
+        rec(4);
+#define CALL_C(NL) bstep_c<NL, double>(B, j)
+        SKR_DISPATCH8(nlb, CALL_C)
+#undef CALL_C
+        rec(5);
+    }
+    if (B.w0.fold) hipLaunchKernelGGL(kb_fold1, grid_b(NFOLD, B), dim3(ROWS), 0, B.s, B.cd, j);
+}
+void blaunch_close_basis(const Batch& B, int kind, int kc, int s_cycle) {
+    if (B.w0.merged) {
+        const int nla = bucket8(kc + s_cycle + 2);
+#define CALL_L(NL) bstep_m<NL, true>(B, kind, kc, 0)
+        SKR_DISPATCH8(nla, CALL_L)
+#undef CALL_L
+    } else if (B.w0.mixed) {
+        hipLaunchKernelGGL(kb_close_basis<float>, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd);
+    } else {
+        hipLaunchKernelGGL(kb_close_basis<double>, grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd);
+    }
+}
+void blaunch_cycle_gram(const Batch& B, int kc, int jd_max) {
+    const int nl = 2 * kc + jd_max + 1;
+    if (!B.w0.mixed) {
+        blaunch_gram_t<double, double>(B, 0, nl, kc + 1, kc + 1, 0, 0);
+    } else {
+        blaunch_gram_t<float, float>(B, 0, nl, kc, kc + 1, 0, 0);
+        blaunch_gram_t<float, double>(B, 3, nl, 1, kc + 1, 0, kc);
+    }
+}
+void blaunch_cycle_update(const Batch& B, int k_bucket) {
+#define SKR_BUPD(KB, BT) hipLaunchKernelGGL((kb_cycle_update<KB, BT>), grid_b(B.w0.nblk, B), dim3(ROWS), 0, B.s, B.cd)
+#define SKR_BUPD_K(BT)                           \
+    switch (k_bucket) {                          \
+        case 0: SKR_BUPD(0, BT); break;          \
+        case 8: SKR_BUPD(8, BT); break;          \
+        case 16: SKR_BUPD(16, BT); break;        \
+        case 20: SKR_BUPD(20, BT); break;        \
+        case 24: SKR_BUPD(24, BT); break;        \
+        default: SKR_BUPD(32, BT); break;        \
+    }
+    if (B.w0.mixed) {
+        SKR_BUPD_K(float)
+    } else {
+        SKR_BUPD_K(double)
+    }
+#undef SKR_BUPD_K
+#undef SKR_BUPD
+    blaunch_fold_n(B, -1);
+}
+
+#endif  // SKR_CHAINS_UNIT
 
 }  // namespace skr

@@ -38,7 +38,7 @@ SKR_FLAG_MIXED = 4
 SKR_FLAG_CONTINUE = 8
 
 EXPORTED = ("skr_ctx_create", "skr_ctx_destroy", "skr_last_error", "skr_version", "skr_sort", "skr_sort_noalloc",
-            "skr_solve_sequence", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
+            "skr_solve_sequence", "skr_solve_chains", "skr_spmv", "skr_spmv_repeat", "skr_profile_get", "skr_profile_reset",
             "skr_serve_start", "skr_submit", "skr_poll", "skr_wait", "skr_ticket_chain", "skr_serve_stats_get",
             "skr_serve_stop", "skr_recycle_get", "skr_recycle_set", "skr_workspace_bytes")
 
@@ -118,6 +118,10 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(skr_opts),
                                        ctypes.POINTER(skr_result)]
     lib.skr_solve_sequence.restype = i32
+    lib.skr_solve_chains.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(skr_op),
+                                     ctypes.POINTER(vp), ctypes.POINTER(vp), i64, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(skr_opts), ctypes.POINTER(skr_result)]
+    lib.skr_solve_chains.restype = i32
     lib.skr_spmv.argtypes = [vp, ctypes.POINTER(skr_op), vp, vp]
     lib.skr_spmv.restype = i32
     lib.skr_spmv_repeat.argtypes = [vp, ctypes.POINTER(skr_op), vp, vp, ctypes.c_int32, ctypes.POINTER(dbl)]
@@ -256,6 +260,31 @@ def skr_solve_sequence(ctx: int, ops, bs, xs, order=None, m: int = 30, k: int = 
     opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
     res = (skr_result * max(N, 1))()
     rc = _check(load_library().skr_solve_sequence(ctx, arr, bp, xp, N, optr, ctypes.byref(opts), res))
+    return rc, [_result_dict(r) for r in list(res)[:N]]
+
+
+def skr_solve_chains(ctx: int, chain_start, ops, bs, xs, order=None, m: int = 30, k: int = 10, rtol: float = 1e-8,
+                     maxit: int = 10000, flags: int = 0):
+    """Solve the sorted order cut into chains (chain c: positions chain_start[c] .. chain_start[c+1]-1 of
+    ``order``), all chains advanced together, each as ``skr_solve_sequence`` would solve it alone.
+
+    Returns (return code, list of result dicts at the original indices).
+    """
+    N = len(ops)
+    cs = np.ascontiguousarray(np.asarray(chain_start, dtype=np.int64))
+    C = len(cs) - 1
+    arr = (skr_op * max(N, 1))(*[o.c for o in ops])
+    bp = (ctypes.c_void_p * max(N, 1))(*[_ptr(b) for b in bs])
+    xp = (ctypes.c_void_p * max(N, 1))(*[_ptr(x) for x in xs])
+    if order is not None:
+        ordarr = np.ascontiguousarray(np.asarray(order, dtype=np.int64))
+        optr = ordarr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    else:
+        optr = None
+    opts = skr_opts(m=m, k=k, rtol=rtol, maxit=maxit, flags=flags)
+    res = (skr_result * max(N, 1))()
+    rc = _check(load_library().skr_solve_chains(ctx, C, cs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr, bp,
+                                                xp, N, optr, ctypes.byref(opts), res))
     return rc, [_result_dict(r) for r in list(res)[:N]]
 
 

@@ -37,13 +37,15 @@ def solution_bound(A, b, x_ref, rr_a, rr_b):
     return max(1e-7, 1.01 * mu * (rr_a + rr_b)), mu
 
 
-def compare_chain(systems, res_gpu, xs, res_ref, tag, order=None, strict=False, rtol=1e-8):
-    """Per-system parity. Step counts, first two systems of the chain: within max(1, 0.5 %) of the
-    oracle's. The recycle space handed from cycle to cycle (Alg. 2) already depends on rounding: on the
-    first two systems of the sorted 256^2 chain with GCRO-DR(60,20) the oracle itself moves by up to
-    4 steps of ~1,490 (0.27 %) with an FP64 basis and by 1 step with an FP32 basis when b is perturbed
-    by 1e-15 relative, so short solves keep a one-step bar and long ones get twice the measured
-    spread. Later systems inherit recycle spaces whose rounding differs, and the oracle moves by up
+def compare_chain(systems, res_gpu, xs, res_ref, tag, order=None, strict=False, rtol=1e-8, lead=0.005):
+    """Per-system parity. Step counts, first two systems of the chain: within max(1, lead) of the
+    oracle's (lead 0.5 % by default). The recycle space handed from cycle to cycle (Alg. 2) already
+    depends on rounding: on the first two systems of the sorted 256^2 chain with GCRO-DR(60,20) the
+    oracle itself moves by up to 4 steps of ~1,490 (0.27 %) with an FP64 basis when b is perturbed by
+    1e-15 relative, so short solves keep a one-step bar and long ones get twice the measured spread.
+    In the mixed mode (FP32 basis and FP32 inner operator) the same perturbation moves the oracle's
+    first system over 1,491..1,505 steps (0.94 %) and its second over 1,182..1,187, and the BLAS
+    thread count alone moves the first from 1,496 to 1,504: the mixed tests pass lead = 2 %. Later systems inherit recycle spaces whose rounding differs, and the oracle moves by up
     to ~8 % per system (0.3 % in total) under the same perturbation, so from the third system on a
     system may differ by max(3, 10 %) and the chain total by 3 %. strict: one step everywhere (no
     recycling)."""
@@ -62,7 +64,7 @@ def compare_chain(systems, res_gpu, xs, res_ref, tag, order=None, strict=False, 
         log(f"  {tag} pos {pos} sys {i}: iters gpu {g['iters']} oracle {r.iters}  cycles {g['cycles']}/{r.cycles}"
             f"  spmv {g['spmv']}/{r.spmv}  rel {rel:.2e} (bound {bound:.1e}, mu {mu:.2f})")
         assert rel <= bound, (tag, i, rel, bound)
-        slack = 1 if strict else (max(1, int(0.005 * r.iters)) if pos < 2 else max(3, int(0.1 * r.iters)))
+        slack = 1 if strict else (max(1, int(lead * r.iters)) if pos < 2 else max(3, int(0.1 * r.iters)))
         assert abs(g["iters"] - r.iters) <= slack, (tag, pos, i, g["iters"], r.iters)
         assert g["k_start"] == r.k_start, (tag, i)
         tot_g += g["iters"]

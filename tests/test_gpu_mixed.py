@@ -4,12 +4,13 @@ refinement step per cycle with the FP64 operator) against the oracle's mixed mod
 seeded inputs, with the same inner operator (the rounded CSR values, or for the stencils the
 matrix assembled from the rounded faces).
 
-Bars (written in the tests): the same as for the FP64 path, since both sides round the same FP64
-values to FP32 and so follow the same trajectory up to the rare value that sits on an FP32 rounding
-tie: status equal, relative residual (FP64, of the FP64 solution) at most rtol, solution within the
-residual bound of the oracle's, Arnoldi step counts equal up to one step for the first two systems
-of a chain and within max(3, 10 %) further down (3 % for the chain), product counts equal where no
-recycle space is inherited.
+Bars (written in the tests): status equal, relative residual (FP64, of the FP64 solution) at most
+rtol, solution within the residual bound of the oracle's, Arnoldi step counts within max(1, 2 %)
+for the first two systems of a chain and within max(3, 10 %) further down (3 % for the chain),
+product counts equal where no recycle space is inherited. Both sides round the same FP64 values to
+FP32, but a long solve amplifies rounding differences: under a 1e-15 relative perturbation of b the
+oracle's own first system of the sorted 256^2 chain moves over 1,491..1,505 steps in this mode
+(0.94 %), so the first-systems bar is twice that spread; GMRES (no recycling) keeps one step.
 """
 import numpy as np
 import pytest
@@ -48,6 +49,10 @@ def _inner(systems, kind):
     return out
 
 
+# bar on the first two systems of a chain: twice the oracle's own spread in this mode (compare_chain)
+MIXED_LEAD = 0.02
+
+
 def _ref(systems, order, m, k, rtol, maxit=20000, kind="csr"):
     return oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], order, m, k, rtol, maxit,
                                  basis_fp32=True, A_inner=_inner(systems, kind))
@@ -64,7 +69,8 @@ def test_mixed_darcy32_chain(env, kind):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8, kind=kind), f"mixed-darcy32-{kind}", order)
+    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8, kind=kind), f"mixed-darcy32-{kind}", order,
+                  lead=MIXED_LEAD)
 
 
 def test_mixed_gmres_k0(env):
@@ -94,7 +100,7 @@ def test_mixed_beyond_fp32(env, rtol):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=12, k=5, rtol=rtol, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(systems, res, xs, _ref(systems, None, 12, 5, rtol), f"mixed-{rtol}", rtol=rtol)
+    compare_chain(systems, res, xs, _ref(systems, None, 12, 5, rtol), f"mixed-{rtol}", rtol=rtol, lead=MIXED_LEAD)
     for s, x in zip(systems, xs):
         xh = x.cpu().numpy()
         rel = np.linalg.norm(s.b - s.A @ xh) / np.linalg.norm(s.b)
@@ -114,7 +120,7 @@ def test_mixed_3d_chain(env, kind):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, order, m=30, k=10, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8, kind=kind), f"mixed-3d-{kind}", order)
+    compare_chain(systems, res, xs, _ref(systems, order, 30, 10, 1e-8, kind=kind), f"mixed-3d-{kind}", order, lead=MIXED_LEAD)
 
 
 def test_mixed_fold_path(env):
@@ -126,7 +132,7 @@ def test_mixed_fold_path(env):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=30, k=10, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED | skr.SKR_FLAG_FOLD)
     assert rc == skr.SKR_OK
-    compare_chain(systems, res, xs, _ref(systems, None, 30, 10, 1e-8), "mixed-fold")
+    compare_chain(systems, res, xs, _ref(systems, None, 30, 10, 1e-8), "mixed-fold", lead=MIXED_LEAD)
 
 
 def test_mixed_darcy256_prefix(env):
@@ -144,7 +150,7 @@ def test_mixed_darcy256_prefix(env):
     rc, res = skr.skr_solve_sequence(ctx, ops, bs, xs, None, m=60, k=20, rtol=1e-8, maxit=20000,
                                      flags=skr.SKR_FLAG_MIXED)
     assert rc == skr.SKR_OK
-    compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-darcy256-prefix")
+    compare_chain(pre, res, xs, _ref(pre, None, 60, 20, 1e-8), "mixed-darcy256-prefix", lead=MIXED_LEAD)
 
 
 def test_mixed_edge_cases(env):

@@ -93,7 +93,7 @@ def test_weakly_nonsymmetric_mixed_takes_general_route(env):
     assert pr["eig_symmetric"] == 0 and pr["eig_general"] > 0
     ref = oracle.solve_sequence([s.A for s in systems], [s.b for s in systems], None, 20, 6, 1e-8, 20000,
                                 basis_fp32=True)
-    compare_chain(systems, res, xs, ref, "weak-nonsym-mixed")
+    compare_chain(systems, res, xs, ref, "weak-nonsym-mixed", lead=0.02)   # the mixed mode's bar (compare_chain)
 
 
 def test_symmetric_csr_takes_symmetric_route(env):
