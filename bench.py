@@ -101,6 +101,9 @@ def parse():
     ap.add_argument("--serve-sizes", default="64,128,256,512,1024")
     ap.add_argument("--serve-systems", type=int, default=30, help="systems submitted per run (sizes round-robin)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the measured capacity")
+    ap.add_argument("--serve-sweep", default="0.3,0.5,0.9,1.2",
+                    help="further arrival rates (fractions of the capacity) swept after the main Poisson run; "
+                         "empty for none")
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-chains", type=int, default=8)
     ap.add_argument("--serve-chain-cap", type=int, default=0,
@@ -130,7 +133,8 @@ def log(*a):
 
 def serve_bench(a):
     """Continuous batching: capacity from a saturation run (every system submitted at once), then
-    a Poisson arrival run at --serve-load times that capacity. Latency = completion - submission."""
+    a Poisson arrival run at --serve-load times that capacity, then the rates of --serve-sweep.
+    Latency = completion - submission."""
     import threading
 
     import numpy as np
@@ -234,6 +238,18 @@ def serve_bench(a):
         "chains": {"created": st["chains_created"], "retired": st["chains_retired"]},
         "saturation_wall_s": round(wall_sat, 2), "poisson_wall_s": round(wall, 2),
     }
+    sweep = []
+    for f in [float(v) for v in a.serve_sweep.split(",") if v.strip()]:
+        rate = f * capacity
+        g = list(np.random.default_rng(2403).exponential(1.0 / rate, len(order)))
+        log(f"sweep: Poisson run at {f:.2f} x capacity ({rate:.2f} systems/s)")
+        w_, lat_, res_, _ = run(g)
+        L_ = np.array([lat_[i] for i in order]) * 1e3
+        c_ = sum(r["status"] in (skr.SKR_CONVERGED, skr.SKR_BREAKDOWN) for r in res_.values())
+        sweep.append(dict(load=f, arrival_rate=round(rate, 3), throughput=round(c_ / w_, 3), converged=c_,
+                          p50_ms=round(float(np.percentile(L_, 50)), 1), p99_ms=round(float(np.percentile(L_, 99)), 1)))
+    if sweep:
+        out["rate_sweep"] = sweep
     print(json.dumps(out), flush=True)
 
 

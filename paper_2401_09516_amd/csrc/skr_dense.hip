@@ -32,21 +32,22 @@ __device__ __forceinline__ double group8_sum(double x) {
 }
 
 // Copy a rows x cols column-major block from global (leading dimension lds) to LDS (leading
-// dimension ldd) with nthr threads, eight loads in flight per thread (all unconditional).
+// dimension ldd) with nthr threads (a multiple of 64): lane t % 64 takes rows t % 64 (+ 64 ...), the
+// wave t / 64 every (nthr / 64)-th column, eight loads in flight per thread (all unconditional).
 __device__ __forceinline__ void stage_block(double* dst, int ldd, const double* src, int lds, int rows, int cols,
                                             int t, int nthr) {
-    const int total = rows * cols;
-    for (int e0 = 0; e0 < total; e0 += 8 * nthr) {
-        double v[8];
+    const int cstep = nthr >> 6;
+    for (int rb = 0; rb < rows; rb += 64) {
+        const int rr = rb + (t & 63), rc = min(rr, rows - 1);
+        for (int c0 = t >> 6; c0 < cols; c0 += 8 * cstep) {
+            double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = min(e0 + u * nthr + t, total - 1);   // unconditional load (clamped index)
-            v[u] = src[(e % rows) + (e / rows) * lds];
-        }
+            for (int u = 0; u < 8; ++u) v[u] = src[rc + min(c0 + u * cstep, cols - 1) * lds];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * nthr + t;
-            if (e < total) dst[(e % rows) + (e / rows) * ldd] = v[u];
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + u * cstep;
+                if (rr < rows && c < cols) dst[rr + c * ldd] = v[u];
+            }
         }
     }
 }
@@ -269,8 +270,12 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __syncthreads();
     // M = X'' R^{-1}: row r of M solves m R = x'' (forward over the columns, right-looking). Four
     // lanes per row, lane part p holding columns 16p..16p+15 in registers; m_c is broadcast from
-    // the lane that owns column c.
+    // the lane that owns column c. The diagonal of R is kept as its reciprocals Rd and zeroed in LDS
+    // (the strict lower triangle is zero), so that the update of column c by m_c R[c, :] needs no
+    // mask: it leaves the columns up to c unchanged.
     if (t < d) Rd[t] = 1.0 / R[t + t * LDS_];
+    __syncthreads();
+    if (t < d) R[t + t * LDS_] = 0.0;
     __syncthreads();
     {
         const int r = t >> 2, p = t & 3;
@@ -284,8 +289,6 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
             for (int s1 = 0; s1 < 16; ++s1) {
                 const int c = c0 + s1;
                 if (c < d) {
-                    // loads first and a masked coefficient instead of a branch, so that nothing
-                    // waits on an LDS load inside a divergent block
                     double rc[16];
 #pragma unroll
                     for (int s2 = 0; s2 < 16; ++s2) rc[s2] = R[c + (16 * p + s2) * LDS_];
@@ -293,10 +296,7 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                     acc[s1] = (p == owner) ? ml : acc[s1];
                     const double mc = __shfl(ml, (t & ~3) | owner, 64);
 #pragma unroll
-                    for (int s2 = 0; s2 < 16; ++s2) {
-                        const double f = (16 * p + s2 > c) ? mc : 0.0;
-                        acc[s2] = fma(-f, rc[s2], acc[s2]);
-                    }
+                    for (int s2 = 0; s2 < 16; ++s2) acc[s2] = fma(-mc, rc[s2], acc[s2]);
                 }
             }
         }
@@ -310,11 +310,13 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __syncthreads();
     // symmetry test: max |M - M^T| <= sym_tol max |M|
     double amax = 0.0, dmax = 0.0;
-    for (int e = t; e < d * d; e += DT) {
-        const int r = e % d, c = e / d;
-        const double a = S[r + c * LDS_];
-        amax = fmax(amax, fabs(a));
-        dmax = fmax(dmax, fabs(a - S[c + r * LDS_]));
+    const int rl = t & 63, cw = t >> 6;     // row, first column of this thread in the d x d loops below
+    if (rl < d) {
+        for (int c = cw; c < d; c += DT / 64) {
+            const double a = S[rl + c * LDS_];
+            amax = fmax(amax, fabs(a));
+            dmax = fmax(dmax, fabs(a - S[c + rl * LDS_]));
+        }
     }
     amax = wave_max64(amax);
     dmax = wave_max64(dmax);
@@ -327,21 +329,20 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     }
     __syncthreads();
     // M goes to the general stage's input in any case: that stage takes over if this one declines
-    for (int e = t; e < d * d; e += DT) {
-        const int r = e % d, c = e / d;
-        dw->X[r + c * DMAX] = S[r + c * LDS_];
-    }
+    if (rl < d)
+        for (int c = cw; c < d; c += DT / 64) dw->X[rl + c * DMAX] = S[rl + c * LDS_];
     if (!sym_s) {
         if (t == 0) dw->mode = DW_GEN;
         return;
     }
     // S = (M + M^T) / 2 in place (each unordered pair by one thread)
-    for (int e = t; e < d * d; e += DT) {
-        const int r = e % d, c = e / d;
-        if (r < c) {
-            const double v = 0.5 * (S[r + c * LDS_] + S[c + r * LDS_]);
-            S[r + c * LDS_] = v;
-            S[c + r * LDS_] = v;
+    if (rl < d) {
+        for (int c = cw; c < d; c += DT / 64) {
+            if (rl < c) {
+                const double v = 0.5 * (S[rl + c * LDS_] + S[c + rl * LDS_]);
+                S[rl + c * LDS_] = v;
+                S[c + rl * LDS_] = v;
+            }
         }
     }
     __syncthreads();
@@ -353,9 +354,9 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     // j forms the reflector and publishes v (double-buffered); every thread adds its part of
     // p = beta S' v; every wave then sums the four parts of its rows in the same order, so all waves
     // hold the same p and K = beta p^T v / 2, and w = p - K v. The update S' -= v w^T + w v^T takes w
-    // at its columns from the lane that holds that row, and adds the two products without
+    // at its columns from the wave's own copy of w in LDS, and adds the two products without
     // contraction so that S stays exactly symmetric.
-    __shared__ double hvb[2][64], hbeta[2], ppart[DT / 64][64];
+    __shared__ double hvb[2][64], hbeta[2], ppart[DT / 64][64], wsh[DT / 64][64];
     {
         const int r = t & 63;
         const int wv = __builtin_amdgcn_readfirstlane(t >> 6);   // this wave's column class
@@ -401,18 +402,25 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                 const double kp = wave_sum64((r >= j1 && r < d) ? pr * vr : 0.0);
                 const double K = 0.5 * beta * kp;
                 const double wr = fma(-K, vr, pr);
-                const unsigned long long wu = (unsigned long long)__double_as_longlong(wr);
                 const bool rin = r >= j1 && r < d;
+                // w at this thread's columns: each wave passes its own copy of w through LDS (the
+                // reads of one column are a broadcast)
+                wsh[wv][r] = wr;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                double wcv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) wcv[u] = wsh[wv][min(wv + 4 * u, 63)];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int c = wv + 4 * u;
-                    const int cl = min(c, 63);
-                    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)wu, cl);
-                    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(wu >> 32), cl);
-                    const double wc = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-                    const double nv = s[u] - __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vc[u]));
+                    const double nv = s[u] - __dadd_rn(__dmul_rn(vr, wcv[u]), __dmul_rn(wr, vc[u]));
                     s[u] = (rin && c >= j1 && c < d) ? nv : s[u];
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
         // the last 2 x 2 block: T(d-2, d-2), T(d-1, d-2), T(d-1, d-1)
@@ -543,19 +551,21 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __syncthreads();
     const int kn = nsel_s;
 
-    // ---- eigenvectors of T (a lane pair per selected eigenvalue): T - lambda I = L+ D+ L+^T =
-    // U- D- U-^T, twist index r = argmin |gamma_r|, gamma_r = D+_r + D-_r - (a_r - lambda), then
-    // z_r = 1 and z_i = -b_i z_{i+1} / D+_i (i < r), z_{i+1} = -b_i z_i / D-_{i+1} (i >= r), so that
-    // (T - lambda I) z = gamma_r e_r. Lane 2o forms D+ and the upper part of z, lane 2o+1 D- and the
-    // lower part. The eigenvalue from multisection (to 2e-8 ||T||) is refined by one Rayleigh-quotient
-    // step, lambda += gamma_r / ||z||^2 (cubically convergent), kept inside its bisection interval;
-    // the second pass gives the eigenvector. D+ and D- live in V (columns of 32), z overwrites D+.
-    // Quotients use v_rcp_f64 with two Newton steps.
+    // ---- eigenvectors of T (wave 0 and wave 1, lane o for selected eigenvalue o): T - lambda I =
+    // L+ D+ L+^T = U- D- U-^T, twist index r = argmin |gamma_r|, gamma_r = D+_r + D-_r - (a_r - lambda),
+    // then z_r = 1 and z_i = -b_i z_{i+1} / D+_i (i < r), z_{i+1} = -b_i z_i / D-_{i+1} (i >= r), so that
+    // (T - lambda I) z = gamma_r e_r. Wave 0 forms D+ and the upper part of z, wave 1 D- and the lower
+    // part, side by side on two SIMDs (the other waves only join the barriers). The eigenvalue from
+    // multisection (to 2e-8 ||T||) is refined by one Rayleigh-quotient step, lambda += gamma_r / ||z||^2
+    // (cubically convergent), kept inside its bisection interval; the second pass gives the
+    // eigenvector. D+ and D- live in V (columns of 32), z overwrites D+. Quotients use v_rcp_f64 with
+    // two Newton steps.
     double* Fp = V;
     double* Fm = V + DS * KMAX;
-    if (t < 64) {
-        const int o = t >> 1, side = t & 1;
-        const bool act = o < kn;
+    __shared__ double nzs[2][KMAX];
+    {
+        const int o = t & 63, side = t >> 6;
+        const bool act = side < 2 && o < kn;
         const int oc = min(o, KMAX - 1);
         const int ie = act ? isel[oc] : 0;
         const double lo_ = blo[ie], hi_ = bhi[ie];
@@ -587,21 +597,18 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __syncthreads();
             int rt = 0;
             double gam = 0.0, nz = 0.0;
             if (act) {
+                // the same search in both waves (same operands and order, so the same twist index)
                 double gb = __builtin_inf();
                 for (int i = 0; i < d; ++i) {
                     const double g = Fp[i * KMAX + o] + Fm[i * KMAX + o] - (ta[i] - lm);
                     if (fabs(g) < gb) { gb = fabs(g); gam = g; rt = i; }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __syncthreads();    // wave 1 has read D+ before wave 0 overwrites it with z
             if (act) {
                 double z = 1.0;
                 if (side == 0) {
@@ -618,20 +625,21 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                         nz = fma(z, z, nz);
                     }
                 }
+                nzs[side][o] = nz;
             }
-            // ||z||^2 = 1 + upper part + lower part, added in the same order on both lanes
-            const double nzo = row_partner<1>(nz);
-            const double nz2 = 1.0 + (side == 0 ? nz + nzo : nzo + nz);
-            if (act && pass == 0) {
-                const double ln = lm + gam / nz2;
-                if (ln == ln) lm = fmin(fmax(ln, lo_), hi_);
+            __syncthreads();
+            // ||z||^2 = 1 + upper part + lower part, added in the same order in both waves
+            if (act) {
+                const double nzo = nzs[side ^ 1][o];
+                const double nz2 = 1.0 + (side == 0 ? nz + nzo : nzo + nz);
+                if (pass == 0) {
+                    const double ln = lm + gam / nz2;
+                    if (ln == ln) lm = fmin(fmax(ln, lo_), hi_);
+                }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __syncthreads();
         }
     }
-    __syncthreads();
 
     // ---- back-transformation z <- H_0 ... H_{d-3} z and modified Gram-Schmidt, eight lanes per
     // column (column c = t / 8, rows t % 8 + 8 i in registers); the finished columns go to V.
@@ -754,11 +762,9 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                     const double yl = y[s1] * Rd[i];
                     y[s1] = (p == owner) ? yl : y[s1];
                     const double yi = __shfl(yl, (t & ~7) | owner, 64);
+                    // rows i and below of column i of R are zero in LDS: no mask
 #pragma unroll
-                    for (int s2 = 0; s2 < 8; ++s2) {
-                        const double f = (8 * p + s2 < i) ? yi : 0.0;
-                        y[s2] = fma(-f, rq[s2], y[s2]);
-                    }
+                    for (int s2 = 0; s2 < 8; ++s2) y[s2] = fma(-yi, rq[s2], y[s2]);
                 }
             }
         }
