@@ -379,7 +379,11 @@ __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restr
 
 // Pass B: h1 = Q^T w (sum of pass A's partials, also stored for the step's closing), w -= Q h1,
 // partials of Q^T w; with NORM also of ||w||^2 (reduction column ncol), which the merged kernel
-// below needs in place of a pass C.
+// below needs in place of a pass C. Without NORM the coefficients come from a copy of h1 padded
+// with zeros past ncol and the products of the re-read columns past ncol are formed and dropped
+// (their partials are written as zero): no per-column select, which would otherwise keep a
+// selected coefficient and a lane mask per column live beside the basis values (spilling past
+// 256 registers from 64 columns on). The column sums are those of the masked form, bit for bit.
 template <int NL, typename BT, bool FOLDED, bool NORM = false>
 __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const BT* __restrict__ basis,
                                                  int n, int ld, int kc, int vbase, int j, int nblk, int npa,
@@ -388,6 +392,7 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
     constexpr int NR = Width<NL>::NR, NR2 = Width<NL>::NR2;
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
+    __shared__ double hz[NORM ? 1 : NC];
     const int ncol = kc + j + 1;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
@@ -401,26 +406,63 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
     sum_partials<FOLDED ? 16 : 64>(part_a, npa, ncol + 1, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
+    if constexpr (NORM) {
 #pragma unroll
-    for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
-    if (valid) w_io[i] = w;
-    else w = 0.0;
-    auto col_val = [&](int c) {
-        const double qw = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
-        return (NORM && c == ncol) ? w * w : qw;
-    };
-    double acc[NR];
+        for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
+        if (valid) w_io[i] = w;
+        else w = 0.0;
+        auto col_val = [&](int c) {
+            const double qw = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
+            return (c == ncol) ? w * w : qw;
+        };
+        double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
-    const double s = wave_reduce_scatter<NR>(acc);
-    if constexpr (NR2 > 0) {
-        double acc2[NR2];
+        for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
+        const double s = wave_reduce_scatter<NR>(acc);
+        if constexpr (NR2 > 0) {
+            double acc2[NR2];
 #pragma unroll
-        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
-        const double s2 = wave_reduce_scatter<NR2>(acc2);
-        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb);
+            for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
+            const double s2 = wave_reduce_scatter<NR2>(acc2);
+            block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb);
+        }
+        block_partials<NR>(s, sh, part_b, lb);
+    } else {
+        if (threadIdx.x < NC) hz[threadIdx.x] = threadIdx.x < ncol ? hs[threadIdx.x] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NL; ++c) w = fma(-q[c], hz[c], w);
+        if (valid) w_io[i] = w;
+        else w = 0.0;
+        double acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = c < NL ? q[c] * w : 0.0;
+        const double s = wave_reduce_scatter<NR>(acc);
+        double s2 = 0.0;
+        if constexpr (NR2 > 0) {
+            double acc2[NR2];
+#pragma unroll
+            for (int c = 0; c < NR2; ++c) acc2[c] = 64 + c < NL ? q[64 + c] * w : 0.0;
+            s2 = wave_reduce_scatter<NR2>(acc2);
+        }
+        // block sums as in block_partials, with the columns from ncol on written as zero
+        if (lane_id() < NR) sh[wave_id() * NR + lane_id()] = s;
+        if constexpr (NR2 > 0)
+            if (lane_id() < NR2) sh[NWAVE * 64 + wave_id() * NR2 + lane_id()] = s2;
+        __syncthreads();
+        const int c = threadIdx.x;
+        if (c < NR) {
+            double t = sh[c];
+#pragma unroll
+            for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[q2 * NR + c];
+            part_b[lb * NC + c] = c < ncol ? t : 0.0;
+        } else if (NR2 > 0 && c >= 64 && c < 64 + NR2) {
+            double t = sh[NWAVE * 64 + (c - 64)];
+#pragma unroll
+            for (int q2 = 1; q2 < NWAVE; ++q2) t += sh[NWAVE * 64 + q2 * NR2 + (c - 64)];
+            part_b[lb * NC + c] = c < ncol ? t : 0.0;
+        }
     }
-    block_partials<NR>(s, sh, part_b, lb);
 }
 template <int NL, typename BT, bool FOLDED, bool NORM = false>
 __global__ __launch_bounds__(ROWS) void k_step_b(double* __restrict__ w_io, const BT* __restrict__ basis,
@@ -439,6 +481,7 @@ __device__ __forceinline__ void k_step_c_body(double* __restrict__ w_io, const B
                                                  double* __restrict__ red2, const Ctrl* ctrl) {
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
+    __shared__ double hz[NC];
     const int ncol = kc + j + 1;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
@@ -452,8 +495,11 @@ __device__ __forceinline__ void k_step_c_body(double* __restrict__ w_io, const B
     sum_partials<FOLDED ? 16 : 64>(part_b, npb, ncol, sh, hs);
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x < ncol) red2[threadIdx.x] = hs[threadIdx.x];
+    // h2 padded with zeros past ncol (as in pass B: no per-column select)
+    if (threadIdx.x < NC) hz[threadIdx.x] = threadIdx.x < ncol ? hs[threadIdx.x] : 0.0;
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
+    for (int c = 0; c < NL; ++c) w = fma(-q[c], hz[c], w);
     if (valid) w_io[i] = w;
     else w = 0.0;
     block_partial1(w * w, part_n, lb, sh);
