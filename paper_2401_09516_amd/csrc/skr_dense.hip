@@ -100,6 +100,7 @@ __device__ __forceinline__ void k_dense_prep_body(const double* __restrict__ H, 
     // ---- D_k, G, X = W-hat^T V-hat (structured), right-hand side W-hat^T r. Global inputs are
     //      staged with eight loads in flight per lane.
     if (t < kc) Dk[t] = 1.0 / sqrt(gram[(kc + jd_max + 1 + t) * nr + t]);
+    if (t < kc) { gcs[t] = 1.0; gsn[t] = 0.0; }     // no rotation on the D_k rows (handed over as such)
     for (int c = 0; c < d; ++c)
         if (t <= d) {
             G[t + c * LDG] = 0.0;
@@ -107,50 +108,47 @@ __device__ __forceinline__ void k_dense_prep_body(const double* __restrict__ H, 
         }
     __syncthreads();
     {
+        // Lane t takes row t of each block (every block has at most 63 rows here), eight columns'
+        // loads in flight, no integer division.
         // Hbar (rows 0..jd, columns 0..jd-1, Hessenberg) -> G[kc + r][kc + c]
-        const int nh = (jd + 1) * jd;
-        for (int e0 = 0; e0 < nh; e0 += 64 * 8) {
+        const int rh = min(t, jd);
+        for (int c0 = 0; c0 < jd; c0 += 8) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / (jd + 1), r = e - c * (jd + 1);
-                v[u] = (e < nh && r <= c + 1) ? H[r + c * LDH] : 0.0;
-            }
+            for (int u = 0; u < 8; ++u) v[u] = H[rh + min(c0 + u, jd - 1) * LDH];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / (jd + 1), r = e - c * (jd + 1);
-                if (e < nh) G[kc + r + (kc + c) * LDG] = v[u];
+                const int c = c0 + u;
+                if (t <= jd && c < jd) G[kc + t + (kc + c) * LDG] = (t <= c + 1) ? v[u] : 0.0;
             }
         }
         // B (kc x jd) -> G[r][kc + c]
-        const int nbm = kc * jd;
-        for (int e0 = 0; e0 < nbm; e0 += 64 * 8) {
-            double v[8];
+        if (kc > 0) {
+            const int rb = min(t, kc - 1);
+            for (int c0 = 0; c0 < jd; c0 += 8) {
+                double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / max(kc, 1), r = e - c * kc;
-                v[u] = (e < nbm) ? Bm[r + c * KMAX] : 0.0;
-            }
+                for (int u = 0; u < 8; ++u) v[u] = Bm[rb + min(c0 + u, jd - 1) * KMAX];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / max(kc, 1), r = e - c * kc;
-                if (e < nbm) G[r + (kc + c) * LDG] = v[u];
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + u;
+                    if (t < kc && c < jd) G[t + (kc + c) * LDG] = v[u];
+                }
             }
         }
         __syncthreads();
         // [C V]^T U (rows 0..d, columns 0..kc-1) -> X[r][c] D_c;  D_k -> G[c][c]
-        const int ng = (d + 1) * kc;
-        for (int e0 = 0; e0 < ng; e0 += 64 * 8) {
-            double v[8];
+        if (kc > 0) {
+            const int rg = min(t, d);
+            for (int c0 = 0; c0 < kc; c0 += 8) {
+                double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / (d + 1), r = e - c * (d + 1);
-                v[u] = (e < ng) ? gram[r * nr + c] : 0.0;
-            }
+                for (int u = 0; u < 8; ++u) v[u] = gram[rg * nr + min(c0 + u, kc - 1)];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * 64 + t, c = e / (d + 1), r = e - c * (d + 1);
-                if (e < ng) X[r + c * LDG] = v[u] * Dk[c];
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + u;
+                    if (t <= d && c < kc) X[t + c * LDG] = v[u] * Dk[c];
+                }
             }
         }
         if (t < kc) G[t + t * LDG] = Dk[t];
@@ -188,7 +186,11 @@ __device__ __forceinline__ void k_dense_prep_body(const double* __restrict__ H, 
     // ---- least squares: y = R_G^{-1} rhs[0:d]
     double yv = (t < d) ? rhs[t] : 0.0;
     for (int c = d - 1; c >= 0; --c) {
-        const double yc = __shfl(yv, c, 64) / G[c + c * LDG];
+        // y_c from lane c (a uniform lane: two lane reads, no LDS round trip)
+        const unsigned long long yu = (unsigned long long)__double_as_longlong(yv);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)yu, c);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(yu >> 32), c);
+        const double yc = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) / G[c + c * LDG];
         if (t == c) yv = yc;
         if (t < c) yv = fma(-G[t + c * LDG], yc, yv);
     }
