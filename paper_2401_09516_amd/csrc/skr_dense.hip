@@ -245,7 +245,174 @@ __global__ __launch_bounds__(64) void k_dense_prep(const double* __restrict__ H,
 // not finite, M is handed to the general stage.
 constexpr int DT = 256;         // threads of the symmetric stage
 constexpr int LDS_ = DS + 1;  // leading dimension of S and V in LDS
-constexpr int NSHIFT = 8;       // multisection: shifts per eigenvalue interval and round
+constexpr int NSLOT = 2 * DT;   // multisection: Sturm counts per round (two recurrences per thread)
+
+// Sturm counts of T - sh[s] I (s = 0, 1; two interleaved recurrences): the number of negative
+// pivots D_i of its LDL^T factorization, D_i = (a_i - sh) - b_{i-1}^2 / D_{i-1}, a pivot of
+// magnitude below pivmin taken as -pivmin. The quotient uses v_rcp_f64 with two Newton steps.
+__device__ __forceinline__ void sturm2(const double* ta, const double* tb2, int d, double pivmin,
+                                       const double sh[2], int cnt[2]) {
+    double D[2];
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+        D[s4] = ta[0] - sh[s4];
+        if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+        cnt[s4] = D[s4] < 0.0;
+    }
+    for (int m0 = 1; m0 < d; m0 += 8) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int mm = min(m0 + u, d - 1);
+            av[u] = ta[mm];
+            bv[u] = tb2[mm - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (m0 + u < d) {
+#pragma unroll
+                for (int s4 = 0; s4 < 2; ++s4) {
+                    double rc = __builtin_amdgcn_rcp(D[s4]);
+                    rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                    rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
+                    D[s4] = fma(-bv[u], rc, av[u] - sh[s4]);
+                    if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
+                    cnt[s4] += D[s4] < 0.0;
+                }
+            }
+        }
+    }
+}
+
+// The eigenvalues of the symmetric tridiagonal T (diagonal ta, off-diagonal tb, squares tb2, in LDS)
+// that the eigen stage keeps: the k_target of largest magnitude (smallest |theta| = 1/|mu|), by
+// multisection with Sturm counts (count(sigma) = number of eigenvalues below sigma), DT threads.
+// * Round 0 counts at 511 points spread evenly over the widened Gershgorin interval and at 0.
+// * The wanted eigenvalues are among the candidates: the min(k_target, n_neg) lowest and the
+//   min(k_target, d - n_neg) highest, n_neg = count(0) (at most k_target can come from either
+//   end). Each candidate takes its bracket from round 0 by a binary search for the point where the
+//   count passes its index (so the bracket always holds a change of the count across the index).
+// * Every later round splits each candidate's bracket at NSLOT / ncand points until all brackets
+//   are below 2e-8 ||T||.
+// * Selection from both ends by magnitude (the eigenvalues ascend); at equal magnitude the upper
+//   one first; a zero eigenvalue (theta infinite) is never taken.
+// Returns the number selected; lsel[o] is the o-th selected eigenvalue (bracket midpoint) and
+// isel[o] the candidate slot whose bracket [blo, bhi] holds it. tnorm and pivmin are set for the
+// eigenvector stage. Every thread of the block calls it.
+__device__ __forceinline__ int multisect_select(int d, int k_target, const double* ta, const double* tb,
+                                                const double* tb2, double* blo, double* bhi, double* lam,
+                                                double* bsh, int* bcnt, int* isel, double* lsel,
+                                                double& tnorm, double& pivmin) {
+    __shared__ int nb_s, nc_s, ns_s;
+    const int t = threadIdx.x;
+    const double eps = 2.220446049250313e-16;
+    double glo = __builtin_inf(), ghi = -__builtin_inf(), bm2 = 0.0;
+    for (int i = 0; i < d; ++i) {
+        const double rad = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < d ? fabs(tb[i]) : 0.0);
+        glo = fmin(glo, ta[i] - rad);
+        ghi = fmax(ghi, ta[i] + rad);
+        if (i + 1 < d) bm2 = fmax(bm2, tb2[i]);
+    }
+    tnorm = fmax(fabs(glo), fabs(ghi));
+    pivmin = 2.2250738585072014e-308 * fmax(1.0, bm2);
+    const double widen = 2.0 * eps * tnorm * d + 2.0 * pivmin;
+    glo -= widen;
+    ghi += widen;
+    const double tol = 2e-8 * tnorm;
+    double sh[2];
+    int cnt[2];
+    // round 0: points glo + (ghi - glo) p / NSLOT (p = 1 .. NSLOT - 1) in slots 0 .. NSLOT - 2, and 0
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+        const int slot = t + DT * s4;
+        sh[s4] = (slot == NSLOT - 1) ? 0.0 : glo + (ghi - glo) * ((double)(slot + 1) / (double)NSLOT);
+    }
+    sturm2(ta, tb2, d, pivmin, sh, cnt);
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+        bsh[t + DT * s4] = sh[s4];
+        bcnt[t + DT * s4] = cnt[s4];
+    }
+    __syncthreads();
+    if (t == 0) {
+        const int nneg = bcnt[NSLOT - 1];
+        const int nb = min(k_target, nneg), nt = min(k_target, d - nneg);
+        nb_s = nb;
+        nc_s = nb + nt;
+    }
+    __syncthreads();
+    const int nb = nb_s, nc = nc_s;
+    // candidate c is eigenvalue index c (c < nb) or d - nc + c
+    int open = 0;
+    if (t < nc) {
+        const int i = t < nb ? t : d - nc + t;
+        int lo = -1, hi = NSLOT - 1;     // point lo has count <= i (-1: glo), point hi count > i (ghi)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bcnt[mid] > i) hi = mid;
+            else lo = mid;
+        }
+        const double nl = lo < 0 ? glo : bsh[lo];
+        double nh = hi == NSLOT - 1 ? ghi : bsh[hi];
+        if (nh < nl) nh = nl;
+        blo[t] = nl;
+        bhi[t] = nh;
+        open = (nh - nl) > tol;
+    }
+    // later rounds: slot -> (candidate, point); slots past ns * nc repeat the last candidate unused
+    const int ns = nc > 0 ? NSLOT / nc : 1;
+    int cs[2], ps[2];
+#pragma unroll
+    for (int s4 = 0; s4 < 2; ++s4) {
+        const int slot = t + DT * s4, c = slot / ns;
+        cs[s4] = min(c, max(nc - 1, 0));
+        ps[s4] = slot - c * ns;
+    }
+    for (int round = 0; round < 48 && __syncthreads_or(open); ++round) {
+#pragma unroll
+        for (int s4 = 0; s4 < 2; ++s4) {
+            const double lo = blo[cs[s4]];
+            sh[s4] = lo + (bhi[cs[s4]] - lo) * ((double)(ps[s4] + 1) / (double)(ns + 1));
+        }
+        sturm2(ta, tb2, d, pivmin, sh, cnt);
+#pragma unroll
+        for (int s4 = 0; s4 < 2; ++s4) {
+            bsh[t + DT * s4] = sh[s4];
+            bcnt[t + DT * s4] = cnt[s4];
+        }
+        __syncthreads();
+        open = 0;
+        if (t < nc) {
+            const int i = t < nb ? t : d - nc + t, base = t * ns;
+            int lo = -1, hi = ns;        // the bracket's ends stand for points -1 and ns
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (bcnt[base + mid] > i) hi = mid;
+                else lo = mid;
+            }
+            const double nl = lo < 0 ? blo[t] : bsh[base + lo];
+            double nh = hi == ns ? bhi[t] : bsh[base + hi];
+            if (nh < nl) nh = nl;
+            blo[t] = nl;
+            bhi[t] = nh;
+            open = (nh - nl) > tol;
+        }
+    }
+    if (t < nc) lam[t] = 0.5 * (blo[t] + bhi[t]);
+    __syncthreads();
+    if (t == 0) {
+        int lo = 0, hi = nc - 1, nsel = 0;   // lo over the lower candidates, hi over the upper ones
+        while (nsel < k_target && (lo < nb || hi >= nb)) {
+            const int pick = lo >= nb ? hi-- : (hi < nb ? lo++ : (fabs(lam[hi]) >= fabs(lam[lo]) ? hi-- : lo++));
+            if (!(fabs(lam[pick]) > 0.0)) break;
+            isel[nsel] = pick;
+            lsel[nsel++] = lam[pick];
+        }
+        ns_s = nsel;
+    }
+    __syncthreads();
+    return ns_s;
+}
 
 __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
                                                   Ctrl* ctrl) {
@@ -257,10 +424,10 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __shared__ double red[DT / 64], red2[DT / 64];
     __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS], hv0[DS];
     __shared__ double blo[DS], bhi[DS], lam[DS], lsel[KMAX];
-    __shared__ double bsh[DS * NSHIFT];
-    __shared__ int bcnt[DS * NSHIFT];
+    __shared__ double bsh[NSLOT];
+    __shared__ int bcnt[NSLOT];
     __shared__ int sel[KMAX], isel[KMAX];
-    __shared__ int nsel_s, sym_s, need2_s, fail_s;
+    __shared__ int sym_s, need2_s, fail_s;
     const int t = threadIdx.x;
     const int d = dw->d, kc = dw->kc;
     const int dp = d + (d & 1);                 // even size (a zero row/column pads an odd d)
@@ -449,109 +616,14 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     if (t < d - 1) tb2[t] = tb[t] * tb[t];
     __syncthreads();
 
-    // ---- eigenvalues of T by multisection: each round splits every interval [lo_i, hi_i] holding
-    // the i-th smallest eigenvalue at NSHIFT points (four threads per eigenvalue, two interleaved
-    // Sturm recurrences per thread); count(sigma) = number of negative pivots of T - sigma I.
-    const double eps = 2.220446049250313e-16;
+    // ---- the wanted eigenvalues of T (multisection over the candidates at both ends)
     double tnorm = 0.0, pivmin = 0.0;
-    {
-        double glo = __builtin_inf(), ghi = -__builtin_inf(), bm2 = 0.0;
-        for (int i = 0; i < d; ++i) {
-            const double rad = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < d ? fabs(tb[i]) : 0.0);
-            glo = fmin(glo, ta[i] - rad);
-            ghi = fmax(ghi, ta[i] + rad);
-            if (i + 1 < d) bm2 = fmax(bm2, tb2[i]);
-        }
-        tnorm = fmax(fabs(glo), fabs(ghi));
-        pivmin = 2.2250738585072014e-308 * fmax(1.0, bm2);
-        const double widen = 2.0 * eps * tnorm * d + 2.0 * pivmin;
-        if (t < d) { blo[t] = glo - widen; bhi[t] = ghi + widen; }
-    }
-    __syncthreads();
-    for (int round = 0; round < 48; ++round) {
-        const int i = t & 63, q = t >> 6;
-        const int ii = min(i, d - 1);
-        const double lo = blo[ii], hi = bhi[ii], wdt = hi - lo;
-        double sh[2], D[2];
-        int cnt[2];
-#pragma unroll
-        for (int s4 = 0; s4 < 2; ++s4) {
-            sh[s4] = lo + wdt * ((double)(q * 2 + s4 + 1) / (double)(NSHIFT + 1));
-            D[s4] = ta[0] - sh[s4];
-            if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
-            cnt[s4] = D[s4] < 0.0;
-        }
-        for (int m0 = 1; m0 < d; m0 += 8) {
-            double av[8], bv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int mm = min(m0 + u, d - 1);
-                av[u] = ta[mm];
-                bv[u] = tb2[mm - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (m0 + u < d) {
-#pragma unroll
-                    for (int s4 = 0; s4 < 2; ++s4) {
-                        double rc = __builtin_amdgcn_rcp(D[s4]);
-                        rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                        rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                        D[s4] = fma(-bv[u], rc, av[u] - sh[s4]);
-                        if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
-                        cnt[s4] += D[s4] < 0.0;
-                    }
-                }
-            }
-        }
-        if (i < d) {
-#pragma unroll
-            for (int s4 = 0; s4 < 2; ++s4) {
-                bsh[i * NSHIFT + q * 2 + s4] = sh[s4];
-                bcnt[i * NSHIFT + q * 2 + s4] = cnt[s4];
-            }
-        }
-        __syncthreads();
-        int open = 0;
-        if (q == 0 && i < d) {
-            double nl = lo, nh = hi, shv[NSHIFT];
-            int cv[NSHIFT];
-#pragma unroll
-            for (int p2 = 0; p2 < NSHIFT; ++p2) {
-                shv[p2] = bsh[i * NSHIFT + p2];
-                cv[p2] = bcnt[i * NSHIFT + p2];
-            }
-#pragma unroll
-            for (int p2 = 0; p2 < NSHIFT; ++p2) nl = (cv[p2] <= i) ? shv[p2] : nl;
-#pragma unroll
-            for (int p2 = NSHIFT - 1; p2 >= 0; --p2) nh = (cv[p2] > i) ? shv[p2] : nh;
-            if (nh < nl) nh = nl;
-            blo[i] = nl;
-            bhi[i] = nh;
-            open = (nh - nl) > 2e-8 * tnorm;
-        }
-        if (!__syncthreads_or(open)) break;
-    }
-    if (t < d) lam[t] = 0.5 * (blo[t] + bhi[t]);
-    __syncthreads();
-
-    // ---- the k_target eigenvalues of largest |mu| (smallest |theta| = 1/|mu|): the eigenvalues are
-    // ascending, so the largest magnitudes are taken from both ends; at equal magnitude the
-    // positive one first; zero eigenvalues (theta infinite) are never taken.
+    const int kn = multisect_select(d, k_target, ta, tb, tb2, blo, bhi, lam, bsh, bcnt, isel, lsel, tnorm, pivmin);
     if (t == 0) {
-        int lo = 0, hi = d - 1, ns = 0;
-        while (ns < k_target && lo <= hi) {
-            const int pick = (fabs(lam[hi]) >= fabs(lam[lo])) ? hi-- : lo++;
-            if (!(fabs(lam[pick]) > 0.0)) break;
-            isel[ns] = pick;
-            lsel[ns++] = lam[pick];
-        }
-        nsel_s = ns;
         need2_s = 0;
         fail_s = 0;
     }
     __syncthreads();
-    const int kn = nsel_s;
 
     // ---- eigenvectors of T (wave 0 and wave 1, lane o for selected eigenvalue o): T - lambda I =
     // L+ D+ L+^T = U- D- U-^T, twist index r = argmin |gamma_r|, gamma_r = D+_r + D-_r - (a_r - lambda),
@@ -1343,10 +1415,10 @@ __device__ __forceinline__ void k_dense_sym_L_body(int k_target, double sym_tol,
     __shared__ double red[DT / 64], red2[DT / 64];
     __shared__ double ta[MMAX], tb[MMAX], tb2[MMAX], hb[MMAX], hv0[MMAX], hP[MMAX];
     __shared__ double blo[MMAX], bhi[MMAX], lam[MMAX], lsel[KMAX], hsig[1], hkp[DT / 64];
-    __shared__ double bsh[MMAX * NSHIFT];
-    __shared__ int bcnt[MMAX * NSHIFT];
+    __shared__ double bsh[NSLOT];
+    __shared__ int bcnt[NSLOT];
     __shared__ int sel[KMAX], isel[KMAX];
-    __shared__ int nsel_s, sym_s, need2_s, fail_s;
+    __shared__ int sym_s, need2_s, fail_s;
     const int t = threadIdx.x;
     const int d = dw->d, kc = dw->kc;
     double* R = V;
@@ -1473,110 +1545,14 @@ __device__ __forceinline__ void k_dense_sym_L_body(int k_target, double sym_tol,
     if (t < d - 1) tb2[t] = tb[t] * tb[t];
     __syncthreads();
 
-    // ---- eigenvalues of T by multisection (as in k_dense_sym; the eigenvalue indices i and i + 64
-    // share a lane, and thread i narrows interval i)
-    const double eps = 2.220446049250313e-16;
+    // ---- the wanted eigenvalues of T (as in k_dense_sym)
     double tnorm = 0.0, pivmin = 0.0;
-    {
-        double glo = __builtin_inf(), ghi = -__builtin_inf(), bm2 = 0.0;
-        for (int i = 0; i < d; ++i) {
-            const double rad = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < d ? fabs(tb[i]) : 0.0);
-            glo = fmin(glo, ta[i] - rad);
-            ghi = fmax(ghi, ta[i] + rad);
-            if (i + 1 < d) bm2 = fmax(bm2, tb2[i]);
-        }
-        tnorm = fmax(fabs(glo), fabs(ghi));
-        pivmin = 2.2250738585072014e-308 * fmax(1.0, bm2);
-        const double widen = 2.0 * eps * tnorm * d + 2.0 * pivmin;
-        if (t < d) { blo[t] = glo - widen; bhi[t] = ghi + widen; }
-    }
-    __syncthreads();
-    for (int round = 0; round < 48; ++round) {
-        const int q = t >> 6;
-        for (int i0 = 0; i0 < d; i0 += 64) {
-            const int i = i0 + (t & 63);
-            const int ii = min(i, d - 1);
-            const double lo = blo[ii], wdt = bhi[ii] - lo;
-            double sh[2], D[2];
-            int cnt[2];
-#pragma unroll
-            for (int s4 = 0; s4 < 2; ++s4) {
-                sh[s4] = lo + wdt * ((double)(q * 2 + s4 + 1) / (double)(NSHIFT + 1));
-                D[s4] = ta[0] - sh[s4];
-                if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
-                cnt[s4] = D[s4] < 0.0;
-            }
-            for (int m0 = 1; m0 < d; m0 += 8) {
-                double av[8], bv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int mm = min(m0 + u, d - 1);
-                    av[u] = ta[mm];
-                    bv[u] = tb2[mm - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (m0 + u < d) {
-#pragma unroll
-                        for (int s4 = 0; s4 < 2; ++s4) {
-                            double rc = __builtin_amdgcn_rcp(D[s4]);
-                            rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                            rc = fma(rc, fma(-D[s4], rc, 1.0), rc);
-                            D[s4] = fma(-bv[u], rc, av[u] - sh[s4]);
-                            if (fabs(D[s4]) < pivmin) D[s4] = -pivmin;
-                            cnt[s4] += D[s4] < 0.0;
-                        }
-                    }
-                }
-            }
-            if (i < d) {
-#pragma unroll
-                for (int s4 = 0; s4 < 2; ++s4) {
-                    bsh[i * NSHIFT + q * 2 + s4] = sh[s4];
-                    bcnt[i * NSHIFT + q * 2 + s4] = cnt[s4];
-                }
-            }
-        }
-        __syncthreads();
-        int open = 0;
-        if (t < d) {
-            const int i = t;
-            double nl = blo[i], nh = bhi[i], shv[NSHIFT];
-            int cv[NSHIFT];
-#pragma unroll
-            for (int p2 = 0; p2 < NSHIFT; ++p2) {
-                shv[p2] = bsh[i * NSHIFT + p2];
-                cv[p2] = bcnt[i * NSHIFT + p2];
-            }
-#pragma unroll
-            for (int p2 = 0; p2 < NSHIFT; ++p2) nl = (cv[p2] <= i) ? shv[p2] : nl;
-#pragma unroll
-            for (int p2 = NSHIFT - 1; p2 >= 0; --p2) nh = (cv[p2] > i) ? shv[p2] : nh;
-            if (nh < nl) nh = nl;
-            blo[i] = nl;
-            bhi[i] = nh;
-            open = (nh - nl) > 2e-8 * tnorm;
-        }
-        if (!__syncthreads_or(open)) break;
-    }
-    if (t < d) lam[t] = 0.5 * (blo[t] + bhi[t]);
-    __syncthreads();
-
-    // ---- the k_target eigenvalues of largest |mu| (as in k_dense_sym)
+    const int kn = multisect_select(d, k_target, ta, tb, tb2, blo, bhi, lam, bsh, bcnt, isel, lsel, tnorm, pivmin);
     if (t == 0) {
-        int lo = 0, hi = d - 1, ns = 0;
-        while (ns < k_target && lo <= hi) {
-            const int pick = (fabs(lam[hi]) >= fabs(lam[lo])) ? hi-- : lo++;
-            if (!(fabs(lam[pick]) > 0.0)) break;
-            isel[ns] = pick;
-            lsel[ns++] = lam[pick];
-        }
-        nsel_s = ns;
         need2_s = 0;
         fail_s = 0;
     }
     __syncthreads();
-    const int kn = nsel_s;
 
     // ---- eigenvectors of T by twisted factorizations (as in k_dense_sym), pivots in V
     double* Fp = V;
