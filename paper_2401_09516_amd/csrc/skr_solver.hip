@@ -192,28 +192,60 @@ __device__ __forceinline__ void block_partials(double s, double* sh, double* par
 // rotation and g_{jj+1}. Only the running entry of the rotated column is needed: after rotation q
 // it is a_{q+1} = -sn_q a_q + cs_q col[q+1], run by lane 0 from LDS copies (shc, 3 x 128 doubles;
 // lane t handles the column entries t and t + 64).
-__device__ __forceinline__ double close_step(int jj, int kc, double tot, const double* __restrict__ h1,
-                                             const double* __restrict__ h2, double* H, double* Bm, Ctrl* ctrl,
+// The global inputs of close_step for lane t of the closing wave: h1 at the rows of the column and
+// of B (e = t, t + 64), ||A v||^2 = h1[ncol], the rotations stored by the earlier closings and g_jj.
+// Every one was written by an earlier kernel, so the caller loads them with its first loads, ahead
+// of the partial sums (clamped indices, unneeded entries zero).
+struct CloseIn {
+    double h1c[2], h1b[2], cs[2], sn[2], anorm2, gj;
+    __device__ __forceinline__ void load(int jj, int kc, const double* __restrict__ h1, const Ctrl* ctrl) {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int e = t + 64 * half;
+            const double a = h1[kc + min(e, jj)], b = h1[min(e, max(kc - 1, 0))];
+            const double c = ctrl->cs[min(e, max(jj - 1, 0))], d = ctrl->sn[min(e, max(jj - 1, 0))];
+            h1c[half] = e <= jj ? a : 0.0;
+            h1b[half] = e < kc ? b : 0.0;
+            cs[half] = e < jj ? c : 0.0;
+            sn[half] = e < jj ? d : 0.0;
+        }
+        anorm2 = h1[kc + jj + 1];
+        gj = ctrl->g[jj];
+    }
+};
+// h2 at the same rows (e = t, t + 64: the column's rows kc + e and B's rows e), from global memory
+// (loaded early like CloseIn) or from LDS.
+__device__ __forceinline__ void load_h2(int jj, int kc, const double* __restrict__ h2, double h2c[2], double h2b[2]) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int e = threadIdx.x + 64 * half;
+        const double a = h2[kc + min(e, jj)], b = h2[min(e, max(kc - 1, 0))];
+        h2c[half] = e <= jj ? a : 0.0;
+        h2b[half] = e < kc ? b : 0.0;
+    }
+}
+__device__ __forceinline__ double close_step(int jj, int kc, double tot, const CloseIn& ci, const double h2c[2],
+                                             const double h2b[2], double* H, double* Bm, Ctrl* ctrl,
                                              bool writer, int& brk_out, double& hnorm_out, double* shc,
                                              const double* __restrict__ g3 = nullptr) {
     const int t = threadIdx.x;
-    const int ncol = kc + jj + 1;
     const double hnorm = sqrt(tot);
-    const double anorm = sqrt(h1[ncol]);
+    const double anorm = sqrt(ci.anorm2);
     const int brk = (hnorm <= 1e-14 * anorm) ? 1 : 0;
     const double hlast = brk ? 0.0 : hnorm;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int e = t + 64 * half;
         double colt = 0.0;
-        if (e <= jj) colt = h1[kc + e] + h2[kc + e] - (g3 ? g3[kc + e] : 0.0);
+        if (e <= jj) colt = ci.h1c[half] + h2c[half] - (g3 ? g3[kc + e] : 0.0);
         if (writer) {
-            if (e < kc) Bm[e + jj * KMAX] = h1[e] + h2[e] - (g3 ? g3[e] : 0.0);
+            if (e < kc) Bm[e + jj * KMAX] = ci.h1b[half] + h2b[half] - (g3 ? g3[e] : 0.0);
             if (e <= jj) H[e + jj * LDH] = colt;
         }
         shc[e] = colt;
-        shc[128 + e] = (e < jj) ? ctrl->cs[e] : 0.0;
-        shc[256 + e] = (e < jj) ? ctrl->sn[e] : 0.0;
+        shc[128 + e] = ci.cs[half];
+        shc[256 + e] = ci.sn[half];
     }
     if (writer && t == 0) H[jj + 1 + jj * LDH] = hlast;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -226,7 +258,7 @@ __device__ __forceinline__ double close_step(int jj, int kc, double tot, const d
     a = first_lane(a);
     const double rho = hypot(a, hlast);
     const double cs = rho > 0.0 ? a / rho : 1.0, sn = rho > 0.0 ? hlast / rho : 0.0;
-    const double gj = ctrl->g[jj];
+    const double gj = ci.gj;
     const double est = fabs(sn * gj);
     if (writer && t == 0) {
         ctrl->cs[jj] = cs;
@@ -289,6 +321,12 @@ __device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict
     const double xi = src[ii];
     double wraw = 0.0;
     if constexpr (!MIX) wraw = op_row_k<KIND>(op, src, ii, 1.0);
+    CloseIn ci;
+    double h2c[2], h2b[2];
+    if (j > 0 && threadIdx.x < 64) {
+        ci.load(j - 1, kc, red1, ctrl);
+        load_h2(j - 1, kc, red2, h2c, h2b);
+    }
     if (stopped) return;
     double tot;
     if (few) {
@@ -317,7 +355,7 @@ __device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict
     } else if (threadIdx.x < 64) {
         int brk;
         double hn;
-        const double est = close_step(j - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn, sh + 64);
+        const double est = close_step(j - 1, kc, tot, ci, h2c, h2b, H, Bm, ctrl, writer, brk, hn, sh + 64);
         if (threadIdx.x == 0) {
             const int stop = (brk || !(est > ctrl->tol_abs)) ? 1 : 0;
             s_stop = stop;
@@ -567,6 +605,8 @@ __device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict
     double aw = 0.0;
     if constexpr (!LAST) aw = op_row_k<KIND>(op, wb, ii, 1.0);
     if (threadIdx.x < NC) gp[threadIdx.x] = (jj > 0 && (int)threadIdx.x < ncolp) ? gprev[threadIdx.x] : 0.0;
+    CloseIn ci;
+    if (threadIdx.x < 64) ci.load(jj, kc, red1, ctrl);
     if (st != 0 && st <= j) return;     // the cycle stopped at an earlier step
     sum_partials<64>(part_b, npb, ncolp + 1, sh, hs);
     if (threadIdx.x < NC) {
@@ -584,7 +624,9 @@ __device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict
         const double tot = fmax(hs[ncolp] - wave_sum(q2), 0.0);
         int brk;
         double hn;
-        const double est = close_step(jj, kc, tot, red1, hs, H, Bm, ctrl, writer, brk, hn, sh + 64, gp);
+        double h2c[2], h2b[2];
+        load_h2(jj, kc, hs, h2c, h2b);
+        const double est = close_step(jj, kc, tot, ci, h2c, h2b, H, Bm, ctrl, writer, brk, hn, sh + 64, gp);
         if (t == 0) {
             const int stop = (brk || !(est > ctrl->tol_abs)) ? 1 : 0;
             s_stop = stop;
@@ -709,11 +751,17 @@ __device__ __forceinline__ void k_close_basis_body(const double* __restrict__ w0
     __shared__ int s_jd, s_brk;
     const bool writer = blockIdx.x == 0;
     if (!ctrl->stop) {
+        CloseIn ci;
+        double h2c[2], h2b[2];
+        if (threadIdx.x < 64) {
+            ci.load(s_cycle - 1, kc, red1, ctrl);
+            load_h2(s_cycle - 1, kc, red2, h2c, h2b);
+        }
         const double tot = sum_partials1(part_n, npn, sh);
         if (threadIdx.x < 64) {
             int brk;
             double hn;
-            close_step(s_cycle - 1, kc, tot, red1, red2, H, Bm, ctrl, writer, brk, hn, sh + 64);
+            close_step(s_cycle - 1, kc, tot, ci, h2c, h2b, H, Bm, ctrl, writer, brk, hn, sh + 64);
             if (threadIdx.x == 0) {
                 s_jd = s_cycle;
                 s_brk = brk;
