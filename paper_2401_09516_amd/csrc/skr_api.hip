@@ -28,13 +28,15 @@ void launch_close_basis(hipStream_t, const Work&, const DevOp&, int, int);
 void launch_apply_c(hipStream_t, const Work&, const DevOp&, int);
 void launch_cycle_gram(hipStream_t, const Work&, int, int);
 void launch_cycle_dense(hipStream_t, const Work&, int, int, int);
-void launch_cycle_update(hipStream_t, const Work&, double*, int, int);
-void launch_true_residual(hipStream_t, const Work&, const DevOp&, const double*, const double*);
+void launch_cycle_update(hipStream_t, const Work&, double*, int, int, int spec_kc);
+void launch_true_residual(hipStream_t, const Work&, const DevOp&, const double*, const double*,
+                          const int* gate = nullptr);
+const int* spec_gate(const Work&);
 void launch_spmm(hipStream_t, const Work&, const DevOp&, int);
 void launch_startup_gram(hipStream_t, const Work&, int);
 void launch_chol(hipStream_t, const Work&, int, int);
 void launch_startup_apply(hipStream_t, const Work&, int, int);
-void launch_startup_project(hipStream_t, const Work&, double*, int, int);
+void launch_startup_project(hipStream_t, const Work&, double*, int, int, const int* gate = nullptr);
 void launch_spmv(hipStream_t, const DevOp&, const double*, double*);
 void launch_spmv_repeat(hipStream_t, const DevOp&, const double*, double*, int);
 void launch_sort(hipStream_t, const double*, long, long, long, double*, double*, long long*, double*);
@@ -428,6 +430,7 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     bool r_fresh = kc == 0 || !w.mixed;
     int prev_jd = 0, prev_scyc = 0;     // launch-length prediction (see the cycle loop)
     double prev_rate = 0.0;
+    bool ahead = false;                 // this cycle's opening was launched before the last read
     // A failed exit test goes on from the true residual, projected onto range(C) as at a system
     // start (App. B.1): the next cycle's v_0 must be orthogonal to C, which the cycle-end
     // eigenproblem's block structure of W^T V assumes.
@@ -451,22 +454,27 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
     // ---- Arnoldi cycles (Alg. 2)
     while (status < 0) {
         if (iters >= maxit) { status = SKR_MAXIT; break; }
+        // The opening of a cycle: the refinement residual (FP32 basis), the projection and Z = A C.
+        // After a cycle end that did not finish the solve, these were launched before the host read
+        // that cycle end (see below), so only the count is kept here.
+        const bool opened = ahead;
+        ahead = false;
         if (!r_fresh) {
             if (w.mixed) {
                 // refinement step: true FP64 residual, projected onto range(C) as at a system start
-                launch_true_residual(s, w, op, b, x);
+                if (!opened) launch_true_residual(s, w, op, b, x);
                 spmv += 1;
             }
             // x += U C^T r, r -= C C^T r (App. B.1's projection): zero in exact arithmetic; it
             // removes the rounding-level component along C that a cycle leaves in r, which would
             // otherwise persist at a fixed absolute size and, relative to the shrinking residual,
             // tilt v_0 = r/||r|| and the next C out of orthogonality
-            if (kc > 0) launch_startup_project(s, w, x, kc, 1);
+            if (kc > 0 && !opened) launch_startup_project(s, w, x, kc, 1);
             HIPLAUNCHCHK();
         }
         r_fresh = false;
         if (w.merged && kc > 0 && !z_valid) {
-            launch_apply_c(s, w, op, kc);
+            if (!opened) launch_apply_c(s, w, op, kc);
             HIPLAUNCHCHK();
             z_valid = true;
         }
@@ -509,9 +517,30 @@ static int solve_system_body(skr_ctx* ctx, const skr_op& opin, const double* b, 
         launch_cycle_dense(s, w, kc, scyc, k);
         // the new recycle size is at most k (0 when no recycle space is formed this cycle)
         const bool forms = k > 0 && (kc > 0 || scyc > k);
-        launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : 32) : 0);
+        // Look-ahead: unless the solve might end here, the next cycle's opening (for the usual k new
+        // columns) is launched behind the read of this cycle end, so that the GPU has work while the
+        // host waits for the read. The cycle-end kernel decides on the device, with the same test
+        // the host applies below, whether the next cycle starts as assumed; when it does not (the
+        // estimate met the tolerance, a breakdown, a non-finite value, fewer new columns), the
+        // opening's kernels that write x, r or the control block return at once, and the host
+        // continues as if they had not been launched (the others fill scratch that is recomputed
+        // before its next use).
+        const int kspec = forms ? k : 0;
+        const bool look = (kspec > 0 || w.mixed) && iters + scyc < maxit;
+        launch_cycle_update(s, w, x, kc, forms ? (k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : 32) : 0,
+                            look ? kspec : -1);
         HIPLAUNCHCHK();
-        if ((rc = read_ctrl(ctx))) return rc;
+        HIPCHK(hipMemcpyAsync(ctx->hctrl, w.ctrl, sizeof(CtrlHost), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->ev_ctrl, s));
+        if (look) {
+            const int* gate = spec_gate(w);
+            if (w.mixed) launch_true_residual(s, w, op, b, x, gate);
+            if (kspec > 0) launch_startup_project(s, w, x, kspec, 1, gate);
+            if (kspec > 0) launch_apply_c(s, w, op, kspec);
+            HIPLAUNCHCHK();
+        }
+        HIPCHK(hipEventSynchronize(ctx->ev_ctrl));
+        ahead = look && !hc.spec_skip;
         const int jd = hc.j_done;
         if (jd < 1 || jd > scyc) return fail(SKR_EHIP, "internal: Arnoldi cycle reported %d steps", jd);
         if (hc.route == 1) ctx->prof.eig_symmetric++;
@@ -629,6 +658,12 @@ int skr::ctx_make(int device, hipStream_t stream, skr_ctx** out, Arena* arena) {
         delete c;
         return fail(SKR_EHIP, "pinned host allocation failed");
     }
+    if (hipEventCreateWithFlags(&c->ev_ctrl, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->hctrl);
+        (void)hipHostFree(c->hkeff);
+        delete c;
+        return fail(SKR_EHIP, "event creation failed");
+    }
     c->ev_ok = true;
     for (int q = 0; q < PROF_MAXSAMP * 6; ++q)
         if (hipEventCreate(&c->ev[q]) != hipSuccess) c->ev_ok = false;
@@ -680,6 +715,7 @@ int skr_ctx_destroy(skr_ctx* ctx) {
     if (ctx->hkeff) (void)hipHostFree(ctx->hkeff);
     for (int q = 0; q < PROF_MAXSAMP * 6; ++q)
         if (ctx->ev[q]) (void)hipEventDestroy(ctx->ev[q]);
+    if (ctx->ev_ctrl) (void)hipEventDestroy(ctx->ev_ctrl);
     if (ctx->owns_arena) delete ctx->arena;
     delete ctx;
     return SKR_OK;

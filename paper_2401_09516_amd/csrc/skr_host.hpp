@@ -37,6 +37,7 @@ struct skr_ctx {
     bool owns_arena = false;            // this context created the Arena record (not the memory)
     skr::Work w;
     skr::CtrlHost* hctrl = nullptr;     // pinned
+    hipEvent_t ev_ctrl = nullptr;       // recorded after the read of a cycle end's control block
     int* hkeff = nullptr;          // pinned
     // sort scratch
     double* sortD = nullptr;

@@ -145,7 +145,8 @@ struct Ctrl {
     int nonsym;      // the operator is not exactly symmetric (CSR check at the system start;
                      // the stencil kinds are symmetric by construction)
     int route;       // eigen stage that formed the last recycle space: 1 symmetric, 2 general, 0 none
-    int pad0;
+    int spec_skip;   // set by each cycle end: nonzero when the kernels the host launched ahead of
+                     // its read of that cycle end (the next cycle's opening) must return at once
     double bnorm;    // ||b||
     double tol_abs;  // rtol * ||b||
     double beta;     // ||r|| at the start of the current cycle
@@ -159,7 +160,7 @@ struct Ctrl {
 
 // Snapshot read back by the host after a cycle.
 struct CtrlHost {
-    int stop, j_done, breakdown, kc, k_new, nonfinite, eig_fail, nonsym, route, pad0;
+    int stop, j_done, breakdown, kc, k_new, nonfinite, eig_fail, nonsym, route, spec_skip;
     double bnorm, tol_abs, beta, inv_h, est, res2;
 };
 

@@ -81,8 +81,12 @@ __device__ __forceinline__ void k_norm_finish_body(const double* __restrict__ pn
     }
 }
 #ifndef SKR_CHAINS_UNIT
+// gate (when given): the control block's spec_skip; a kernel launched ahead of the host's read of a
+// cycle end returns at once when that cycle end cleared the way for none (every thread reads the
+// same value, so the whole grid returns)
 __global__ __launch_bounds__(ROWS) void k_norm_finish(const double* __restrict__ pn, int npn, int mode, double rtol,
-                                                      int ke, Ctrl* ctrl) {
+                                                      int ke, Ctrl* ctrl, const int* __restrict__ gate) {
+    if (gate && *gate) return;
     k_norm_finish_body(pn, npn, mode, rtol, ke, ctrl);
 }
 #endif
@@ -1098,11 +1102,21 @@ __device__ __forceinline__ void k_cycle_update_body(double* __restrict__ x, doub
     block_partial1(rn2, part_n, lb, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->stop = 0;
 }
+// spec_kc >= 0: the host launches the next cycle's opening for spec_kc recycled columns before it
+// reads this cycle end; spec_skip tells those kernels whether the next cycle starts as assumed (the
+// same test the host applies to the values it reads: a finite estimate above the tolerance, no
+// breakdown, k_new == spec_kc).
 template <int KB, typename BT>
 __global__ __launch_bounds__(ROWS) void k_cycle_update(double* __restrict__ x, double* __restrict__ r,
                                                        BT* __restrict__ basis, BT* __restrict__ U,
                                                        int n, int ld, int vbase, int kc, int nblk, const Coef* coef,
-                                                       double* part_n, Ctrl* ctrl) {
+                                                       double* part_n, Ctrl* ctrl, int spec_kc) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double est = ctrl->est;
+        const bool go = spec_kc >= 0 && ctrl->k_new == spec_kc && !ctrl->breakdown && isfinite(est) &&
+                        est > ctrl->tol_abs;
+        ctrl->spec_skip = go ? 0 : 1;
+    }
     k_cycle_update_body<KB, BT>(x, r, basis, U, n, ld, vbase, kc, nblk, coef, part_n, ctrl);
 }
 
@@ -1127,7 +1141,8 @@ __device__ __forceinline__ void k_true_residual_body(DevOp op, const double* __r
 #ifndef SKR_CHAINS_UNIT
 __global__ __launch_bounds__(ROWS) void k_true_residual(DevOp op, const double* __restrict__ b,
                                                         const double* __restrict__ x, double* __restrict__ r,
-                                                        int nblk, double* part_n) {
+                                                        int nblk, double* part_n, const int* __restrict__ gate) {
+    if (gate && *gate) return;
     k_true_residual_body(op, b, x, r, nblk, part_n);
 }
 #endif
@@ -1354,7 +1369,9 @@ template <typename BT>
 __global__ __launch_bounds__(ROWS) void k_startup_project(double* __restrict__ x, double* __restrict__ r,
                                                           const BT* __restrict__ C, const BT* __restrict__ U,
                                                           int n, int ld, int nblk, int ke, int add_x,
-                                                          const double* __restrict__ cvec, double* part_n) {
+                                                          const double* __restrict__ cvec, double* part_n,
+                                                          const int* __restrict__ gate) {
+    if (gate && *gate) return;
     k_startup_project_body<BT>(x, r, C, U, n, ld, nblk, ke, add_x, cvec, part_n);
 }
 
@@ -1468,8 +1485,12 @@ void launch_fold_n(hipStream_t s, const Work& w) {
     if (w.fold) hipLaunchKernelGGL(k_fold1, dim3(NFOLD), dim3(ROWS), 0, s, (const double*)w.part_n, w.nblk, w.fold_n);
 }
 
-static void launch_norm_finish(hipStream_t s, const Work& w, int mode, double rtol, int ke) {
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(ROWS), 0, s, pn_src(w), pn_cnt(w), mode, rtol, ke, w.ctrl);
+static void launch_norm_finish(hipStream_t s, const Work& w, int mode, double rtol, int ke,
+                               const int* gate = nullptr) {
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(ROWS), 0, s, pn_src(w), pn_cnt(w), mode, rtol, ke, w.ctrl, gate);
+}
+const int* spec_gate(const Work& w) {
+    return reinterpret_cast<const int*>(reinterpret_cast<const char*>(w.ctrl) + offsetof(Ctrl, spec_skip));
 }
 void launch_init(hipStream_t s, const Work& w, const double* b, double* x, double rtol) {
     hipLaunchKernelGGL(k_init, dim3(w.nblk), dim3(ROWS), 0, s, b, x, w.r, w.n, w.nblk, w.part_n);
@@ -1735,10 +1756,10 @@ void launch_cycle_gram(hipStream_t s, const Work& w, int kc, int jd_max) {
         launch_gram_r(s, w, L, nl, w.gram + kc, kc + 1);
     }
 }
-void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_bucket) {
+void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_bucket, int spec_kc) {
 #define SKR_UPD(KB, BT)                                                                                      \
     hipLaunchKernelGGL((k_cycle_update<KB, BT>), dim3(w.nblk), dim3(ROWS), 0, s, x, w.r, bas<BT>(w), ucols<BT>(w), \
-                       w.n, w.ld, w.k, kc, w.nblk, (const Coef*)w.coef, w.part_n, w.ctrl)
+                       w.n, w.ld, w.k, kc, w.nblk, (const Coef*)w.coef, w.part_n, w.ctrl, spec_kc)
 #define SKR_UPD_K(BT)                           \
     switch (k_bucket) {                         \
         case 0: SKR_UPD(0, BT); break;          \
@@ -1757,10 +1778,11 @@ void launch_cycle_update(hipStream_t s, const Work& w, double* x, int kc, int k_
 #undef SKR_UPD
     launch_fold_n(s, w);
 }
-void launch_true_residual(hipStream_t s, const Work& w, const DevOp& op, const double* b, const double* x) {
-    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n);
+void launch_true_residual(hipStream_t s, const Work& w, const DevOp& op, const double* b, const double* x,
+                          const int* gate) {
+    hipLaunchKernelGGL(k_true_residual, dim3(w.nblk), dim3(ROWS), 0, s, op, b, x, w.r, w.nblk, w.part_n, gate);
     launch_fold_n(s, w);
-    launch_norm_finish(s, w, FIN_TRUE_RES, 0.0, 0);
+    launch_norm_finish(s, w, FIN_TRUE_RES, 0.0, 0, gate);
 }
 void launch_spmm(hipStream_t s, const Work& w, const DevOp& op, int kin) {
     if (w.mixed)
@@ -1783,19 +1805,21 @@ void launch_startup_apply(hipStream_t s, const Work& w, int use_keep, int second
                            ucols<double>(w), w.n, w.ld, (const Coef*)w.coef, use_keep, second);
 }
 // c = C^T r (ke columns, on the matrix cores), then x = x0 + U c, r -= C c and ||r||.
-void launch_startup_project(hipStream_t s, const Work& w, double* x, int ke, int add_x) {
+// gate: see k_norm_finish (the Gram product before it only fills scratch that every later use
+// recomputes first)
+void launch_startup_project(hipStream_t s, const Work& w, double* x, int ke, int add_x, const int* gate) {
     ColList L = {{bcol(w, 0), nullptr, nullptr, nullptr}, {ke, 0, 0, 0}};
     launch_gram_r(s, w, L, ke, w.red1, 1);
     if (w.mixed)
         hipLaunchKernelGGL(k_startup_project<float>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r,
                            (const float*)bas<float>(w), (const float*)ucols<float>(w), w.n, w.ld, w.nblk, ke, add_x,
-                           (const double*)w.red1, w.part_n);
+                           (const double*)w.red1, w.part_n, gate);
     else
         hipLaunchKernelGGL(k_startup_project<double>, dim3(w.nblk), dim3(ROWS), 0, s, x, w.r,
                            (const double*)bas<double>(w), (const double*)ucols<double>(w), w.n, w.ld, w.nblk, ke,
-                           add_x, (const double*)w.red1, w.part_n);
+                           add_x, (const double*)w.red1, w.part_n, gate);
     launch_fold_n(s, w);
-    launch_norm_finish(s, w, FIN_PROJECT, 0.0, ke);
+    launch_norm_finish(s, w, FIN_PROJECT, 0.0, ke, gate);
 }
 void launch_spmv(hipStream_t s, const DevOp& op, const double* x, double* y) {
     hipLaunchKernelGGL(k_spmv, dim3(blocks_for(op.n)), dim3(ROWS), 0, s, op, x, y);
