@@ -571,7 +571,6 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                 const double kp = wave_sum64((r >= j1 && r < d) ? pr * vr : 0.0);
                 const double K = 0.5 * beta * kp;
                 const double wr = fma(-K, vr, pr);
-                const bool rin = r >= j1 && r < d;
                 // w at this thread's columns: each wave passes its own copy of w through LDS (the
                 // reads of one column are a broadcast)
                 wsh[wv][r] = wr;
@@ -581,12 +580,12 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                 double wcv[16];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) wcv[u] = wsh[wv][min(wv + 4 * u, 63)];
+                // every entry is updated: those outside the trailing block (row or column < j1, or
+                // padding) are never read again except as factors of an exact zero of v, and stay
+                // finite, so they change no value that is used (a select per entry cost more than
+                // the update itself)
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int c = wv + 4 * u;
-                    const double nv = s[u] - __dadd_rn(__dmul_rn(vr, wcv[u]), __dmul_rn(wr, vc[u]));
-                    s[u] = (rin && c >= j1 && c < d) ? nv : s[u];
-                }
+                for (int u = 0; u < 16; ++u) s[u] = s[u] - __dadd_rn(__dmul_rn(vr, wcv[u]), __dmul_rn(wr, vc[u]));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
