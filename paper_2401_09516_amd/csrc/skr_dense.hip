@@ -178,8 +178,7 @@ __device__ __forceinline__ void k_dense_prep_body(const double* __restrict__ H, 
             gcs[c] = cs;
             gsn[c] = sn;
         }
-        __syncthreads();
-        if (t == 0) G[c + 1 + c * LDG] = 0.0;
+        // G[c + 1, c] is left at its rounding-level value: only the upper triangle is read after this
         __syncthreads();
     }
 
@@ -422,7 +421,7 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __shared__ double R[LDS_ * DS];
     __shared__ double gcs[DS], gsn[DS], Dk[KMAX], Rd[DS];
     __shared__ double red[DT / 64], red2[DT / 64];
-    __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS], hv0[DS];
+    __shared__ double ta[DS], tb[DS], tb2[DS], hb[DS];
     __shared__ double blo[DS], bhi[DS], lam[DS], lsel[KMAX];
     __shared__ double bsh[NSLOT];
     __shared__ int bcnt[NSLOT];
@@ -517,8 +516,8 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     __syncthreads();
 
     // ---- Householder tridiagonalization. Step j maps x = S[j+1:d, j] to alpha e_1 with
-    // H_j = I - beta v v^T, v = x - alpha e_1: the first entry of v is kept in hv0[j], the others in
-    // S[j+2:d, j] (LDS, for the back-transformation). The trailing matrix lives in registers: thread
+    // H_j = I - beta v v^T, v = x - alpha e_1 (zero above row j + 1): v is kept whole in column j of
+    // S (LDS, for the back-transformation). The trailing matrix lives in registers: thread
     // t holds row r = t % 64 at the columns c = t / 64 + 4u (u < 16). Step j: the wave holding column
     // j forms the reflector and publishes v (double-buffered); every thread adds its part of
     // p = beta S' v; every wave then sums the four parts of its rows in the same order, so all waves
@@ -550,9 +549,10 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
                     alpha = (xh >= 0.0) ? -mu : mu;
                     beta = 2.0 / fma(v0, v0, sig);
                 }
-                hvb[buf][r] = (r == j1) ? v0 : ((r > j1 && r < d) ? x : 0.0);
-                if (r > j1 && r < d) S[r + j * LDS_] = x;
-                if (r == 0) { ta[j] = diag; tb[j] = alpha; hb[j] = beta; hv0[j] = v0; hbeta[buf] = beta; }
+                const double vrow = (r == j1) ? v0 : ((r > j1 && r < d) ? x : 0.0);
+                hvb[buf][r] = vrow;
+                if (r < LDS_) S[r + j * LDS_] = vrow;      // the whole reflector, for the back-transformation
+                if (r == 0) { ta[j] = diag; tb[j] = alpha; hb[j] = beta; hbeta[buf] = beta; }
             }
             __syncthreads();
             const double beta = hbeta[buf];
@@ -727,15 +727,9 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     for (int j = d - 3; j >= 0; --j) {
         const double beta = hb[j];
         if (beta == 0.0) continue;
-        const double v0 = hv0[j];
-        double vr[8];
+        double vr[8];     // column j of S holds the whole reflector (zero outside rows j+1 .. d-1)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int r = part + 8 * i;
-            const double sv = S[min(r, d - 1) + j * LDS_];
-            const double m1 = (r > j + 1 && r < d) ? 1.0 : 0.0, m0 = (r == j + 1) ? 1.0 : 0.0;
-            vr[i] = fma(m1, sv, m0 * v0);
-        }
+        for (int i = 0; i < 8; ++i) vr[i] = S[min(part + 8 * i, LDS_ - 1) + j * LDS_];
         double dt0 = 0.0, dt1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; i += 2) { dt0 = fma(vr[i], zr[i], dt0); dt1 = fma(vr[i + 1], zr[i + 1], dt1); }
@@ -1340,8 +1334,7 @@ __device__ __forceinline__ void k_dense_prep_L_body(const double* __restrict__ H
             gcs[c] = cs;
             gsn[c] = sn;
         }
-        __syncthreads();
-        if (t == 0) G[c + 1 + c * LDP] = 0.0;
+        // G[c + 1, c] is left at its rounding-level value: only the upper triangle is read after this
         __syncthreads();
     }
 

@@ -990,6 +990,35 @@ __device__ __forceinline__ void k_cycle_update_body(double* __restrict__ x, doub
     const int nv = jd + (brk ? 0 : 1);     // V columns of W-hat (v_{jd} is zero after a breakdown)
     const int ncl = 2 * kc + nv;           // input columns: C (kc), U (kc), V (nv)
     const int nks = (ncl + 3) / 4;         // column steps
+    const int w = wave_id(), l = lane_id();
+    const int lrow = l & 15, lk = l >> 4;
+    const int lb = logical_block(blockIdx.x, nblk);
+    const int wrow0 = lb * ROWS + w * 16 * RT;               // first row of this wave
+    auto colp = [&](int q) {
+        return q < kc ? basis + (size_t)q * ld
+                      : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
+    };
+    // The first operand batch, and x or r at the rows of the lanes that update them (outputs 2 KB and
+    // 2 KB + 1), are loaded before W is gathered, so that their latency overlaps the gather's.
+    double av[KSB][RT];
+    auto fetch = [&](int ks0) {
+#pragma unroll
+        for (int u = 0; u < KSB; ++u) {
+            const BT* cp = colp(min(4 * (ks0 + u) + lk, ncl - 1));
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) av[u][rt] = (double)cp[min(wrow0 + 16 * rt + lrow, n - 1)];
+        }
+    };
+    fetch(0);
+    const bool ownx = lrow == (2 * KB) % 16, ownr = lrow == (2 * KB + 1) % 16;
+    double xr0[RT][4];
+    if (ownx || ownr) {
+        const double* src = ownx ? x : r;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int t2 = 0; t2 < 4; ++t2) xr0[rt][t2] = src[min(wrow0 + 16 * rt + 4 * t2 + lk, n - 1)];
+    }
     const double* cf = reinterpret_cast<const double*>(coef);
     for (int e0 = 0; e0 < nks * 4 * NP; e0 += 8 * ROWS) {
         double v[8];
@@ -1027,29 +1056,11 @@ __device__ __forceinline__ void k_cycle_update_body(double* __restrict__ x, doub
         }
     }
     __syncthreads();
-    const int w = wave_id(), l = lane_id();
-    const int lrow = l & 15, lk = l >> 4;
-    const int lb = logical_block(blockIdx.x, nblk);
-    const int wrow0 = lb * ROWS + w * 16 * RT;               // first row of this wave
-    auto colp = [&](int q) {
-        return q < kc ? basis + (size_t)q * ld
-                      : (q < 2 * kc ? U + (size_t)(q - kc) * ld : basis + (size_t)(vbase + q - 2 * kc) * ld);
-    };
     skr_d4u acc[RT][NTN];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int nt = 0; nt < NTN; ++nt) acc[rt][nt] = skr_d4u{0.0, 0.0, 0.0, 0.0};
-    double av[KSB][RT];
-    auto fetch = [&](int ks0) {
-#pragma unroll
-        for (int u = 0; u < KSB; ++u) {
-            const BT* cp = colp(min(4 * (ks0 + u) + lk, ncl - 1));
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) av[u][rt] = (double)cp[min(wrow0 + 16 * rt + lrow, n - 1)];
-        }
-    };
-    fetch(0);
     for (int ks0 = 0; ks0 < nks; ks0 += KSB) {
         double ac[KSB][RT];
 #pragma unroll
@@ -1089,9 +1100,9 @@ __device__ __forceinline__ void k_cycle_update_body(double* __restrict__ x, doub
                     } else if (o < 2 * KB) {
                         if (o - KB < kn) U[(size_t)(o - KB) * ld + row] = (BT)val;
                     } else if (o == 2 * KB) {
-                        x[row] += val;
+                        x[row] = xr0[rt][t2] + val;
                     } else if (o == 2 * KB + 1) {
-                        const double rn = r[row] + val;
+                        const double rn = xr0[rt][t2] + val;
                         r[row] = rn;
                         rn2 = fma(rn, rn, rn2);
                     }
