@@ -174,16 +174,18 @@ __device__ __forceinline__ size_t qoff(int c, int kc, int vbase, int ld) {
 }
 
 // Block-combine NR column values (one reduce-scattered value per lane) into the per-workgroup
-// partial part[lb * NC + OFF + c], c < NR. sh: NWAVE * NR doubles of its own.
+// partial part[lb * NC + OFF + c], c < NR; columns past cmax are written as zero (so a caller can
+// leave products of no meaning in them instead of selecting zero per lane and column). sh:
+// NWAVE * NR doubles of its own.
 template <int NR, int OFF = 0>
-__device__ __forceinline__ void block_partials(double s, double* sh, double* part, int lb) {
+__device__ __forceinline__ void block_partials(double s, double* sh, double* part, int lb, int cmax = NC + 64) {
     if (lane_id() < NR) sh[wave_id() * NR + lane_id()] = s;
     __syncthreads();
     if (threadIdx.x < NR) {
         double t = sh[threadIdx.x];
 #pragma unroll
         for (int q = 1; q < NWAVE; ++q) t += sh[q * NR + threadIdx.x];
-        part[lb * NC + OFF + threadIdx.x] = t;
+        part[lb * NC + OFF + threadIdx.x] = (OFF + (int)threadIdx.x <= cmax) ? t : 0.0;
     }
 }
 
@@ -391,9 +393,11 @@ __device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict
     } else {
         w = 0.0;
     }
+    // columns past ncol hold products of no meaning (the clamped basis loads); the block sums write
+    // them as zero
     auto col_val = [&](int c) {
         const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-        return (c < nst) ? qc * w : (c == nst ? vj * w : (c == ncol ? w * w : 0.0));
+        return (c == nst) ? vj * w : (c == ncol ? w * w : qc * w);
     };
     double acc[NR];
 #pragma unroll
@@ -404,9 +408,9 @@ __device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict
 #pragma unroll
         for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
         const double s2 = wave_reduce_scatter<NR2>(acc2);
-        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb);
+        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb, ncol);
     }
-    block_partials<NR>(s, sh, part_a, lb);
+    block_partials<NR>(s, sh, part_a, lb, ncol);
 }
 template <int NL, int KIND, typename BT>
 __global__ __launch_bounds__(ROWS) void k_step_a(DevOp op, const double* __restrict__ src,
@@ -434,7 +438,7 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
     constexpr int NR = Width<NL>::NR, NR2 = Width<NL>::NR2;
     __shared__ double sh[NWAVE * NC];
     __shared__ double hs[NC];
-    __shared__ double hz[NORM ? 1 : NC];
+    __shared__ double hz[NC];
     const int ncol = kc + j + 1;
     const int lb = logical_block(blockIdx.x, nblk);
     const int i = lb * ROWS + threadIdx.x;
@@ -449,13 +453,17 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
     if (stopped) return;
     if (blockIdx.x == 0 && threadIdx.x <= ncol) red1[threadIdx.x] = hs[threadIdx.x];
     if constexpr (NORM) {
+        // h1 padded with zeros past ncol (no per-column select); the products past ncol have no
+        // meaning and the block sums write them as zero
+        if (threadIdx.x < NC) hz[threadIdx.x] = threadIdx.x < ncol ? hs[threadIdx.x] : 0.0;
+        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < NL; ++c) w = fma(-q[c], c < ncol ? hs[c] : 0.0, w);
+        for (int c = 0; c < NL; ++c) w = fma(-q[c], hz[c], w);
         if (valid) w_io[i] = w;
         else w = 0.0;
         auto col_val = [&](int c) {
-            const double qw = (c < NL && c < ncol) ? q[c < NL ? c : 0] * w : 0.0;
-            return (c == ncol) ? w * w : qw;
+            const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
+            return (c == ncol) ? w * w : qc * w;
         };
         double acc[NR];
 #pragma unroll
@@ -466,9 +474,9 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
 #pragma unroll
             for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
             const double s2 = wave_reduce_scatter<NR2>(acc2);
-            block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb);
+            block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb, ncol);
         }
-        block_partials<NR>(s, sh, part_b, lb);
+        block_partials<NR>(s, sh, part_b, lb, ncol);
     } else {
         if (threadIdx.x < NC) hz[threadIdx.x] = threadIdx.x < ncol ? hs[threadIdx.x] : 0.0;
         __syncthreads();
@@ -680,9 +688,10 @@ __device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict
     double w = (aw - corr) * scale;
     if (valid) dst[i] = w;
     else w = 0.0;
+    // columns past ncol hold products of no meaning; the block sums write them as zero
     auto col_val = [&](int c) {
         const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-        return (c < ncolp) ? qc * w : (c == ncolp ? vj * w : (c == ncol ? w * w : 0.0));
+        return (c == ncolp) ? vj * w : (c == ncol ? w * w : qc * w);
     };
     double acc[NR];
 #pragma unroll
@@ -693,9 +702,9 @@ __device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict
 #pragma unroll
         for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
         const double s2 = wave_reduce_scatter<NR2>(acc2);
-        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb);
+        block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb, ncol);
     }
-    block_partials<NR>(s, sh, part_a, lb);
+    block_partials<NR>(s, sh, part_a, lb, ncol);
     if (!writer) return;
     __syncthreads();
     // g / h for the closing of step j: row t < kc is (B h2_V)_t, row kc + e is (Hbar h2_V)_e, e <= j.
