@@ -393,21 +393,23 @@ __device__ __forceinline__ void k_step_a_body(DevOp op, const double* __restrict
     } else {
         w = 0.0;
     }
-    // columns past ncol hold products of no meaning (the clamped basis loads); the block sums write
-    // them as zero
-    auto col_val = [&](int c) {
-        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-        return (c == nst) ? vj * w : (c == ncol ? w * w : qc * w);
-    };
+    // Column products q_c w for every column (no per-column select); the columns of v_j and of
+    // ||w||^2 sit at runtime positions, so their sums come from wave sums, which pair the lanes in
+    // the reduce-scatter's order (the same bits), and replace the sum of the lane that holds each.
+    // Columns past ncol hold products of no meaning; the block sums write them as zero.
+    const double vw = wave_sum(vj * w), ww = wave_sum(w * w);
+    const int lane = lane_id();
     double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
-    const double s = wave_reduce_scatter<NR>(acc);
+    for (int c = 0; c < NR; ++c) acc[c] = (c < NL) ? q[c < NL ? c : 0] * w : 0.0;
+    double s = wave_reduce_scatter<NR>(acc);
+    s = (lane == nst) ? vw : ((lane == ncol) ? ww : s);
     if constexpr (NR2 > 0) {
         double acc2[NR2];
 #pragma unroll
-        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
-        const double s2 = wave_reduce_scatter<NR2>(acc2);
+        for (int c = 0; c < NR2; ++c) acc2[c] = (64 + c < NL) ? q[64 + c < NL ? 64 + c : 0] * w : 0.0;
+        double s2 = wave_reduce_scatter<NR2>(acc2);
+        s2 = (lane + 64 == nst) ? vw : ((lane + 64 == ncol) ? ww : s2);
         block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb, ncol);
     }
     block_partials<NR>(s, sh, part_a, lb, ncol);
@@ -461,19 +463,21 @@ __device__ __forceinline__ void k_step_b_body(double* __restrict__ w_io, const B
         for (int c = 0; c < NL; ++c) w = fma(-q[c], hz[c], w);
         if (valid) w_io[i] = w;
         else w = 0.0;
-        auto col_val = [&](int c) {
-            const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-            return (c == ncol) ? w * w : qc * w;
-        };
+        // ||w||^2 from a wave sum (the reduce-scatter's lane pairing, so the same bits) in the lane
+        // of column ncol, as in pass A
+        const double ww = wave_sum(w * w);
+        const int lane = lane_id();
         double acc[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
-        const double s = wave_reduce_scatter<NR>(acc);
+        for (int c = 0; c < NR; ++c) acc[c] = (c < NL) ? q[c < NL ? c : 0] * w : 0.0;
+        double s = wave_reduce_scatter<NR>(acc);
+        s = (lane == ncol) ? ww : s;
         if constexpr (NR2 > 0) {
             double acc2[NR2];
 #pragma unroll
-            for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
-            const double s2 = wave_reduce_scatter<NR2>(acc2);
+            for (int c = 0; c < NR2; ++c) acc2[c] = (64 + c < NL) ? q[64 + c < NL ? 64 + c : 0] * w : 0.0;
+            double s2 = wave_reduce_scatter<NR2>(acc2);
+            s2 = (lane + 64 == ncol) ? ww : s2;
             block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_b, lb, ncol);
         }
         block_partials<NR>(s, sh, part_b, lb, ncol);
@@ -688,20 +692,19 @@ __device__ __forceinline__ void k_step_m_body(DevOp op, const double* __restrict
     double w = (aw - corr) * scale;
     if (valid) dst[i] = w;
     else w = 0.0;
-    // columns past ncol hold products of no meaning; the block sums write them as zero
-    auto col_val = [&](int c) {
-        const double qc = (c < NL) ? q[c < NL ? c : 0] : 0.0;
-        return (c == ncolp) ? vj * w : (c == ncol ? w * w : qc * w);
-    };
+    // column products without per-column selects; v_j w and ||w||^2 from wave sums, as in pass A
+    const double vw = wave_sum(vj * w), ww = wave_sum(w * w);
     double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = col_val(c);
-    const double s = wave_reduce_scatter<NR>(acc);
+    for (int c = 0; c < NR; ++c) acc[c] = (c < NL) ? q[c < NL ? c : 0] * w : 0.0;
+    double s = wave_reduce_scatter<NR>(acc);
+    s = (lane == ncolp) ? vw : ((lane == ncol) ? ww : s);
     if constexpr (NR2 > 0) {
         double acc2[NR2];
 #pragma unroll
-        for (int c = 0; c < NR2; ++c) acc2[c] = col_val(64 + c);
-        const double s2 = wave_reduce_scatter<NR2>(acc2);
+        for (int c = 0; c < NR2; ++c) acc2[c] = (64 + c < NL) ? q[64 + c < NL ? 64 + c : 0] * w : 0.0;
+        double s2 = wave_reduce_scatter<NR2>(acc2);
+        s2 = (lane + 64 == ncolp) ? vw : ((lane + 64 == ncol) ? ww : s2);
         block_partials<NR2, 64>(s2, sh + NWAVE * 64, part_a, lb, ncol);
     }
     block_partials<NR>(s, sh, part_a, lb, ncol);
