@@ -411,8 +411,16 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblk, int n
         if (col < nr) {
             for (int b = b0; b < b1; b += BATCH) {
                 double v[BATCH];
+                if (b + BATCH <= b1) {
+                    // a full batch (wave-uniform test): one row pointer and constant offsets, no
+                    // per-load guard (a guarded load compiles into an exec-mask branch of its own)
+                    const double* pb = part + (size_t)b * NC + (unsigned)col;
 #pragma unroll
-                for (int u = 0; u < BATCH; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + col] : 0.0;
+                    for (int u = 0; u < BATCH; ++u) v[u] = pb[u * NC];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < BATCH; ++u) v[u] = (b + u < b1) ? part[(b + u) * NC + col] : 0.0;
+                }
 #pragma unroll
                 for (int u = 0; u < BATCH; ++u) s += v[u];
             }
