@@ -413,6 +413,39 @@ __device__ __forceinline__ int multisect_select(int d, int k_target, const doubl
     return ns_s;
 }
 
+// Entries S0.. (at most 32 of them) of row C of R, read ahead of their FMAs into acc (one row of M
+// in registers): acc[s] -= m_C R[C, s]. The scheduling barrier keeps the reads together, so that
+// they stream through LDS while the FMAs consume them.
+template <int C, int S0>
+__device__ __forceinline__ void msolve_chunk(double (&acc)[DS], const double* R, double mc) {
+    if constexpr (S0 < DS) {
+        constexpr int N = (DS - S0) < 32 ? (DS - S0) : 32;
+        double rv[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) rv[u] = R[C + (S0 + u) * LDS_];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < N; ++u) acc[S0 + u] = fma(-mc, rv[u], acc[S0 + u]);
+        __builtin_amdgcn_sched_barrier(0);
+        msolve_chunk<C, S0 + N>(acc, R, mc);
+    }
+}
+// Column C of the forward substitution m R = x'' for one row held in registers (acc): m_C is the
+// product of acc[C] with the reciprocal of R[C, C], then every later entry s takes -m_C R[C, s] as
+// one FMA, in increasing C. The column index is a template parameter so that every index into acc
+// is a constant.
+template <int C>
+__device__ __forceinline__ void msolve_col(double (&acc)[DS], const double* R, const double* Rd, int d) {
+    if constexpr (C < DS) {
+        if (C < d) {
+            const double mc = acc[C] * Rd[C];
+            acc[C] = mc;
+            msolve_chunk<C, C + 1>(acc, R, mc);
+            msolve_col<C + 1>(acc, R, Rd, d);
+        }
+    }
+}
+
 __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, Coef* coef, DenseWork* dw,
                                                   Ctrl* ctrl) {
     if (dw->mode != DW_PENDING) return;
@@ -436,45 +469,28 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
     if (t < d) { gcs[t] = dw->gcs[t]; gsn[t] = dw->gsn[t]; }
     if (t < kc) Dk[t] = dw->Dk[t];
     __syncthreads();
-    // M = X'' R^{-1}: row r of M solves m R = x'' (forward over the columns, right-looking). Four
-    // lanes per row, lane part p holding columns 16p..16p+15 in registers; m_c is broadcast from
-    // the lane that owns column c. The diagonal of R is kept as its reciprocals Rd and zeroed in LDS
-    // (the strict lower triangle is zero), so that the update of column c by m_c R[c, :] needs no
-    // mask: it leaves the columns up to c unchanged.
+    // M = X'' R^{-1}: row r of M solves m R = x'' by forward substitution over the columns. The rows
+    // are independent: one lane per row (d <= 62 rows, wave 0) keeps its whole row in registers, and
+    // row c of R reaches every lane as an LDS broadcast, so no value moves between lanes. Entry s
+    // takes the terms m_c R[c, s] for c < s in increasing c, one FMA each, and m_s is the product of
+    // the result with the reciprocal of R[s, s]. Columns past d compute on padding and are not
+    // stored. The diagonal of R is then zeroed in LDS for the triangular solve of the Qu formation.
     if (t < d) Rd[t] = 1.0 / R[t + t * LDS_];
     __syncthreads();
-    if (t < d) R[t + t * LDS_] = 0.0;
-    __syncthreads();
-    {
-        const int r = t >> 2, p = t & 3;
-        const int rr = min(r, d - 1);
-        double acc[16];
+    if (t < 64) {
+        const int rr = min(t, d - 1);
+        double acc[DS];
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) acc[s2] = S[rr + min(16 * p + s2, d - 1) * LDS_];
-        for (int c0 = 0; c0 < d; c0 += 16) {
-            const int owner = c0 >> 4;
+        for (int s2 = 0; s2 < DS; ++s2) acc[s2] = S[rr + min(s2, d - 1) * LDS_];
+        msolve_col<0>(acc, R, Rd, d);
+        if (t < d) {
 #pragma unroll
-            for (int s1 = 0; s1 < 16; ++s1) {
-                const int c = c0 + s1;
-                if (c < d) {
-                    double rc[16];
-#pragma unroll
-                    for (int s2 = 0; s2 < 16; ++s2) rc[s2] = R[c + (16 * p + s2) * LDS_];
-                    const double ml = acc[s1] * Rd[c];
-                    acc[s1] = (p == owner) ? ml : acc[s1];
-                    const double mc = __shfl(ml, (t & ~3) | owner, 64);
-#pragma unroll
-                    for (int s2 = 0; s2 < 16; ++s2) acc[s2] = fma(-mc, rc[s2], acc[s2]);
-                }
-            }
-        }
-        __syncthreads();
-        if (r < d) {
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2)
-                if (16 * p + s2 < d) S[r + (16 * p + s2) * LDS_] = acc[s2];
+            for (int s2 = 0; s2 < DS; ++s2)
+                if (s2 < d) S[t + s2 * LDS_] = acc[s2];
         }
     }
+    __syncthreads();
+    if (t < d) R[t + t * LDS_] = 0.0;
     __syncthreads();
     // symmetry test: max |M - M^T| <= sym_tol max |M|
     double amax = 0.0, dmax = 0.0;
