@@ -413,35 +413,43 @@ __device__ __forceinline__ int multisect_select(int d, int k_target, const doubl
     return ns_s;
 }
 
-// Entries S0.. (at most 32 of them) of row C of R, read ahead of their FMAs into acc (one row of M
-// in registers): acc[s] -= m_C R[C, s]. The scheduling barrier keeps the reads together, so that
-// they stream through LDS while the FMAs consume them.
-template <int C, int S0>
-__device__ __forceinline__ void msolve_chunk(double (&acc)[DS], const double* R, double mc) {
-    if constexpr (S0 < DS) {
-        constexpr int N = (DS - S0) < 32 ? (DS - S0) : 32;
-        double rv[N];
+// Forward substitution m R = x'' for one row of M held in registers (acc), over chunks of at most
+// 16 entries of the rows of R: chunk (C, S0) holds R[C, S0 .. S0 + N - 1]. Column C sets m_C to
+// the product of acc[C] with the reciprocal of R[C, C]; every later entry s then takes
+// -m_C R[C, s] as one FMA, in increasing C. The chunk after this one (the next chunk of row C, or
+// the first of row C + 1 with its reciprocal) is read from LDS before this chunk's FMAs, and
+// scheduling barriers keep that order, so the reads overlap the arithmetic. Template parameters
+// make every index into acc a constant.
+template <int S0>
+constexpr int mchunk_n() { return (DS - S0) < 16 ? (DS - S0) : 16; }
+template <int C, int S0, int N>
+__device__ __forceinline__ void msolve_chunk(double (&acc)[DS], const double* R, const double* Rd, int d,
+                                             double mc, const double (&cur)[N]) {
+    constexpr bool row_end = S0 + N >= DS;
+    constexpr int NC = row_end ? C + 1 : C;
+    constexpr int NS0 = row_end ? C + 2 : S0 + N;
+    constexpr bool more = NS0 < DS;
+    constexpr int NN = more ? mchunk_n<NS0>() : 1;
+    double nxt[NN];
+    double rdn = 0.0;
+    if constexpr (more) {
 #pragma unroll
-        for (int u = 0; u < N; ++u) rv[u] = R[C + (S0 + u) * LDS_];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < N; ++u) acc[S0 + u] = fma(-mc, rv[u], acc[S0 + u]);
-        __builtin_amdgcn_sched_barrier(0);
-        msolve_chunk<C, S0 + N>(acc, R, mc);
+        for (int u = 0; u < NN; ++u) nxt[u] = R[NC + (NS0 + u) * LDS_];
+        if constexpr (row_end) rdn = Rd[NC];
     }
-}
-// Column C of the forward substitution m R = x'' for one row held in registers (acc): m_C is the
-// product of acc[C] with the reciprocal of R[C, C], then every later entry s takes -m_C R[C, s] as
-// one FMA, in increasing C. The column index is a template parameter so that every index into acc
-// is a constant.
-template <int C>
-__device__ __forceinline__ void msolve_col(double (&acc)[DS], const double* R, const double* Rd, int d) {
-    if constexpr (C < DS) {
-        if (C < d) {
-            const double mc = acc[C] * Rd[C];
-            acc[C] = mc;
-            msolve_chunk<C, C + 1>(acc, R, mc);
-            msolve_col<C + 1>(acc, R, Rd, d);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < N; ++u) acc[S0 + u] = fma(-mc, cur[u], acc[S0 + u]);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (more) {
+        if constexpr (row_end) {
+            if (NC < d) {
+                const double mn = acc[NC] * rdn;
+                acc[NC] = mn;
+                msolve_chunk<NC, NS0, NN>(acc, R, Rd, d, mn, nxt);
+            }
+        } else {
+            msolve_chunk<NC, NS0, NN>(acc, R, Rd, d, mc, nxt);
         }
     }
 }
@@ -482,7 +490,14 @@ __device__ __forceinline__ void k_dense_sym_body(int k_target, double sym_tol, C
         double acc[DS];
 #pragma unroll
         for (int s2 = 0; s2 < DS; ++s2) acc[s2] = S[rr + min(s2, d - 1) * LDS_];
-        msolve_col<0>(acc, R, Rd, d);
+        {
+            double cur[mchunk_n<1>()];
+#pragma unroll
+            for (int u = 0; u < mchunk_n<1>(); ++u) cur[u] = R[(1 + u) * LDS_];
+            const double m0 = acc[0] * Rd[0];
+            acc[0] = m0;
+            msolve_chunk<0, 1>(acc, R, Rd, d, m0, cur);
+        }
         if (t < d) {
 #pragma unroll
             for (int s2 = 0; s2 < DS; ++s2)
